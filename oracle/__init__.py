@@ -1,0 +1,370 @@
+"""Python access to the FP64 CPU oracle (``pdlp_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  The test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this module; the product
+package never does.  It shares no code with the GPU library: the only
+common dependency is the seeded input generator package ``lpgen``.
+
+The C sources follow the paper step by step (see the header comment of
+``pdlp_oracle.c`` for the passage each function follows).  This module only
+marshals numpy arrays into the C structs.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle_pdlp.so")
+SRC = os.path.join(HERE, "pdlp_oracle.c")
+
+D = C.POINTER(C.c_double)
+I32 = C.POINTER(C.c_int32)
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2 -ffp-contract=off)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        tmp = LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall",
+               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True, cwd=HERE)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class _LP(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n", C.c_int32), ("row_ptr", I32), ("col", I32),
+                ("val", D), ("c", D), ("lc", D), ("uc", D), ("lv", D), ("uv", D)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("eps_feas", C.c_double), ("eps_gap", C.c_double), ("max_iters", C.c_int64),
+                ("check_every", C.c_int32), ("terminate", C.c_int32),
+                ("beta_suff", C.c_double), ("beta_nec", C.c_double), ("beta_art", C.c_double),
+                ("theta", C.c_double), ("eps_zero", C.c_double),
+                ("red_exp", C.c_double), ("grow_exp", C.c_double),
+                ("reduced_cost_mode", C.c_int32), ("polish", C.c_int32),
+                ("polish_first", C.c_int64), ("fixed_step", C.c_int32),
+                ("fixed_eta", C.c_double), ("adaptive_restarts", C.c_int32)]
+
+
+class _State(C.Structure):
+    _fields_ = [("x", D), ("y", D), ("ax", D), ("aty", D), ("x0", D), ("y0", D),
+                ("sx", D), ("sy", D), ("seta", C.c_double), ("omega", C.c_double),
+                ("eta_hat", C.c_double), ("k", C.c_int64), ("t", C.c_int64),
+                ("n_outer", C.c_int64), ("attempts", C.c_int64), ("kkt_passes", C.c_int64),
+                ("mu_ref", C.c_double), ("mu_c_prev", C.c_double),
+                ("restarts_i", C.c_int64), ("restarts_ii", C.c_int64),
+                ("restarts_iii", C.c_int64), ("last_eta", C.c_double),
+                ("last_eta_bar", C.c_double)]
+
+
+class _Scratch(C.Structure):
+    _fields_ = [(f"n{i}", D) for i in range(6)] + [(f"m{i}", D) for i in range(6)]
+
+
+class _Unscale(C.Structure):
+    _fields_ = [("orig", _LP), ("d1", D), ("d2", D), ("obj_offset", C.c_double)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int64), ("attempts", C.c_int64),
+                ("kkt_passes", C.c_int64), ("restarts", C.c_int64), ("restarts_i", C.c_int64),
+                ("restarts_ii", C.c_int64), ("restarts_iii", C.c_int64),
+                ("primal_obj", C.c_double), ("dual_obj", C.c_double), ("rel_gap", C.c_double),
+                ("primal_res_abs", C.c_double), ("primal_res_rel", C.c_double),
+                ("dual_res_abs", C.c_double), ("dual_res_rel", C.c_double),
+                ("omega", C.c_double), ("eta", C.c_double),
+                ("polish_attempts", C.c_int64), ("polish_iters", C.c_int64),
+                ("polished", C.c_int32)]
+
+
+class _KKT(C.Structure):
+    _fields_ = [("primal_obj", C.c_double), ("dual_obj", C.c_double), ("rel_gap", C.c_double),
+                ("primal_res_abs", C.c_double), ("primal_res_rel", C.c_double),
+                ("dual_res_abs", C.c_double), ("dual_res_rel", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB_PATH)
+        L.orc_spmv.argtypes = [C.POINTER(_LP), D, D]
+        L.orc_spmv_t.argtypes = [C.POINTER(_LP), D, D]
+        L.orc_precondition.argtypes = [C.c_int32, C.c_int32, I32, I32, D, C.c_int32, C.c_int32, D, D]
+        L.orc_scale_vectors.argtypes = [C.c_int32, C.c_int32, D, D, D, D, D, D, D, D, D, D, D, D]
+        L.orc_initial_primal_weight.argtypes = [C.POINTER(_LP)]
+        L.orc_initial_primal_weight.restype = C.c_double
+        L.orc_init_state.argtypes = [C.POINTER(_LP), C.POINTER(_State)]
+        L.orc_dual_case.argtypes = [C.c_double] * 4
+        L.orc_dual_case.restype = C.c_double
+        L.orc_adaptive_step.argtypes = [C.POINTER(_LP), C.POINTER(_Params), C.POINTER(_State),
+                                        C.POINTER(_Scratch)]
+        L.orc_norm_gap.argtypes = [C.POINTER(_LP), D, D, D, D, D, D, C.c_double, D, D]
+        L.orc_norm_gap.restype = C.c_double
+        L.orc_norm_gap_bisect.argtypes = [C.POINTER(_LP), D, D, D, D, D, D, C.c_double, D]
+        L.orc_norm_gap_bisect.restype = C.c_double
+        L.orc_path_value.argtypes = [C.POINTER(_LP), D, D, D, D, C.c_double, C.c_double,
+                                     C.c_int32, D, D, D]
+        L.orc_path_value.restype = C.c_double
+        L.orc_primal_weight_update.argtypes = [C.c_double] * 5
+        L.orc_primal_weight_update.restype = C.c_double
+        L.orc_kkt_eval.argtypes = [C.POINTER(_Unscale), D, D, C.c_int32, D, D, D, D, D,
+                                   C.POINTER(_KKT)]
+        L.orc_pdlp.argtypes = [C.POINTER(_LP), C.POINTER(_Unscale), C.POINTER(_Params),
+                               C.POINTER(_State), C.POINTER(_Scratch), D, D, C.POINTER(_Result)]
+        L.orc_pdlp.restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _d(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(D)
+
+
+def _i(a: np.ndarray):
+    assert a.dtype == np.int32 and a.flags.c_contiguous
+    return a.ctypes.data_as(I32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class LPView:
+    """Keeps numpy arrays alive behind an ``orc_lp`` struct."""
+
+    def __init__(self, m, n, row_ptr, col, val, c, lc, uc, lv, uv):
+        self.m, self.n = int(m), int(n)
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        self.col = np.ascontiguousarray(col, dtype=np.int32)
+        self.val = _f64(val)
+        self.c, self.lc, self.uc, self.lv, self.uv = map(_f64, (c, lc, uc, lv, uv))
+        self.s = _LP(self.m, self.n, _i(self.row_ptr), _i(self.col), _d(self.val), _d(self.c),
+                     _d(self.lc), _d(self.uc), _d(self.lv), _d(self.uv))
+
+    @classmethod
+    def of(cls, lp):
+        return cls(lp.m, lp.n, lp.row_ptr, lp.col, lp.val, lp.c, lp.lc, lp.uc, lp.lv, lp.uv)
+
+    def ref(self):
+        return C.byref(self.s)
+
+
+def spmv(view: LPView, x) -> np.ndarray:
+    x = _f64(x)
+    out = np.empty(view.m)
+    lib().orc_spmv(view.ref(), _d(x), _d(out))
+    return out
+
+
+def spmv_t(view: LPView, y) -> np.ndarray:
+    y = _f64(y)
+    out = np.empty(view.n)
+    lib().orc_spmv_t(view.ref(), _d(y), _d(out))
+    return out
+
+
+def precondition(lp, ruiz_iters: int = 10, pc: bool = True):
+    """Returns (scaled values, d1, d2)."""
+    val = np.array(lp.val, dtype=np.float64, copy=True)
+    d1 = np.empty(lp.m)
+    d2 = np.empty(lp.n)
+    rp = np.ascontiguousarray(lp.row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(lp.col, dtype=np.int32)
+    lib().orc_precondition(lp.m, lp.n, _i(rp), _i(cl), _d(val), int(ruiz_iters), int(pc),
+                           _d(d1), _d(d2))
+    return val, d1, d2
+
+
+def scale_vectors(lp, d1, d2):
+    m, n = lp.m, lp.n
+    outs = [np.empty(n), np.empty(m), np.empty(m), np.empty(n), np.empty(n)]
+    ins = [_f64(a) for a in (d1, d2, lp.c, lp.lc, lp.uc, lp.lv, lp.uv)]
+    lib().orc_scale_vectors(m, n, *[_d(a) for a in ins], *[_d(a) for a in outs])
+    return outs  # c, lc, uc, lv, uv
+
+
+def dual_case(yhat, sigma, lc, uc) -> float:
+    return lib().orc_dual_case(float(yhat), float(sigma), float(lc), float(uc))
+
+
+@dataclasses.dataclass
+class Params:
+    eps_feas: float = 1e-8
+    eps_gap: float = 1e-8
+    max_iters: int = 100_000
+    check_every: int = 64
+    terminate: bool = True
+    beta_suff: float = 0.1
+    beta_nec: float = 0.9
+    beta_art: float = 0.5
+    theta: float = 0.5
+    eps_zero: float = 1e-10
+    red_exp: float = 0.3
+    grow_exp: float = 0.6
+    reduced_cost_mode: int | None = None   # None: 0 with polishing, 1 without
+    polish: bool = False
+    polish_first: int = 100
+    fixed_step: bool = False
+    fixed_eta: float = 0.0
+    adaptive_restarts: bool = True
+    ruiz_iters: int = 10
+    pc: bool = True
+
+    def cstruct(self) -> _Params:
+        rc = self.reduced_cost_mode
+        if rc is None:
+            rc = 0 if self.polish else 1
+        return _Params(self.eps_feas, self.eps_gap, int(self.max_iters), int(self.check_every),
+                       int(bool(self.terminate)), self.beta_suff, self.beta_nec, self.beta_art,
+                       self.theta, self.eps_zero, self.red_exp, self.grow_exp, int(rc),
+                       int(bool(self.polish)), int(self.polish_first), int(bool(self.fixed_step)),
+                       float(self.fixed_eta), int(bool(self.adaptive_restarts)))
+
+
+STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 3: "NUMERICAL_ERROR"}
+
+
+class Solver:
+    """Oracle PDLP on one LP: preconditions, initializes, iterates or solves.
+
+    All quantities exposed here are in the scaled space except the results
+    of :meth:`kkt` and the unscaled solution returned by :meth:`solution`.
+    """
+
+    def __init__(self, lp, params: Params | None = None, scale: bool = True):
+        self.lp = lp
+        self.params = params or Params()
+        m, n = lp.m, lp.n
+        self.m, self.n = m, n
+        if scale:
+            val, d1, d2 = precondition(lp, self.params.ruiz_iters, self.params.pc)
+        else:
+            val, d1, d2 = np.array(lp.val, dtype=np.float64), np.ones(m), np.ones(n)
+        self.d1, self.d2 = d1, d2
+        cs, lcs, ucs, lvs, uvs = scale_vectors(lp, d1, d2)
+        self.scaled = LPView(m, n, lp.row_ptr, lp.col, val, cs, lcs, ucs, lvs, uvs)
+        self.orig = LPView.of(lp)
+        self.uns = _Unscale(self.orig.s, _d(self.d1), _d(self.d2), float(lp.obj_offset))
+        z = lambda k: np.zeros(k)
+        self.arr = {k: z(n) for k in ("x", "aty", "x0", "sx")}
+        self.arr.update({k: z(m) for k in ("y", "ax", "y0", "sy")})
+        self.st = _State(*[_d(self.arr[k]) for k in ("x", "y", "ax", "aty", "x0", "y0", "sx", "sy")])
+        self.scr_arr = [z(max(n, 1)) for _ in range(6)] + [z(max(m, 1)) for _ in range(6)]
+        self.scr = _Scratch(*[_d(a) for a in self.scr_arr])
+        lib().orc_init_state(self.scaled.ref(), C.byref(self.st))
+        self.out_x = z(n)
+        self.out_y = z(m)
+        self.result = None
+
+    # -- state access
+    def __getattr__(self, name):
+        arr = self.__dict__.get("arr")
+        if arr is not None and name in arr:
+            return arr[name]
+        raise AttributeError(name)
+
+    @property
+    def omega(self):
+        return self.st.omega
+
+    @property
+    def eta_hat(self):
+        return self.st.eta_hat
+
+    @property
+    def k(self):
+        return self.st.k
+
+    def counters(self) -> dict:
+        s = self.st
+        return dict(k=s.k, t=s.t, n_outer=s.n_outer, attempts=s.attempts, kkt_passes=s.kkt_passes,
+                    restarts_i=s.restarts_i, restarts_ii=s.restarts_ii, restarts_iii=s.restarts_iii,
+                    omega=s.omega, eta_hat=s.eta_hat, seta=s.seta, mu_ref=s.mu_ref,
+                    mu_c_prev=s.mu_c_prev, last_eta=s.last_eta, last_eta_bar=s.last_eta_bar)
+
+    # -- running
+    def _run(self, params: Params) -> dict:
+        res = _Result()
+        cp = params.cstruct()
+        lib().orc_pdlp(self.scaled.ref(), C.byref(self.uns), C.byref(cp), C.byref(self.st),
+                       C.byref(self.scr), _d(self.out_x), _d(self.out_y), C.byref(res))
+        d = {f: getattr(res, f) for f, _ in _Result._fields_}
+        d["status_name"] = STATUS.get(d["status"], str(d["status"]))
+        self.result = d
+        return d
+
+    def iterate(self, k: int) -> dict:
+        """Exactly k more accepted steps, restart checks on, no termination."""
+        p = dataclasses.replace(self.params, terminate=False, max_iters=self.st.k + int(k),
+                                polish=False)
+        return self._run(p)
+
+    def step(self) -> None:
+        """One bare adaptive PDHG step (Algorithm 2) without averaging or checks."""
+        cp = self.params.cstruct()
+        rc = lib().orc_adaptive_step(self.scaled.ref(), C.byref(cp), C.byref(self.st),
+                                     C.byref(self.scr))
+        if rc != 0:
+            raise FloatingPointError("numerical error in PDHG step")
+
+    def solve(self) -> dict:
+        return self._run(self.params)
+
+    def solution(self):
+        """Unscaled (x, y) of the returned point: x = D2 x~, y = D1 y~."""
+        return self.d2 * self.out_x, self.d1 * self.out_y
+
+    def kkt(self, xs, ys, mode: int | None = None) -> dict:
+        if mode is None:
+            mode = 0 if self.params.polish else 1
+        k = _KKT()
+        sc = [np.empty(self.n) for _ in range(3)] + [np.empty(self.m) for _ in range(2)]
+        lib().orc_kkt_eval(C.byref(self.uns), _d(_f64(xs)), _d(_f64(ys)), int(mode),
+                           *[_d(a) for a in sc], C.byref(k))
+        return {f: getattr(k, f) for f, _ in _KKT._fields_}
+
+    def gap(self, x, y, ax, aty, xr, yr, omega, bisect=False) -> float:
+        return norm_gap(self.scaled, x, y, ax, aty, xr, yr, omega, bisect)
+
+
+def norm_gap(view: LPView, x, y, ax, aty, xr, yr, omega, bisect=False) -> float:
+    x, y, ax, aty, xr, yr = map(_f64, (x, y, ax, aty, xr, yr))
+    g = np.empty(max(view.n, 1))
+    if bisect:
+        return lib().orc_norm_gap_bisect(view.ref(), _d(x), _d(y), _d(ax), _d(aty), _d(xr),
+                                         _d(yr), float(omega), _d(g))
+    bp = np.empty(2 * (view.m + view.n) + 1)
+    return lib().orc_norm_gap(view.ref(), _d(x), _d(y), _d(ax), _d(aty), _d(xr), _d(yr),
+                              float(omega), _d(g), _d(bp))
+
+
+def path_value(view: LPView, x, y, ax, aty, omega, s, which):
+    """D(s) (which=0) or f(z^(s)) (which=1) on the proximal path; also returns z^(s)."""
+    x, y, ax, aty = map(_f64, (x, y, ax, aty))
+    g = np.empty(max(view.n, 1))
+    xh = np.empty(view.n)
+    yh = np.empty(view.m)
+    v = lib().orc_path_value(view.ref(), _d(x), _d(y), _d(ax), _d(aty), float(omega), float(s),
+                             int(which), _d(g), _d(xh), _d(yh))
+    return v, xh, yh
+
+
+def primal_weight_update(dx, dy, omega, theta=0.5, eps_zero=1e-10) -> float:
+    return lib().orc_primal_weight_update(float(dx), float(dy), float(omega), float(theta),
+                                          float(eps_zero))
+
+
+def initial_primal_weight(view: LPView) -> float:
+    return lib().orc_initial_primal_weight(view.ref())

@@ -1,0 +1,90 @@
+/*
+ * FP64 CPU oracle for PDLP (restarted, diagonally preconditioned PDHG).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the plain, slow reference that the GPU
+ * library is checked against.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the product path never
+ * does.  It shares no code with the GPU library.
+ *
+ * Precision: IEEE binary64 throughout, compiled with -ffp-contract=off, all
+ * sums accumulated sequentially in index order.
+ *
+ * Problem form (paper, Section 2, eq. "lp"):
+ *     min c^T x  s.t.  lc <= A x <= uc,  lv <= x <= uv
+ * Absent bounds are +-HUGE_VAL.  A is CSR (int32 row_ptr/col, double val)
+ * with strictly increasing columns inside each row.
+ *
+ * Parity status of each function is stated in the function comment in
+ * pdlp_oracle.c.
+ */
+#ifndef PDLP_ORACLE_H
+#define PDLP_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+    int32_t m, n;
+    const int32_t *row_ptr, *col;
+    const double *val;
+    const double *c, *lc, *uc, *lv, *uv;
+} orc_lp;
+
+typedef struct {
+    double eps_feas, eps_gap;      /* termination tolerances */
+    int64_t max_iters;             /* limit on accepted steps */
+    int32_t check_every;           /* cadence of restart/termination checks (64) */
+    int32_t terminate;             /* 0: run exactly max_iters steps, no termination test */
+    double beta_suff, beta_nec, beta_art;   /* 0.1, 0.9, 0.5 */
+    double theta, eps_zero;        /* 0.5, 1e-10 */
+    double red_exp, grow_exp;      /* 0.3, 0.6 */
+    int32_t reduced_cost_mode;     /* 0: projection onto R, 1: Appendix A choice */
+    int32_t polish;                /* feasibility polishing on/off */
+    int64_t polish_first;          /* 100 */
+    int32_t fixed_step;            /* test mode: constant eta, no adaptive rule */
+    double fixed_eta;
+    int32_t adaptive_restarts;     /* 0: only condition (iii) */
+} orc_params;
+
+/* Iterate state; every array is owned by the caller. */
+typedef struct {
+    double *x, *y, *ax, *aty;      /* current z^{n,t} and cached A x, A^T y (scaled) */
+    double *x0, *y0;               /* restart point z^{n,0} */
+    double *sx, *sy;               /* sums of eta_i x^i and eta_i y^i since restart */
+    double seta;                   /* sum of eta_i */
+    double omega, eta_hat;
+    int64_t k, t, n_outer, attempts, kkt_passes;
+    double mu_ref, mu_c_prev;
+    int64_t restarts_i, restarts_ii, restarts_iii;
+    double last_eta;               /* eta of the last accepted step */
+    double last_eta_bar;           /* eta_bar of the last attempt */
+} orc_state;
+
+/* Scratch arrays (caller owned): 6 of length n, 6 of length m. */
+typedef struct {
+    double *n0, *n1, *n2, *n3, *n4, *n5;
+    double *m0, *m1, *m2, *m3, *m4, *m5;
+} orc_scratch;
+
+/* Original-unit data for termination criteria. */
+typedef struct {
+    orc_lp orig;                   /* unscaled problem */
+    const double *d1, *d2;         /* diagonal scalings, A~ = D1 A D2 */
+    double obj_offset;
+} orc_unscale;
+
+typedef struct {
+    int32_t status;                /* 0 optimal, 1 iteration limit, 3 numerical error */
+    int64_t iterations, attempts, kkt_passes;
+    int64_t restarts, restarts_i, restarts_ii, restarts_iii;
+    double primal_obj, dual_obj, rel_gap;
+    double primal_res_abs, primal_res_rel, dual_res_abs, dual_res_rel;
+    double omega, eta;
+    int64_t polish_attempts, polish_iters;
+    int32_t polished;
+} orc_result;
+
+typedef struct {
+    double primal_obj, dual_obj, rel_gap;
+    double primal_res_abs, primal_res_rel, dual_res_abs, dual_res_rel;
+} orc_kkt;
+
+#endif
