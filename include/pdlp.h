@@ -1,0 +1,193 @@
+/*
+ * pdlp.h -- C ABI of the MI355X (gfx950) PDLP library.
+ *
+ * PDLP is the restarted, diagonally preconditioned primal-dual hybrid
+ * gradient method of Applegate et al., "PDLP: A Practical First-Order Method
+ * for Large-Scale Linear Programming" (arXiv 2501.07018), for the LP
+ *
+ *     min c^T x  s.t.  lc <= A x <= uc,  lv <= x <= uv          (Section 2, eq. "lp")
+ *
+ * with dual  max -p(-y; lc, uc) - p(-r; lv, uv)  s.t. c - A^T y = r, y in Y, r in R,
+ * where p(y; l, u) = u^T y+ - l^T y-.
+ *
+ * Every floating-point quantity is IEEE binary64, on the host and on the GPU.
+ *
+ * Conventions shared by all entry points
+ *   - Absent bounds are +-HUGE_VAL (+-infinity).  lc = uc encodes an equality.
+ *   - A is CSR: row_ptr[m+1] (int32, row_ptr[0] = 0, nondecreasing),
+ *     col[nnz] (int32, strictly increasing inside each row, in [0, n)),
+ *     val[nnz] (finite doubles).  Empty rows and columns, and m = 0, are allowed.
+ *   - Pointers named *_host are host memory; the library copies what it
+ *     needs before returning and never keeps a caller pointer.
+ *   - Output arrays are caller-owned and may be NULL when not wanted.
+ *   - Return codes: PDLP_OK (0) or a negative PDLP_ERR_*; the message of the
+ *     last error on the calling thread is returned by pdlp_last_error().
+ *   - One problem (and its states) is used from one host thread at a time;
+ *     all GPU work is ordered on the stream given at creation (NULL = the
+ *     default stream), and every entry point returns after that work ends.
+ */
+#ifndef PDLP_H
+#define PDLP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDLP_OK 0
+#define PDLP_ERR_INVALID_ARGUMENT (-1)
+#define PDLP_ERR_HIP (-2)
+#define PDLP_ERR_OUT_OF_MEMORY (-3)
+#define PDLP_ERR_STATE (-4)
+
+/* Solve status (Section 6 outcomes: solved, time limit, numerical error). */
+#define PDLP_STATUS_OPTIMAL 0
+#define PDLP_STATUS_ITERATION_LIMIT 1
+#define PDLP_STATUS_TIME_LIMIT 2
+#define PDLP_STATUS_NUMERICAL_ERROR 3
+
+typedef struct pdlp_problem pdlp_problem; /* opaque: device copy of A, A^T, scaling */
+typedef struct pdlp_state pdlp_state;     /* opaque: iterate state on the device */
+
+/*
+ * Parameters.  Defaults (pdlp_params_default) are the paper's constants:
+ * restart/termination checks every 64 accepted steps (Section 3, "Periodic
+ * checks"), beta_sufficient 0.1, beta_necessary 0.9, beta_artificial 0.5
+ * (Section 3, "Adaptive restarts"), theta 0.5 and eps_zero 1e-10
+ * (Algorithm 3), step exponents 0.3 and 0.6 (Algorithm 2), 10 Ruiz rounds
+ * then Pock-Chambolle with alpha = 1 (Section 3, "Diagonal Preconditioning"),
+ * feasibility polishing at k = 100, 200, 400, ... with k/8 caps (Algorithm 4).
+ */
+typedef struct pdlp_params {
+    double eps_feas;          /* relative primal/dual residual tolerance (1e-8) */
+    double eps_gap;           /* relative duality gap tolerance (1e-8) */
+    int64_t max_iters;        /* limit on accepted PDHG steps */
+    double time_limit;        /* seconds; <= 0 means the limit is already reached */
+    int32_t check_every;      /* 64 */
+    int32_t ruiz_iters;       /* 10 */
+    int32_t pock_chambolle;   /* 1: one Pock-Chambolle round (alpha = 1) after Ruiz */
+    int32_t polish;           /* feasibility polishing (Algorithm 4) on/off */
+    int64_t polish_first;     /* 100 */
+    int32_t reduced_cost_mode;/* -1: App. A choice without polishing, projection with it;
+                                 0: projection onto R; 1: Appendix A choice */
+    int32_t adaptive_restarts;/* 1: criteria (i)-(iii); 0: only (iii) */
+    double beta_suff, beta_nec, beta_art;
+    double theta, eps_zero;
+    double red_exp, grow_exp;
+    int32_t verbose;          /* 1: one line per check on stderr */
+    int32_t reserved;
+} pdlp_params;
+
+/* Result of a solve.  x, y, r are caller buffers of length n, m, n (or NULL);
+ * they receive the unscaled solution x = D2 x~, y = D1 y~ and the reduced
+ * costs used in the termination test.  Residuals follow Section 6, eq.
+ * "rescaled-termination-criteria" (relative) and its l_inf absolute form. */
+typedef struct pdlp_result {
+    double *x, *y, *r;        /* in: caller buffers or NULL */
+    int32_t status;
+    int32_t polished;         /* 1 when the returned point came from polishing */
+    int64_t iterations;       /* accepted PDHG steps of the main run */
+    int64_t attempts;         /* step attempts including rejected ones */
+    int64_t kkt_passes;       /* products A x + A^T y computed (all phases) */
+    int64_t restarts, restarts_i, restarts_ii, restarts_iii;
+    int64_t polish_attempts, polish_iters;
+    double primal_obj, dual_obj, rel_gap;
+    double primal_res_abs, primal_res_rel, dual_res_abs, dual_res_rel;
+    double omega, eta;        /* final primal weight and step size */
+    double seconds;           /* wall time inside pdlp_solve */
+    double seconds_setup;     /* preconditioning + initialization part of it */
+} pdlp_result;
+
+/* Counters after pdlp_iterate_k. */
+typedef struct pdlp_iter_info {
+    int64_t k, t, n_outer, attempts, kkt_passes;
+    int64_t restarts_i, restarts_ii, restarts_iii;
+    double omega, eta_hat, last_eta, last_eta_bar, seta, mu_ref, mu_c_prev;
+} pdlp_iter_info;
+
+/* Full iterate state in the scaled space, for export and bitwise resume.
+ * Arrays are caller buffers: x, x0, sx, aty of length n; y, y0, sy, ax of
+ * length m (any may be NULL on get; none may be NULL on set). */
+typedef struct pdlp_state_blob {
+    double *x, *y, *ax, *aty, *x0, *y0, *sx, *sy;
+    double seta, omega, eta_hat, mu_ref, mu_c_prev, last_eta;
+    int64_t k, t, n_outer, attempts, kkt_passes;
+    int64_t restarts_i, restarts_ii, restarts_iii;
+} pdlp_state_blob;
+
+/*
+ * Create a problem from host CSR arrays (see conventions).  Validates the
+ * input, uploads it, builds A^T on the GPU and applies the diagonal
+ * preconditioning of params (NULL = defaults): ruiz_iters Ruiz rounds then
+ * an optional Pock-Chambolle round (Section 3, "Diagonal Preconditioning").
+ * hip_stream: a hipStream_t or NULL.  Errors: INVALID_ARGUMENT for bad sizes,
+ * unsorted/duplicate/out-of-range columns, non-finite values or c, NaN
+ * bounds, lc > uc, lv > uv, a lower bound of +inf or an upper bound of -inf;
+ * OUT_OF_MEMORY; HIP_ERROR.
+ */
+int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr_host,
+                        const int32_t *col_host, const double *val_host, const double *c_host,
+                        const double *lc_host, const double *uc_host, const double *lv_host,
+                        const double *uv_host, double obj_offset, const pdlp_params *params,
+                        void *hip_stream, pdlp_problem **out);
+
+void pdlp_problem_destroy(pdlp_problem *p);
+
+/* Sizes of a created problem. */
+int pdlp_problem_dims(const pdlp_problem *p, int32_t *m, int32_t *n, int64_t *nnz);
+
+/* Copy out the preconditioned problem: D1 (m), D2 (n), the scaled values of
+ * A in the caller's CSR order (nnz), and the scaled c~, lc~, uc~, lv~, uv~
+ * (Section 3: c~ = D2 c, (lc~, uc~) = D1 (lc, uc), (lv~, uv~) = D2^-1 (lv, uv)). */
+int pdlp_problem_get_scaled(const pdlp_problem *p, double *d1, double *d2, double *val,
+                            double *c, double *lc, double *uc, double *lv, double *uv);
+
+/* One GPU sparse product on host vectors: transpose = 0 gives out = A x
+ * (x: n, out: m), transpose = 1 gives out = A^T x (x: m, out: n); scaled = 1
+ * uses the preconditioned matrix A~, 0 the original one (original = D1^-1 A~ D2^-1,
+ * applied through the diagonals).  `repeat` >= 1 runs the product that many
+ * times (for timing); *ms receives the average kernel time if not NULL. */
+int pdlp_spmv(const pdlp_problem *p, int32_t transpose, int32_t scaled, const double *x_host,
+              double *out_host, int32_t repeat, double *ms);
+
+void pdlp_params_default(pdlp_params *params);
+
+/*
+ * Solve (Algorithm 1 with Algorithm 2 steps, adaptive restarts, Algorithm 3
+ * primal weights, Algorithm 4 polishing when params->polish; termination by
+ * eq. "rescaled-termination-criteria" and eq. "relative-gap").  params NULL
+ * = defaults.  x0_host/y0_host (unscaled, length n and m, both or neither)
+ * give a warm start; NULL starts from (proj_X(0), 0).  result must not be
+ * NULL.  Returns PDLP_OK when a status was reached (the status is in result).
+ */
+int pdlp_solve(pdlp_problem *p, const pdlp_params *params, const double *x0_host,
+               const double *y0_host, pdlp_result *result);
+
+/* Create a state: preconditioned problem + initial point of Algorithm 1
+ * (eta_hat = 1/max|A~_ij|, omega from InitializePrimalWeight, z = (proj_X(0), 0)). */
+int pdlp_state_create(pdlp_problem *p, const pdlp_params *params, pdlp_state **out);
+void pdlp_state_destroy(pdlp_state *s);
+
+/* Run exactly k more accepted steps with the restart checks of Algorithm 1
+ * but no termination test or polishing; info may be NULL.  k >= 0. */
+int pdlp_iterate_k(pdlp_state *s, int64_t k, pdlp_iter_info *info);
+
+/* Copy the state out (get) or in (set); see pdlp_state_blob. */
+int pdlp_state_get(const pdlp_state *s, pdlp_state_blob *blob);
+int pdlp_state_set(pdlp_state *s, const pdlp_state_blob *blob);
+
+/* Normalized duality gap mu(z, z_ref) = rho_r(z), r = ||z - z_ref||_omega
+ * (Section 3, "Adaptive restarts") of scaled host points; ax/aty are A~x and
+ * A~^T y.  Vectors: x, aty, xr of length n; y, ax, yr of length m. */
+int pdlp_norm_gap(const pdlp_problem *p, const double *x, const double *y, const double *ax,
+                  const double *aty, const double *xr, const double *yr, double omega,
+                  double *mu);
+
+/* Message for the last error on this thread ("" if none). */
+const char *pdlp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,309 @@
+"""Python binding of the gfx950 PDLP library (``include/pdlp.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library
+``libpdlp.so`` built in this directory.  There is no CPU fallback; loading
+fails with an error when the library has not been built.
+
+Functions carry the C names without the ``pdlp_`` prefix duplication kept,
+e.g. ``pdlp_problem_create``; ``Problem`` is a small owner object around a
+problem handle.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdlp.so")
+
+PDLP_OK = 0
+PDLP_ERR_INVALID_ARGUMENT = -1
+PDLP_ERR_HIP = -2
+PDLP_ERR_OUT_OF_MEMORY = -3
+PDLP_ERR_STATE = -4
+STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
+
+D = C.POINTER(C.c_double)
+I32 = C.POINTER(C.c_int32)
+
+
+class PdlpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pdlp error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("eps_feas", C.c_double), ("eps_gap", C.c_double), ("max_iters", C.c_int64),
+                ("time_limit", C.c_double), ("check_every", C.c_int32),
+                ("ruiz_iters", C.c_int32), ("pock_chambolle", C.c_int32), ("polish", C.c_int32),
+                ("polish_first", C.c_int64), ("reduced_cost_mode", C.c_int32),
+                ("adaptive_restarts", C.c_int32), ("beta_suff", C.c_double),
+                ("beta_nec", C.c_double), ("beta_art", C.c_double), ("theta", C.c_double),
+                ("eps_zero", C.c_double), ("red_exp", C.c_double), ("grow_exp", C.c_double),
+                ("verbose", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Result(C.Structure):
+    _fields_ = [("x", D), ("y", D), ("r", D), ("status", C.c_int32), ("polished", C.c_int32),
+                ("iterations", C.c_int64), ("attempts", C.c_int64), ("kkt_passes", C.c_int64),
+                ("restarts", C.c_int64), ("restarts_i", C.c_int64), ("restarts_ii", C.c_int64),
+                ("restarts_iii", C.c_int64), ("polish_attempts", C.c_int64),
+                ("polish_iters", C.c_int64), ("primal_obj", C.c_double),
+                ("dual_obj", C.c_double), ("rel_gap", C.c_double),
+                ("primal_res_abs", C.c_double), ("primal_res_rel", C.c_double),
+                ("dual_res_abs", C.c_double), ("dual_res_rel", C.c_double),
+                ("omega", C.c_double), ("eta", C.c_double), ("seconds", C.c_double),
+                ("seconds_setup", C.c_double)]
+
+
+class IterInfo(C.Structure):
+    _fields_ = [("k", C.c_int64), ("t", C.c_int64), ("n_outer", C.c_int64),
+                ("attempts", C.c_int64), ("kkt_passes", C.c_int64),
+                ("restarts_i", C.c_int64), ("restarts_ii", C.c_int64),
+                ("restarts_iii", C.c_int64), ("omega", C.c_double), ("eta_hat", C.c_double),
+                ("last_eta", C.c_double), ("last_eta_bar", C.c_double), ("seta", C.c_double),
+                ("mu_ref", C.c_double), ("mu_c_prev", C.c_double)]
+
+
+class StateBlob(C.Structure):
+    _fields_ = [(k, D) for k in ("x", "y", "ax", "aty", "x0", "y0", "sx", "sy")] + \
+               [(k, C.c_double) for k in ("seta", "omega", "eta_hat", "mu_ref", "mu_c_prev",
+                                          "last_eta")] + \
+               [(k, C.c_int64) for k in ("k", "t", "n_outer", "attempts", "kkt_passes",
+                                         "restarts_i", "restarts_ii", "restarts_iii")]
+
+
+_lib = None
+
+EXPORTS = ("pdlp_problem_create", "pdlp_problem_destroy", "pdlp_problem_dims",
+           "pdlp_problem_get_scaled", "pdlp_spmv", "pdlp_params_default", "pdlp_solve",
+           "pdlp_state_create", "pdlp_state_destroy", "pdlp_iterate_k", "pdlp_state_get",
+           "pdlp_state_set", "pdlp_norm_gap", "pdlp_last_error")
+
+
+def lib() -> C.CDLL:
+    """Load libpdlp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python paper_2501_07018_amd/build.py` (hipcc, gfx950)")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.pdlp_problem_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, I32, I32, D, D, D, D, D, D,
+                                      C.c_double, C.POINTER(Params), vp, C.POINTER(vp)]
+    L.pdlp_problem_destroy.argtypes = [vp]
+    L.pdlp_problem_destroy.restype = None
+    L.pdlp_problem_dims.argtypes = [vp, I32, I32, C.POINTER(C.c_int64)]
+    L.pdlp_problem_get_scaled.argtypes = [vp, D, D, D, D, D, D, D, D]
+    L.pdlp_spmv.argtypes = [vp, C.c_int32, C.c_int32, D, D, C.c_int32, D]
+    L.pdlp_params_default.argtypes = [C.POINTER(Params)]
+    L.pdlp_params_default.restype = None
+    L.pdlp_solve.argtypes = [vp, C.POINTER(Params), D, D, C.POINTER(Result)]
+    L.pdlp_state_create.argtypes = [vp, C.POINTER(Params), C.POINTER(vp)]
+    L.pdlp_state_destroy.argtypes = [vp]
+    L.pdlp_state_destroy.restype = None
+    L.pdlp_iterate_k.argtypes = [vp, C.c_int64, C.POINTER(IterInfo)]
+    L.pdlp_state_get.argtypes = [vp, C.POINTER(StateBlob)]
+    L.pdlp_state_set.argtypes = [vp, C.POINTER(StateBlob)]
+    L.pdlp_norm_gap.argtypes = [vp, D, D, D, D, D, D, C.c_double, D]
+    L.pdlp_last_error.argtypes = []
+    L.pdlp_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != PDLP_OK:
+        raise PdlpError(rc, lib().pdlp_last_error().decode())
+
+
+def _d(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def pdlp_params_default(**over) -> Params:
+    p = Params()
+    lib().pdlp_params_default(C.byref(p))
+    for k, v in over.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def pdlp_problem_create(m, n, row_ptr, col, val, c, lc, uc, lv, uv, obj_offset=0.0,
+                        params: Params | None = None, stream=None):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    arrs = [_f64(a) for a in (val, c, lc, uc, lv, uv)]
+    h = C.c_void_p()
+    rc = lib().pdlp_problem_create(int(m), int(n), int(rp[-1]) if rp.size else 0,
+                                   rp.ctypes.data_as(I32), cl.ctypes.data_as(I32),
+                                   *[_d(a) for a in arrs], float(obj_offset),
+                                   C.byref(params) if params is not None else None,
+                                   stream, C.byref(h))
+    _check(rc)
+    return h
+
+
+def pdlp_problem_destroy(h):
+    lib().pdlp_problem_destroy(h)
+
+
+def pdlp_problem_dims(h):
+    m, n, nnz = C.c_int32(), C.c_int32(), C.c_int64()
+    _check(lib().pdlp_problem_dims(h, C.byref(m), C.byref(n), C.byref(nnz)))
+    return m.value, n.value, nnz.value
+
+
+def pdlp_problem_get_scaled(h) -> dict:
+    m, n, nnz = pdlp_problem_dims(h)
+    out = {"d1": np.empty(m), "d2": np.empty(n), "val": np.empty(nnz), "c": np.empty(n),
+           "lc": np.empty(m), "uc": np.empty(m), "lv": np.empty(n), "uv": np.empty(n)}
+    _check(lib().pdlp_problem_get_scaled(h, *[_d(out[k]) for k in
+                                              ("d1", "d2", "val", "c", "lc", "uc", "lv", "uv")]))
+    return out
+
+
+def pdlp_spmv(h, x, transpose=False, scaled=True, repeat=1):
+    m, n, _ = pdlp_problem_dims(h)
+    x = _f64(x)
+    out = np.empty(n if transpose else m)
+    ms = C.c_double()
+    _check(lib().pdlp_spmv(h, int(bool(transpose)), int(bool(scaled)), _d(x), _d(out),
+                           int(repeat), C.byref(ms)))
+    return out, ms.value
+
+
+def pdlp_solve(h, params: Params | None = None, x0=None, y0=None) -> dict:
+    m, n, _ = pdlp_problem_dims(h)
+    x = np.empty(n)
+    y = np.empty(m)
+    r = np.empty(n)
+    res = Result()
+    res.x, res.y, res.r = _d(x), _d(y), _d(r)
+    x0 = None if x0 is None else _f64(x0)
+    y0 = None if y0 is None else _f64(y0)
+    _check(lib().pdlp_solve(h, C.byref(params) if params is not None else None, _d(x0), _d(y0),
+                            C.byref(res)))
+    d = {f: getattr(res, f) for f, _ in Result._fields_ if f not in ("x", "y", "r")}
+    d["status_name"] = STATUS.get(d["status"], str(d["status"]))
+    d["x"], d["y"], d["r"] = x, y, r
+    return d
+
+
+def pdlp_state_create(h, params: Params | None = None):
+    s = C.c_void_p()
+    _check(lib().pdlp_state_create(h, C.byref(params) if params is not None else None, C.byref(s)))
+    return s
+
+
+def pdlp_state_destroy(s):
+    lib().pdlp_state_destroy(s)
+
+
+def pdlp_iterate_k(s, k) -> dict:
+    info = IterInfo()
+    _check(lib().pdlp_iterate_k(s, int(k), C.byref(info)))
+    return {f: getattr(info, f) for f, _ in IterInfo._fields_}
+
+
+def pdlp_state_get(s, m, n) -> dict:
+    arrs = {k: np.empty(n) for k in ("x", "aty", "x0", "sx")}
+    arrs.update({k: np.empty(m) for k in ("y", "ax", "y0", "sy")})
+    b = StateBlob(*[_d(arrs[k]) for k in ("x", "y", "ax", "aty", "x0", "y0", "sx", "sy")])
+    _check(lib().pdlp_state_get(s, C.byref(b)))
+    for f, _ in StateBlob._fields_[8:]:
+        arrs[f] = getattr(b, f)
+    return arrs
+
+
+def pdlp_state_set(s, blob: dict):
+    arrs = {k: _f64(blob[k]) for k in ("x", "y", "ax", "aty", "x0", "y0", "sx", "sy")}
+    b = StateBlob(*[_d(arrs[k]) for k in ("x", "y", "ax", "aty", "x0", "y0", "sx", "sy")])
+    for f, _ in StateBlob._fields_[8:]:
+        setattr(b, f, blob[f])
+    _check(lib().pdlp_state_set(s, C.byref(b)))
+
+
+def pdlp_norm_gap(h, x, y, ax, aty, xr, yr, omega) -> float:
+    mu = C.c_double()
+    x, y, ax, aty, xr, yr = map(_f64, (x, y, ax, aty, xr, yr))
+    _check(lib().pdlp_norm_gap(h, _d(x), _d(y), _d(ax), _d(aty), _d(xr), _d(yr), float(omega),
+                               C.byref(mu)))
+    return mu.value
+
+
+def pdlp_last_error() -> str:
+    return lib().pdlp_last_error().decode()
+
+
+class Problem:
+    """Owner of a problem handle created from an object with CSR fields
+    (m, n, row_ptr, col, val, c, lc, uc, lv, uv, obj_offset)."""
+
+    def __init__(self, lp, params: Params | None = None, stream=None):
+        self.m, self.n = int(lp.m), int(lp.n)
+        self.h = pdlp_problem_create(lp.m, lp.n, lp.row_ptr, lp.col, lp.val, lp.c, lp.lc, lp.uc,
+                                     lp.lv, lp.uv, getattr(lp, "obj_offset", 0.0), params, stream)
+
+    def close(self):
+        if self.h:
+            pdlp_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, params: Params | None = None, x0=None, y0=None) -> dict:
+        return pdlp_solve(self.h, params, x0, y0)
+
+    def scaled(self) -> dict:
+        return pdlp_problem_get_scaled(self.h)
+
+    def spmv(self, x, transpose=False, scaled=True, repeat=1):
+        return pdlp_spmv(self.h, x, transpose, scaled, repeat)
+
+    def state(self, params: Params | None = None) -> "State":
+        return State(self, params)
+
+
+class State:
+    def __init__(self, prob: Problem, params: Params | None = None):
+        self.prob = prob
+        self.s = pdlp_state_create(prob.h, params)
+
+    def iterate(self, k) -> dict:
+        return pdlp_iterate_k(self.s, k)
+
+    def get(self) -> dict:
+        return pdlp_state_get(self.s, self.prob.m, self.prob.n)
+
+    def set(self, blob: dict):
+        pdlp_state_set(self.s, blob)
+
+    def close(self):
+        if self.s:
+            pdlp_state_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

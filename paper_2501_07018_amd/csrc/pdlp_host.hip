@@ -1,0 +1,1150 @@
+// Host driver and C ABI of the gfx950 PDLP library.
+//
+// The host runs the control logic of Algorithm 1 at iteration-block
+// boundaries; the device runs every per-element step.  Block boundaries
+// are the accepted-step counts where something other than a plain PDHG step
+// must happen: multiples of the check cadence (restart criteria (i), (ii)
+// and termination, Section 3 "Periodic checks"), the first count where
+// condition (iii) t >= beta_art k holds (it depends only on t and k, so it is
+// known in advance), feasibility-polishing points (Algorithm 4) and the
+// iteration cap.  Inside a block the step attempts (Algorithm 2) run on the
+// device with their accept/reject decision in the device control block.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "pdlp.h"
+#include "pdlp_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct LibError : std::runtime_error {
+    int code;
+    LibError(int c, const std::string &msg) : std::runtime_error(msg), code(c) {}
+};
+
+void hip_fail(hipError_t e, const char *what, int line) {
+    const int code = (e == hipErrorOutOfMemory) ? PDLP_ERR_OUT_OF_MEMORY : PDLP_ERR_HIP;
+    throw LibError(code, std::string(what) + " failed (line " + std::to_string(line) +
+                             "): " + hipGetErrorString(e));
+}
+
+#define HIPCHECK(expr)                                       \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) hip_fail(e_, #expr, __LINE__); \
+    } while (0)
+
+void invalid(const std::string &msg) { throw LibError(PDLP_ERR_INVALID_ARGUMENT, msg); }
+
+// Device allocations owned by an object, freed together.
+struct Arena {
+    std::vector<void *> ptrs;
+    std::vector<void *> pinned;
+    template <class T>
+    T *dev(size_t count) {
+        void *p = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw LibError(e == hipErrorOutOfMemory ? PDLP_ERR_OUT_OF_MEMORY : PDLP_ERR_HIP,
+                           "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                               hipGetErrorString(e));
+        }
+        ptrs.push_back(p);
+        return static_cast<T *>(p);
+    }
+    template <class T>
+    T *host(size_t count) {
+        void *p = nullptr;
+        HIPCHECK(hipHostMalloc(&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
+        pinned.push_back(p);
+        return static_cast<T *>(p);
+    }
+    void release(void *p) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) {
+            (void)hipFree(p);
+            ptrs.erase(it);
+        }
+    }
+    ~Arena() {
+        for (void *p : ptrs) (void)hipFree(p);
+        for (void *p : pinned) (void)hipHostFree(p);
+    }
+};
+
+using pdlp::Ctrl;
+using pdlp::DCsr;
+using pdlp::GapState;
+using pdlp::Iter;
+using pdlp::KktOut;
+using pdlp::kThreads;
+using pdlp::Vecs;
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+int red_grid(int64_t len) {
+    int64_t g = (len + kThreads - 1) / kThreads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
+}
+
+// Row blocks for the CSR stream kernels: consecutive rows whose nonzeros
+// fit the LDS stage (at most kMaxBlockRows rows), or one long row alone.
+std::vector<int32_t> make_blocks(const int32_t *rp, int32_t rows) {
+    std::vector<int32_t> blk;
+    blk.push_back(0);
+    int32_t r = 0;
+    while (r < rows) {
+        const int32_t len = rp[r + 1] - rp[r];
+        if (len > pdlp::kStage) {
+            ++r;
+            blk.push_back(r);
+            continue;
+        }
+        const int32_t start = r;
+        int64_t nz = 0;
+        while (r < rows && r - start < pdlp::kMaxBlockRows) {
+            const int32_t l = rp[r + 1] - rp[r];
+            if (l > pdlp::kStage || nz + l > pdlp::kStage) break;
+            nz += l;
+            ++r;
+        }
+        blk.push_back(r);
+    }
+    return blk;
+}
+
+}  // namespace
+
+// ===================================================================== problem
+
+struct pdlp_problem {
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    hipStream_t stream = nullptr;
+    Arena arena;
+    DCsr A, AT;
+    double *d1 = nullptr, *d2 = nullptr;                                // scaling
+    double *c = nullptr, *lc = nullptr, *uc = nullptr, *lv = nullptr, *uv = nullptr;  // original
+    double *cs = nullptr, *lcs = nullptr, *ucs = nullptr, *lvs = nullptr, *uvs = nullptr;
+    double *zero_n = nullptr;                                            // c = 0 (primal polish)
+    double *lc0 = nullptr, *uc0 = nullptr, *lv0 = nullptr, *uv0 = nullptr;  // finite bounds -> 0
+    double obj_offset = 0.0;
+    double *red_part = nullptr;  // partials of generic reductions
+    int red_cap = 0;
+    double *res_d = nullptr, *res_h = nullptr;  // small reduction results
+    pdlp_params scale_params;
+
+    Vecs scaled() const { return Vecs{cs, lcs, ucs, lvs, uvs}; }
+};
+
+namespace {
+
+void validate(int32_t m, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
+              const double *val, const double *c, const double *lc, const double *uc,
+              const double *lv, const double *uv) {
+    if (m < 0 || n < 1) invalid("need m >= 0 and n >= 1");
+    if (nnz < 0 || nnz > (int64_t)std::numeric_limits<int32_t>::max())
+        invalid("nnz must lie in [0, 2^31)");
+    if (!rp || (nnz > 0 && (!col || !val)) || !c || (m > 0 && (!lc || !uc)) || !lv || !uv)
+        invalid("NULL input array");
+    if (rp[0] != 0) invalid("row_ptr[0] must be 0");
+    for (int32_t i = 0; i < m; ++i)
+        if (rp[i + 1] < rp[i]) invalid("row_ptr must be nondecreasing (row " + std::to_string(i) + ")");
+    if ((int64_t)rp[m] != nnz) invalid("row_ptr[m] must equal nnz");
+    for (int32_t i = 0; i < m; ++i) {
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+            if (col[e] < 0 || col[e] >= n)
+                invalid("column index out of range in row " + std::to_string(i));
+            if (e > rp[i] && col[e] <= col[e - 1])
+                invalid("columns must be strictly increasing within row " + std::to_string(i));
+            if (!std::isfinite(val[e])) invalid("non-finite matrix value in row " + std::to_string(i));
+        }
+    }
+    for (int32_t j = 0; j < n; ++j) {
+        if (!std::isfinite(c[j])) invalid("non-finite objective coefficient " + std::to_string(j));
+        if (std::isnan(lv[j]) || std::isnan(uv[j])) invalid("NaN variable bound");
+        if (lv[j] == INFINITY || uv[j] == -INFINITY) invalid("variable bound of wrong infinity");
+        if (lv[j] > uv[j]) invalid("lv > uv for variable " + std::to_string(j));
+    }
+    for (int32_t i = 0; i < m; ++i) {
+        if (std::isnan(lc[i]) || std::isnan(uc[i])) invalid("NaN constraint bound");
+        if (lc[i] == INFINITY || uc[i] == -INFINITY) invalid("constraint bound of wrong infinity");
+        if (lc[i] > uc[i]) invalid("lc > uc for row " + std::to_string(i));
+    }
+}
+
+void upload_blocks(pdlp_problem *P, DCsr &M, const int32_t *rp_host) {
+    std::vector<int32_t> blk = make_blocks(rp_host, M.rows);
+    M.nblk = (int32_t)blk.size() - 1;
+    M.blk = P->arena.dev<int32_t>(blk.size());
+    HIPCHECK(hipMemcpyAsync(M.blk, blk.data(), blk.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, P->stream));
+    M.grid = std::min<int32_t>(M.nblk, 2048);
+    HIPCHECK(hipStreamSynchronize(P->stream));
+}
+
+void build_transpose(pdlp_problem *P) {
+    hipStream_t s = P->stream;
+    const int64_t nnz = P->nnz;
+    DCsr &T = P->AT;
+    T.rows = P->n;
+    T.cols = P->m;
+    T.nnz = nnz;
+    T.row_ptr = P->arena.dev<int32_t>((size_t)P->n + 1);
+    T.col = P->arena.dev<int32_t>(nnz);
+    T.val = P->arena.dev<double>(nnz);
+    if (nnz == 0) {
+        HIPCHECK(hipMemsetAsync(T.row_ptr, 0, sizeof(int32_t) * ((size_t)P->n + 1), s));
+        return;
+    }
+    Arena tmp;
+    int32_t *rowid = tmp.dev<int32_t>(nnz);
+    uint32_t *keys_out = tmp.dev<uint32_t>(nnz);
+    const uint32_t *keys_in = reinterpret_cast<const uint32_t *>(P->A.col);
+    int32_t *vals_in = tmp.dev<int32_t>(nnz);
+    int32_t *vals_out = tmp.dev<int32_t>(nnz);
+    HIPCHECK(pdlp::launch_row_ids(s, P->m, P->A.row_ptr, rowid));
+    HIPCHECK(pdlp::launch_iota(s, nnz, vals_in));
+    int end_bit = 1;
+    while (end_bit < 31 && (1LL << end_bit) <= (long long)P->n) ++end_bit;
+    size_t temp_bytes = 0;
+    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, keys_in, keys_out, vals_in,
+                                                vals_out, (int)nnz, 0, end_bit, s));
+    void *temp = tmp.dev<char>(temp_bytes);
+    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in,
+                                                vals_out, (int)nnz, 0, end_bit, s));
+    HIPCHECK(pdlp::launch_transpose_finish(s, nnz, P->n, reinterpret_cast<const int32_t *>(keys_out),
+                                           vals_out, rowid, P->A.val,
+                                           T.row_ptr, T.col, T.val));
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+double reduce_result(pdlp_problem *P, int idx = 0) {
+    HIPCHECK(hipMemcpyAsync(P->res_h, P->res_d, 8 * sizeof(double), hipMemcpyDeviceToHost,
+                            P->stream));
+    HIPCHECK(hipStreamSynchronize(P->stream));
+    return P->res_h[idx];
+}
+
+// Diagonal preconditioning (Section 3): ruiz_iters Ruiz rounds (infinity
+// norms) then an optional Pock-Chambolle round (alpha = 1: 1-norms); in each
+// round both factors come from the same current matrix, zero norms give 1.
+// Row norms of A and of A^T (= column norms of A) are summed one lane per
+// row in index order, so the scaled matrix matches a sequential reference.
+void precondition(pdlp_problem *P, const pdlp_params &prm) {
+    hipStream_t s = P->stream;
+    const int m = P->m, n = P->n;
+    HIPCHECK(pdlp::launch_fill(s, m, P->d1, 1.0));
+    HIPCHECK(pdlp::launch_fill(s, n, P->d2, 1.0));
+    Arena tmp;
+    double *rn = tmp.dev<double>(m), *cn = tmp.dev<double>(n);
+    const int rounds = prm.ruiz_iters + (prm.pock_chambolle ? 1 : 0);
+    for (int round = 0; round < rounds; ++round) {
+        const int use_inf = round < prm.ruiz_iters;
+        HIPCHECK(pdlp::launch_row_norms(s, P->A, use_inf, rn));
+        HIPCHECK(pdlp::launch_row_norms(s, P->AT, use_inf, cn));
+        HIPCHECK(pdlp::launch_norm_to_factor(s, m, rn));
+        HIPCHECK(pdlp::launch_norm_to_factor(s, n, cn));
+        HIPCHECK(pdlp::launch_scale_matrix(s, P->A, rn, cn));
+        HIPCHECK(pdlp::launch_scale_matrix(s, P->AT, cn, rn));
+        HIPCHECK(pdlp::launch_div_inplace(s, m, P->d1, rn));
+        HIPCHECK(pdlp::launch_div_inplace(s, n, P->d2, cn));
+    }
+    HIPCHECK(pdlp::launch_scale_vectors(s, m, n, P->d1, P->d2, P->c, P->lc, P->uc, P->lv, P->uv,
+                                        P->cs, P->lcs, P->ucs, P->lvs, P->uvs));
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+// ====================================================================== engine
+
+namespace {
+
+enum { TERM_NONE = 0, TERM_FULL = 1, TERM_PRIMAL = 2, TERM_DUAL = 3 };
+enum { RUN_OK = 0, RUN_LIMIT = 1, RUN_TIME = 2, RUN_NUMERR = 3, RUN_POLISHED = 10 };
+
+// One PDLP run (the main run or a feasibility-polishing run) on the device.
+struct Engine {
+    pdlp_problem *P = nullptr;
+    Vecs v{};
+    int m = 0, n = 0;
+    Arena arena;
+    Iter it{};
+    double *x0 = nullptr, *y0 = nullptr, *xb = nullptr, *yb = nullptr, *axb = nullptr,
+           *atyb = nullptr, *xp = nullptr, *yp = nullptr;
+    Ctrl *ctrl_d = nullptr, *ctrl_h = nullptr;
+    double *part_dual = nullptr, *part_ps = nullptr, *part_pf = nullptr;
+    int gd = 0, gps = 0, gpf = 0;
+    GapState *gap_d = nullptr, *gap_h = nullptr;
+    KktOut *kkt_d = nullptr, *kkt_h = nullptr;
+    double *gap_part = nullptr;
+    int ggrid = 0;
+    // host-side counters of Algorithm 1
+    long long n_outer = 0, kkt_passes = 0, restarts_i = 0, restarts_ii = 0, restarts_iii = 0;
+    double mu_ref = INFINITY, mu_c_prev = INFINITY;
+
+    Engine(pdlp_problem *p, Vecs vv) : P(p), v(vv), m(p->m), n(p->n) {
+        for (int b = 0; b < 2; ++b) {
+            it.X[b] = arena.dev<double>(n);
+            it.ATY[b] = arena.dev<double>(n);
+            it.Y[b] = arena.dev<double>(m);
+            it.AX[b] = arena.dev<double>(m);
+        }
+        it.sx = arena.dev<double>(n);
+        it.sy = arena.dev<double>(m);
+        x0 = arena.dev<double>(n);
+        xb = arena.dev<double>(n);
+        atyb = arena.dev<double>(n);
+        xp = arena.dev<double>(n);
+        y0 = arena.dev<double>(m);
+        yb = arena.dev<double>(m);
+        axb = arena.dev<double>(m);
+        yp = arena.dev<double>(m);
+        ctrl_d = arena.dev<Ctrl>(1);
+        ctrl_h = arena.host<Ctrl>(1);
+        gd = P->A.grid;
+        gpf = P->AT.grid;
+        gps = red_grid(n);
+        part_dual = arena.dev<double>(2 * (size_t)std::max(gd, 1));
+        part_pf = arena.dev<double>(std::max(gpf, 1));
+        part_ps = arena.dev<double>(gps);
+        gap_d = arena.dev<GapState>(4);
+        gap_h = arena.host<GapState>(4);
+        kkt_d = arena.dev<KktOut>(1);
+        kkt_h = arena.host<KktOut>(1);
+        ggrid = red_grid((int64_t)m + n);
+        gap_part = arena.dev<double>((size_t)ggrid * (2 * pdlp::kGapPts));
+        std::memset(ctrl_h, 0, sizeof(Ctrl));
+    }
+
+    hipStream_t s() const { return P->stream; }
+    double *X() const { return it.X[ctrl_h->cur]; }
+    double *Y() const { return it.Y[ctrl_h->cur]; }
+    double *AXc() const { return it.AX[ctrl_h->cur]; }
+    double *ATYc() const { return it.ATY[ctrl_h->cur]; }
+
+    void push() {
+        HIPCHECK(hipMemcpyAsync(ctrl_d, ctrl_h, sizeof(Ctrl), hipMemcpyHostToDevice, s()));
+    }
+    void pull() {
+        HIPCHECK(hipMemcpyAsync(ctrl_h, ctrl_d, sizeof(Ctrl), hipMemcpyDeviceToHost, s()));
+        HIPCHECK(hipStreamSynchronize(s()));
+    }
+
+    double dist2(const double *a, const double *b, int64_t len) {
+        HIPCHECK(pdlp::launch_dist2(s(), len, a, b, P->red_part, red_grid(len), P->res_d));
+        return reduce_result(P);
+    }
+
+    // z = (x, y) from host-chosen device vectors; products computed here.
+    void set_point(const double *x_src, const double *y_src) {
+        Ctrl &c = *ctrl_h;
+        c.cur = 0;
+        HIPCHECK(pdlp::launch_copy(s(), n, x_src, it.X[0]));
+        HIPCHECK(pdlp::launch_copy(s(), m, y_src, it.Y[0]));
+        HIPCHECK(pdlp::launch_spmv_plain(s(), P->A, it.X[0], it.AX[0]));
+        HIPCHECK(pdlp::launch_spmv_plain(s(), P->AT, it.Y[0], it.ATY[0]));
+        HIPCHECK(pdlp::launch_copy(s(), n, it.X[0], x0));
+        HIPCHECK(pdlp::launch_copy(s(), m, it.Y[0], y0));
+        HIPCHECK(pdlp::launch_fill(s(), n, it.sx, 0.0));
+        HIPCHECK(pdlp::launch_fill(s(), m, it.sy, 0.0));
+    }
+
+    // Algorithm 1 initialization.  Reading: ||A||_inf in eta_hat^{0,0} is the
+    // largest absolute entry of the scaled matrix; the initial point is
+    // (proj_X(0), 0) unless a warm start is given.
+    void init(double omega, double eta_hat, const pdlp_params &prm) {
+        Ctrl &c = *ctrl_h;
+        std::memset(&c, 0, sizeof(Ctrl));
+        c.eta = eta_hat;
+        c.eta_hat = eta_hat;
+        c.omega = omega;
+        c.red_exp = prm.red_exp;
+        c.grow_exp = prm.grow_exp;
+        c.need_primal = 1;
+        n_outer = 0;
+        kkt_passes = 1;
+        restarts_i = restarts_ii = restarts_iii = 0;
+        mu_ref = INFINITY;
+        mu_c_prev = INFINITY;
+    }
+
+    void enqueue_attempt() {
+        HIPCHECK(pdlp::launch_primal(s(), n, v, it, ctrl_d, part_ps, gps));
+        HIPCHECK(pdlp::launch_spmv_dual(s(), P->A, v, it, ctrl_d, part_dual));
+        HIPCHECK(pdlp::launch_step_decide(s(), ctrl_d, part_dual, gd, part_ps, gps, part_pf, gpf));
+        HIPCHECK(pdlp::launch_spmv_primal(s(), P->AT, v, it, ctrl_d, part_pf));
+    }
+
+    // Exactly `target` accepted steps (or a numerical error).
+    void run_block(long long target) {
+        Ctrl &c = *ctrl_h;
+        c.block_target = target;
+        c.block_acc = 0;
+        c.stop = 0;
+        c.need_primal = 1;
+        c.run_at = 0;
+        push();
+        long long remaining = target;
+        for (;;) {
+            long long n_att = remaining + remaining / 8 + 1;
+            if (n_att > 4096) n_att = 4096;
+            for (long long a = 0; a < n_att; ++a) enqueue_attempt();
+            pull();
+            if (c.stop) break;
+            remaining = target - c.block_acc;
+        }
+        kkt_passes += c.block_acc;
+        if (c.pending_sy && !c.numerr) {
+            HIPCHECK(pdlp::launch_flush_sy(s(), m, it, ctrl_d));
+            c.pending_sy = 0;
+        }
+    }
+
+    void average() {
+        const double seta = ctrl_h->seta;
+        HIPCHECK(pdlp::launch_average(s(), n, it.sx, seta, xb));
+        HIPCHECK(pdlp::launch_average(s(), m, it.sy, seta, yb));
+        HIPCHECK(pdlp::launch_spmv_plain(s(), P->A, xb, axb));
+        HIPCHECK(pdlp::launch_spmv_plain(s(), P->AT, yb, atyb));
+        kkt_passes += 1;
+    }
+
+    void gap_enqueue(int slot, const double *x, const double *y, const double *ax,
+                     const double *aty, const double *xr, const double *yr, double omega) {
+        HIPCHECK(pdlp::launch_gap(s(), m, n, v, x, y, ax, aty, xr, yr, omega, gap_part, ggrid,
+                                  gap_d + slot));
+    }
+    void gap_fetch() {
+        HIPCHECK(hipMemcpyAsync(gap_h, gap_d, 4 * sizeof(GapState), hipMemcpyDeviceToHost, s()));
+        HIPCHECK(hipStreamSynchronize(s()));
+    }
+
+    KktOut kkt(const double *x, const double *y, const double *ax, const double *aty, int mode,
+               double *r_out = nullptr, double *x_out = nullptr, double *y_out = nullptr) {
+        HIPCHECK(pdlp::launch_kkt(s(), m, n, x, y, ax, aty, P->d1, P->d2, P->c, P->lc, P->uc,
+                                  P->lv, P->uv, mode, P->obj_offset, P->red_part,
+                                  red_grid((int64_t)m + n), r_out, x_out, y_out, kkt_d));
+        HIPCHECK(hipMemcpyAsync(kkt_h, kkt_d, sizeof(KktOut), hipMemcpyDeviceToHost, s()));
+        HIPCHECK(hipStreamSynchronize(s()));
+        return *kkt_h;
+    }
+};
+
+struct Candidate {
+    const double *x, *y, *ax, *aty;
+};
+
+struct RunOut {
+    Candidate cand{};
+    KktOut kkt{};
+    bool have = false;
+};
+
+bool term_met(const pdlp_params &prm, int mode, const KktOut &k) {
+    const double e = prm.eps_feas;
+    if (mode == TERM_PRIMAL) return k.primal_res_rel <= e;
+    if (mode == TERM_DUAL) return k.dual_res_rel <= e;
+    return k.primal_res_rel <= e && k.dual_res_rel <= e && k.rel_gap <= prm.eps_gap;
+}
+
+int effective_rc_mode(const pdlp_params &prm) {
+    if (prm.reduced_cost_mode >= 0) return prm.reduced_cost_mode;
+    return prm.polish ? 0 : 1;
+}
+
+// Smallest k' > k with (double)(t + k' - k) >= beta * (double)k' (condition (iii)).
+long long next_art(long long k, long long t, double beta, long long cap) {
+    if (!(beta < 1.0)) {
+        if (beta == 1.0 && t == k) return k + 1;
+        return cap;
+    }
+    double est = (beta * (double)k - (double)t) / (1.0 - beta);
+    long long d = (long long)std::ceil(est);
+    if (d < 1) d = 1;
+    d = std::max<long long>(1, d - 2);
+    while ((double)(t + d) < beta * (double)(k + d)) ++d;
+    return std::min(cap, k + d);
+}
+
+struct Ctx {
+    pdlp_problem *P;
+    const pdlp_params *prm;
+    double t_start;
+    pdlp_result *res;
+    Engine *sub = nullptr;  // polishing engine (lazy)
+    Arena *store = nullptr; // polishing result buffers
+    double *pol_x = nullptr, *pol_ax = nullptr, *pol_y = nullptr, *pol_aty = nullptr;
+    double *zero_m = nullptr;
+};
+
+int run_loop(Ctx &X, Engine &E, long long max_k, int term_mode, bool allow_polish, RunOut &out);
+
+// Feasibility polishing (Algorithm 4): primal feasibility LP (c = 0) from
+// (x_bar, 0), then dual feasibility LP (finite bounds set to 0) from (0, y_bar),
+// each for at most floor(k/8) accepted steps with the current omega and
+// eta_hat, then the polished pair must meet the full termination criteria.
+bool feasibility_polish(Ctx &X, Engine &E, RunOut &out) {
+    pdlp_problem *P = X.P;
+    const pdlp_params &prm = *X.prm;
+    const long long cap = E.ctrl_h->k / 8;
+    X.res->polish_attempts += 1;
+    if (!X.sub) {
+        X.store = new Arena();
+        X.pol_x = X.store->dev<double>(P->n);
+        X.pol_aty = X.store->dev<double>(P->n);
+        X.pol_y = X.store->dev<double>(P->m);
+        X.pol_ax = X.store->dev<double>(P->m);
+        X.zero_m = X.store->dev<double>(P->m);
+        HIPCHECK(pdlp::launch_fill(P->stream, P->m, X.zero_m, 0.0));
+        X.sub = new Engine(P, P->scaled());
+    }
+    Engine &S = *X.sub;
+    pdlp_params p2 = prm;
+    p2.polish = 0;
+    p2.reduced_cost_mode = 0;
+    Ctx X2 = X;
+    X2.prm = &p2;
+    bool ok = false;
+    // primal feasibility problem
+    S.v = Vecs{P->zero_n, P->lcs, P->ucs, P->lvs, P->uvs};
+    S.init(E.ctrl_h->omega, E.ctrl_h->eta_hat, prm);
+    S.set_point(E.xb, X.zero_m);
+    RunOut o1;
+    int rc = run_loop(X2, S, cap, TERM_PRIMAL, false, o1);
+    X.res->polish_iters += S.ctrl_h->k;
+    E.kkt_passes += S.kkt_passes;
+    if (rc == RUN_OK) {
+        HIPCHECK(pdlp::launch_copy(P->stream, P->n, o1.cand.x, X.pol_x));
+        HIPCHECK(pdlp::launch_copy(P->stream, P->m, o1.cand.ax, X.pol_ax));
+        // dual feasibility problem
+        S.v = Vecs{P->cs, P->lc0, P->uc0, P->lv0, P->uv0};
+        S.init(E.ctrl_h->omega, E.ctrl_h->eta_hat, prm);
+        S.set_point(P->zero_n, E.yb);
+        RunOut o2;
+        rc = run_loop(X2, S, cap, TERM_DUAL, false, o2);
+        X.res->polish_iters += S.ctrl_h->k;
+        E.kkt_passes += S.kkt_passes;
+        if (rc == RUN_OK) {
+            HIPCHECK(pdlp::launch_copy(P->stream, P->m, o2.cand.y, X.pol_y));
+            HIPCHECK(pdlp::launch_copy(P->stream, P->n, o2.cand.aty, X.pol_aty));
+            KktOut k = E.kkt(X.pol_x, X.pol_y, X.pol_ax, X.pol_aty, 0);
+            if (term_met(prm, TERM_FULL, k)) {
+                out.cand = Candidate{X.pol_x, X.pol_y, X.pol_ax, X.pol_aty};
+                out.kkt = k;
+                out.have = true;
+                ok = true;
+            }
+        }
+    }
+    if (rc == RUN_TIME) return false;
+    return ok;
+}
+
+// Algorithm 1 with the periodic checks (same readings as the oracle: at
+// n = 0 only (iii); mu_c_prev is the previous evaluation in the outer loop;
+// restart = candidate, then omega update, then mu_ref under the new omega;
+// ties in GetRestartCandidate go to the average).
+int run_loop(Ctx &X, Engine &E, long long max_k, int term_mode, bool allow_polish, RunOut &out) {
+    const pdlp_params &prm = *X.prm;
+    Ctrl &C = *E.ctrl_h;
+    const int rc_mode = effective_rc_mode(prm);
+    const int m = E.m, n = E.n;
+    long long next_polish = prm.polish_first > 0 ? prm.polish_first : 100;
+    while (allow_polish && next_polish <= C.k) next_polish *= 2;
+
+    if (term_mode != TERM_NONE) {
+        out.cand = Candidate{E.X(), E.Y(), E.AXc(), E.ATYc()};
+        out.kkt = E.kkt(out.cand.x, out.cand.y, out.cand.ax, out.cand.aty, rc_mode);
+        out.have = true;
+        if (term_met(prm, term_mode, out.kkt)) return RUN_OK;
+        if (C.k >= max_k) return RUN_LIMIT;
+    }
+    while (C.k < max_k) {
+        if (term_mode != TERM_NONE && now_s() - X.t_start >= prm.time_limit) return RUN_TIME;
+        long long kb = (C.k / prm.check_every + 1) * prm.check_every;
+        kb = std::min(kb, next_art(C.k, C.t, prm.beta_art, max_k));
+        kb = std::min(kb, max_k);
+        if (allow_polish && prm.polish) kb = std::min(kb, next_polish);
+        E.run_block(kb - C.k);
+        if (C.numerr) return RUN_NUMERR;
+
+        const bool full = (C.k % prm.check_every) == 0;
+        const bool art = (double)C.t >= prm.beta_art * (double)C.k;
+        const bool capchk = term_mode != TERM_NONE && C.k == max_k;
+        const bool pol = allow_polish && prm.polish && C.k == next_polish;
+        if (!(full || art || capchk || pol)) continue;
+
+        E.average();
+        if (pol) {
+            next_polish *= 2;
+            KktOut kb_ = E.kkt(E.xb, E.yb, E.axb, E.atyb, 0);
+            if (kb_.rel_gap < prm.eps_gap) {
+                RunOut po;
+                if (feasibility_polish(X, E, po)) {
+                    out = po;
+                    return RUN_POLISHED;
+                }
+            }
+            if (now_s() - X.t_start >= prm.time_limit) return RUN_TIME;
+            if (!(full || art || capchk)) continue;
+        }
+        E.gap_enqueue(0, E.X(), E.Y(), E.AXc(), E.ATYc(), E.x0, E.y0, C.omega);
+        E.gap_enqueue(1, E.xb, E.yb, E.axb, E.atyb, E.x0, E.y0, C.omega);
+        E.gap_fetch();
+        const double mu_cur = E.gap_h[0].mu, mu_avg = E.gap_h[1].mu;
+        if (!std::isfinite(mu_cur) || !std::isfinite(mu_avg)) return RUN_NUMERR;
+        const bool use_cur = mu_cur < mu_avg;
+        const double mu_c = use_cur ? mu_cur : mu_avg;
+        Candidate cand = use_cur ? Candidate{E.X(), E.Y(), E.AXc(), E.ATYc()}
+                                 : Candidate{E.xb, E.yb, E.axb, E.atyb};
+        if ((full || capchk) && term_mode != TERM_NONE) {
+            out.cand = cand;
+            out.kkt = E.kkt(cand.x, cand.y, cand.ax, cand.aty, rc_mode);
+            out.have = true;
+            if (prm.verbose)
+                std::fprintf(stderr,
+                             "[pdlp] k=%lld n=%lld omega=%.3e eta=%.3e mu=%.3e pres=%.2e "
+                             "dres=%.2e gap=%.2e obj=%.10e\n",
+                             C.k, E.n_outer, C.omega, C.eta_hat, mu_c, out.kkt.primal_res_rel,
+                             out.kkt.dual_res_rel, out.kkt.rel_gap, out.kkt.primal_obj);
+            if (!std::isfinite(out.kkt.rel_gap)) return RUN_NUMERR;
+            if (term_met(prm, term_mode, out.kkt)) return RUN_OK;
+            if (capchk) return RUN_LIMIT;
+        }
+        int why = 0;
+        if (!prm.adaptive_restarts || E.n_outer == 0) {
+            if (art) why = 3;
+        } else {
+            if (full && mu_c <= prm.beta_suff * E.mu_ref) why = 1;
+            else if (full && mu_c <= prm.beta_nec * E.mu_ref && mu_c > E.mu_c_prev) why = 2;
+            else if (art) why = 3;
+        }
+        if (!why) {
+            if (full) E.mu_c_prev = mu_c;
+            continue;
+        }
+        if (why == 1) E.restarts_i += 1;
+        if (why == 2) E.restarts_ii += 1;
+        if (why == 3) E.restarts_iii += 1;
+        hipStream_t s = E.s();
+        HIPCHECK(pdlp::launch_copy(s, n, E.x0, E.xp));
+        HIPCHECK(pdlp::launch_copy(s, m, E.y0, E.yp));
+        if (!use_cur) {
+            HIPCHECK(pdlp::launch_copy(s, n, E.xb, E.X()));
+            HIPCHECK(pdlp::launch_copy(s, m, E.yb, E.Y()));
+            HIPCHECK(pdlp::launch_copy(s, m, E.axb, E.AXc()));
+            HIPCHECK(pdlp::launch_copy(s, n, E.atyb, E.ATYc()));
+        }
+        HIPCHECK(pdlp::launch_copy(s, n, E.X(), E.x0));
+        HIPCHECK(pdlp::launch_copy(s, m, E.Y(), E.y0));
+        const double dx = std::sqrt(E.dist2(E.x0, E.xp, n));
+        const double dy = std::sqrt(E.dist2(E.y0, E.yp, m));
+        const double ez = prm.eps_zero;
+        if (dx > ez && dx < 1.0 / ez && dy > ez && dy < 1.0 / ez)
+            C.omega = std::exp(prm.theta * std::log(dy / dx) + (1.0 - prm.theta) * std::log(C.omega));
+        E.n_outer += 1;
+        C.t = 0;
+        C.seta = 0.0;
+        HIPCHECK(pdlp::launch_fill(s, n, E.it.sx, 0.0));
+        HIPCHECK(pdlp::launch_fill(s, m, E.it.sy, 0.0));
+        E.gap_enqueue(2, E.x0, E.y0, E.AXc(), E.ATYc(), E.xp, E.yp, C.omega);
+        E.gap_fetch();
+        E.mu_ref = E.gap_h[2].mu;
+        E.mu_c_prev = INFINITY;
+    }
+    return RUN_LIMIT;
+}
+
+}  // namespace
+
+struct pdlp_state {
+    pdlp_problem *P = nullptr;
+    pdlp_params prm{};
+    Engine *E = nullptr;
+    ~pdlp_state() { delete E; }
+};
+
+// ===================================================================== C ABI
+
+namespace {
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        f();
+        return PDLP_OK;
+    } catch (const LibError &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return PDLP_ERR_OUT_OF_MEMORY;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return PDLP_ERR_HIP;
+    }
+}
+
+void check_params(const pdlp_params &p) {
+    if (!(p.check_every >= 1)) invalid("check_every must be >= 1");
+    if (p.ruiz_iters < 0) invalid("ruiz_iters must be >= 0");
+    if (!(p.eps_feas >= 0.0) || !(p.eps_gap >= 0.0)) invalid("tolerances must be >= 0");
+    if (p.max_iters < 0) invalid("max_iters must be >= 0");
+    if (!(p.theta >= 0.0 && p.theta <= 1.0)) invalid("theta must lie in [0, 1]");
+    if (!(p.beta_art > 0.0)) invalid("beta_art must be > 0");
+}
+
+void engine_initialize(pdlp_state *S, const double *x0_host, const double *y0_host) {
+    pdlp_problem *P = S->P;
+    Engine &E = *S->E;
+    hipStream_t s = P->stream;
+    HIPCHECK(pdlp::launch_absmax(s, P->nnz, P->A.val, P->red_part, red_grid(P->nnz), P->res_d));
+    const double amax = reduce_result(P);
+    HIPCHECK(pdlp::launch_primal_weight_init(s, P->m, P->n, P->cs, P->lcs, P->ucs, P->red_part,
+                                             red_grid(std::max(P->m, P->n)), P->res_d));
+    const double cc = reduce_result(P, 0), bb = reduce_result(P, 1);
+    const double nc = std::sqrt(cc), nb = std::sqrt(bb);
+    const double omega = (nc > 0.0 && nb > 0.0) ? nc / nb : 1.0;
+    const double eta_hat = amax > 0.0 ? 1.0 / amax : 1.0;
+    E.init(omega, eta_hat, S->prm);
+    Arena tmp;
+    double *xs = tmp.dev<double>(P->n), *ys = tmp.dev<double>(P->m);
+    if (x0_host && y0_host) {
+        // warm start (unscaled) -> x~ = x / D2, y~ = y / D1, then project
+        HIPCHECK(hipMemcpyAsync(xs, x0_host, sizeof(double) * P->n, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(ys, y0_host, sizeof(double) * P->m, hipMemcpyHostToDevice, s));
+        HIPCHECK(pdlp::launch_scale_div(s, P->n, xs, P->d2, xs));
+        HIPCHECK(pdlp::launch_scale_div(s, P->m, ys, P->d1, ys));
+    } else {
+        HIPCHECK(pdlp::launch_clamp0(s, P->n, P->lvs, P->uvs, xs));
+        HIPCHECK(pdlp::launch_fill(s, P->m, ys, 0.0));
+    }
+    E.set_point(xs, ys);
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pdlp_last_error(void) { return g_last_error.c_str(); }
+
+void pdlp_params_default(pdlp_params *p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->eps_feas = 1e-8;
+    p->eps_gap = 1e-8;
+    p->max_iters = 1000000;
+    p->time_limit = 1e30;
+    p->check_every = 64;
+    p->ruiz_iters = 10;
+    p->pock_chambolle = 1;
+    p->polish = 0;
+    p->polish_first = 100;
+    p->reduced_cost_mode = -1;
+    p->adaptive_restarts = 1;
+    p->beta_suff = 0.1;
+    p->beta_nec = 0.9;
+    p->beta_art = 0.5;
+    p->theta = 0.5;
+    p->eps_zero = 1e-10;
+    p->red_exp = 0.3;
+    p->grow_exp = 0.6;
+    p->verbose = 0;
+}
+
+int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                        const int32_t *col, const double *val, const double *c, const double *lc,
+                        const double *uc, const double *lv, const double *uv, double obj_offset,
+                        const pdlp_params *params, void *hip_stream, pdlp_problem **out) {
+    return guarded([&] {
+        if (!out) invalid("out is NULL");
+        *out = nullptr;
+        validate(m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv);
+        if (!std::isfinite(obj_offset)) invalid("objective offset must be finite");
+        pdlp_params prm;
+        pdlp_params_default(&prm);
+        if (params) prm = *params;
+        check_params(prm);
+        auto *P = new pdlp_problem();
+        try {
+            P->m = m;
+            P->n = n;
+            P->nnz = nnz;
+            P->obj_offset = obj_offset;
+            P->scale_params = prm;
+            P->stream = static_cast<hipStream_t>(hip_stream);
+            hipStream_t s = P->stream;
+            Arena &a = P->arena;
+            DCsr &A = P->A;
+            A.rows = m;
+            A.cols = n;
+            A.nnz = nnz;
+            A.row_ptr = a.dev<int32_t>((size_t)m + 1);
+            A.col = a.dev<int32_t>(nnz);
+            A.val = a.dev<double>(nnz);
+            HIPCHECK(hipMemcpyAsync(A.row_ptr, row_ptr, sizeof(int32_t) * ((size_t)m + 1),
+                                    hipMemcpyHostToDevice, s));
+            if (nnz > 0) {
+                HIPCHECK(hipMemcpyAsync(A.col, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+                HIPCHECK(hipMemcpyAsync(A.val, val, sizeof(double) * nnz, hipMemcpyHostToDevice, s));
+            }
+            double **vecs_n[] = {&P->c, &P->lv, &P->uv, &P->cs, &P->lvs, &P->uvs, &P->d2,
+                                 &P->zero_n, &P->lv0, &P->uv0};
+            for (auto pp : vecs_n) *pp = a.dev<double>(n);
+            double **vecs_m[] = {&P->lc, &P->uc, &P->lcs, &P->ucs, &P->d1, &P->lc0, &P->uc0};
+            for (auto pp : vecs_m) *pp = a.dev<double>(m);
+            HIPCHECK(hipMemcpyAsync(P->c, c, sizeof(double) * n, hipMemcpyHostToDevice, s));
+            HIPCHECK(hipMemcpyAsync(P->lv, lv, sizeof(double) * n, hipMemcpyHostToDevice, s));
+            HIPCHECK(hipMemcpyAsync(P->uv, uv, sizeof(double) * n, hipMemcpyHostToDevice, s));
+            if (m > 0) {
+                HIPCHECK(hipMemcpyAsync(P->lc, lc, sizeof(double) * m, hipMemcpyHostToDevice, s));
+                HIPCHECK(hipMemcpyAsync(P->uc, uc, sizeof(double) * m, hipMemcpyHostToDevice, s));
+            }
+            // dual-feasibility bounds: every finite bound set to 0 (Algorithm 4)
+            {
+                std::vector<double> t((size_t)std::max(m, n));
+                for (int32_t j = 0; j < n; ++j) t[j] = std::isfinite(lv[j]) ? 0.0 : lv[j];
+                HIPCHECK(hipMemcpy(P->lv0, t.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+                for (int32_t j = 0; j < n; ++j) t[j] = std::isfinite(uv[j]) ? 0.0 : uv[j];
+                HIPCHECK(hipMemcpy(P->uv0, t.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+                if (m > 0) {
+                    for (int32_t i = 0; i < m; ++i) t[i] = std::isfinite(lc[i]) ? 0.0 : lc[i];
+                    HIPCHECK(hipMemcpy(P->lc0, t.data(), sizeof(double) * m, hipMemcpyHostToDevice));
+                    for (int32_t i = 0; i < m; ++i) t[i] = std::isfinite(uc[i]) ? 0.0 : uc[i];
+                    HIPCHECK(hipMemcpy(P->uc0, t.data(), sizeof(double) * m, hipMemcpyHostToDevice));
+                }
+            }
+            HIPCHECK(pdlp::launch_fill(s, n, P->zero_n, 0.0));
+            P->red_cap = 1024 * 8;
+            P->red_part = a.dev<double>(P->red_cap);
+            P->res_d = a.dev<double>(8);
+            P->res_h = a.host<double>(8);
+            build_transpose(P);
+            upload_blocks(P, A, row_ptr);
+            {
+                std::vector<int32_t> trp((size_t)n + 1);
+                HIPCHECK(hipMemcpy(trp.data(), P->AT.row_ptr, sizeof(int32_t) * ((size_t)n + 1),
+                                   hipMemcpyDeviceToHost));
+                upload_blocks(P, P->AT, trp.data());
+            }
+            precondition(P, prm);
+        } catch (...) {
+            delete P;
+            throw;
+        }
+        *out = P;
+    });
+}
+
+void pdlp_problem_destroy(pdlp_problem *p) { delete p; }
+
+int pdlp_problem_dims(const pdlp_problem *p, int32_t *m, int32_t *n, int64_t *nnz) {
+    return guarded([&] {
+        if (!p) invalid("problem is NULL");
+        if (m) *m = p->m;
+        if (n) *n = p->n;
+        if (nnz) *nnz = p->nnz;
+    });
+}
+
+int pdlp_problem_get_scaled(const pdlp_problem *p, double *d1, double *d2, double *val, double *c,
+                            double *lc, double *uc, double *lv, double *uv) {
+    return guarded([&] {
+        if (!p) invalid("problem is NULL");
+        auto get = [&](double *dst, const double *src, int64_t len) {
+            if (dst && len > 0)
+                HIPCHECK(hipMemcpy(dst, src, sizeof(double) * len, hipMemcpyDeviceToHost));
+        };
+        get(d1, p->d1, p->m);
+        get(d2, p->d2, p->n);
+        get(val, p->A.val, p->nnz);
+        get(c, p->cs, p->n);
+        get(lc, p->lcs, p->m);
+        get(uc, p->ucs, p->m);
+        get(lv, p->lvs, p->n);
+        get(uv, p->uvs, p->n);
+    });
+}
+
+int pdlp_spmv(const pdlp_problem *pc, int32_t transpose, int32_t scaled, const double *x_host,
+              double *out_host, int32_t repeat, double *ms) {
+    return guarded([&] {
+        auto *p = const_cast<pdlp_problem *>(pc);
+        if (!p || !x_host || !out_host) invalid("NULL argument");
+        if (repeat < 1) invalid("repeat must be >= 1");
+        const DCsr &M = transpose ? p->AT : p->A;
+        const int in_len = transpose ? p->m : p->n, out_len = transpose ? p->n : p->m;
+        const double *din = transpose ? p->d1 : p->d2;   // original = D1^-1 A~ D2^-1
+        const double *dout = transpose ? p->d2 : p->d1;
+        hipStream_t s = p->stream;
+        Arena tmp;
+        double *xi = tmp.dev<double>(in_len), *yo = tmp.dev<double>(out_len);
+        if (in_len > 0)
+            HIPCHECK(hipMemcpyAsync(xi, x_host, sizeof(double) * in_len, hipMemcpyHostToDevice, s));
+        if (!scaled) HIPCHECK(pdlp::launch_scale_div(s, in_len, xi, din, xi));
+        hipEvent_t e0, e1;
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        HIPCHECK(hipEventRecord(e0, s));
+        for (int r = 0; r < repeat; ++r) HIPCHECK(pdlp::launch_spmv_plain(s, M, xi, yo));
+        HIPCHECK(hipEventRecord(e1, s));
+        HIPCHECK(hipEventSynchronize(e1));
+        float el = 0.f;
+        HIPCHECK(hipEventElapsedTime(&el, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (ms) *ms = el / repeat;
+        if (!scaled) HIPCHECK(pdlp::launch_scale_div(s, out_len, yo, dout, yo));
+        if (out_len > 0)
+            HIPCHECK(hipMemcpyAsync(out_host, yo, sizeof(double) * out_len, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+    });
+}
+
+int pdlp_norm_gap(const pdlp_problem *pc, const double *x, const double *y, const double *ax,
+                  const double *aty, const double *xr, const double *yr, double omega,
+                  double *mu) {
+    return guarded([&] {
+        auto *p = const_cast<pdlp_problem *>(pc);
+        if (!p || !x || !aty || !xr || !mu || (p->m > 0 && (!y || !ax || !yr)))
+            invalid("NULL argument");
+        if (!(omega > 0.0)) invalid("omega must be > 0");
+        hipStream_t s = p->stream;
+        Arena tmp;
+        const int m = p->m, n = p->n;
+        double *d[6];
+        const double *h[6] = {x, aty, xr, y, ax, yr};
+        for (int i = 0; i < 6; ++i) {
+            const int len = i < 3 ? n : m;
+            d[i] = tmp.dev<double>(len);
+            if (len > 0)
+                HIPCHECK(hipMemcpyAsync(d[i], h[i], sizeof(double) * len, hipMemcpyHostToDevice, s));
+        }
+        const int grid = red_grid((int64_t)m + n);
+        double *part = tmp.dev<double>((size_t)grid * 2 * pdlp::kGapPts);
+        GapState *gs = tmp.dev<GapState>(1);
+        HIPCHECK(pdlp::launch_gap(s, m, n, p->scaled(), d[0], d[3], d[4], d[1], d[2], d[5], omega,
+                                  part, grid, gs));
+        GapState hs;
+        HIPCHECK(hipMemcpyAsync(&hs, gs, sizeof(GapState), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        *mu = hs.mu;
+    });
+}
+
+int pdlp_state_create(pdlp_problem *p, const pdlp_params *params, pdlp_state **out) {
+    return guarded([&] {
+        if (!p || !out) invalid("NULL argument");
+        *out = nullptr;
+        auto *S = new pdlp_state();
+        try {
+            S->P = p;
+            pdlp_params_default(&S->prm);
+            if (params) S->prm = *params;
+            check_params(S->prm);
+            S->E = new Engine(p, p->scaled());
+            engine_initialize(S, nullptr, nullptr);
+        } catch (...) {
+            delete S;
+            throw;
+        }
+        *out = S;
+    });
+}
+
+void pdlp_state_destroy(pdlp_state *s) { delete s; }
+
+int pdlp_iterate_k(pdlp_state *S, int64_t k, pdlp_iter_info *info) {
+    return guarded([&] {
+        if (!S || k < 0) invalid("bad state or k < 0");
+        Engine &E = *S->E;
+        pdlp_result dummy;
+        std::memset(&dummy, 0, sizeof dummy);
+        Ctx X{S->P, &S->prm, now_s(), &dummy};
+        RunOut out;
+        const int rc = run_loop(X, E, E.ctrl_h->k + k, TERM_NONE, false, out);
+        if (rc == RUN_NUMERR) throw LibError(PDLP_ERR_STATE, "numerical error during iterations");
+        if (info) {
+            const Ctrl &C = *E.ctrl_h;
+            info->k = C.k;
+            info->t = C.t;
+            info->n_outer = E.n_outer;
+            info->attempts = C.attempts;
+            info->kkt_passes = E.kkt_passes;
+            info->restarts_i = E.restarts_i;
+            info->restarts_ii = E.restarts_ii;
+            info->restarts_iii = E.restarts_iii;
+            info->omega = C.omega;
+            info->eta_hat = C.eta_hat;
+            info->last_eta = C.eta_used;
+            info->last_eta_bar = C.last_eta_bar;
+            info->seta = C.seta;
+            info->mu_ref = E.mu_ref;
+            info->mu_c_prev = E.mu_c_prev;
+        }
+    });
+}
+
+int pdlp_state_get(const pdlp_state *S, pdlp_state_blob *b) {
+    return guarded([&] {
+        if (!S || !b) invalid("NULL argument");
+        Engine &E = *S->E;
+        const int m = E.m, n = E.n;
+        auto get = [&](double *dst, const double *src, int len) {
+            if (dst && len > 0)
+                HIPCHECK(hipMemcpy(dst, src, sizeof(double) * len, hipMemcpyDeviceToHost));
+        };
+        get(b->x, E.X(), n);
+        get(b->y, E.Y(), m);
+        get(b->ax, E.AXc(), m);
+        get(b->aty, E.ATYc(), n);
+        get(b->x0, E.x0, n);
+        get(b->y0, E.y0, m);
+        get(b->sx, E.it.sx, n);
+        get(b->sy, E.it.sy, m);
+        const Ctrl &C = *E.ctrl_h;
+        b->seta = C.seta;
+        b->omega = C.omega;
+        b->eta_hat = C.eta_hat;
+        b->mu_ref = E.mu_ref;
+        b->mu_c_prev = E.mu_c_prev;
+        b->last_eta = C.eta_used;
+        b->k = C.k;
+        b->t = C.t;
+        b->n_outer = E.n_outer;
+        b->attempts = C.attempts;
+        b->kkt_passes = E.kkt_passes;
+        b->restarts_i = E.restarts_i;
+        b->restarts_ii = E.restarts_ii;
+        b->restarts_iii = E.restarts_iii;
+    });
+}
+
+int pdlp_state_set(pdlp_state *S, const pdlp_state_blob *b) {
+    return guarded([&] {
+        if (!S || !b) invalid("NULL argument");
+        Engine &E = *S->E;
+        const int m = E.m, n = E.n;
+        if (!b->x || !b->aty || !b->x0 || !b->sx || (m > 0 && (!b->y || !b->ax || !b->y0 || !b->sy)))
+            invalid("state blob arrays must not be NULL");
+        Ctrl &C = *E.ctrl_h;
+        C.cur = 0;
+        auto put = [&](double *dst, const double *src, int len) {
+            if (len > 0) HIPCHECK(hipMemcpy(dst, src, sizeof(double) * len, hipMemcpyHostToDevice));
+        };
+        put(E.it.X[0], b->x, n);
+        put(E.it.Y[0], b->y, m);
+        put(E.it.AX[0], b->ax, m);
+        put(E.it.ATY[0], b->aty, n);
+        put(E.x0, b->x0, n);
+        put(E.y0, b->y0, m);
+        put(E.it.sx, b->sx, n);
+        put(E.it.sy, b->sy, m);
+        C.seta = b->seta;
+        C.omega = b->omega;
+        C.eta_hat = b->eta_hat;
+        C.eta = b->eta_hat;
+        C.eta_used = b->last_eta;
+        C.k = b->k;
+        C.t = b->t;
+        C.attempts = b->attempts;
+        C.pending_sy = 0;
+        C.numerr = 0;
+        E.mu_ref = b->mu_ref;
+        E.mu_c_prev = b->mu_c_prev;
+        E.n_outer = b->n_outer;
+        E.kkt_passes = b->kkt_passes;
+        E.restarts_i = b->restarts_i;
+        E.restarts_ii = b->restarts_ii;
+        E.restarts_iii = b->restarts_iii;
+    });
+}
+
+int pdlp_solve(pdlp_problem *p, const pdlp_params *params, const double *x0_host,
+               const double *y0_host, pdlp_result *res) {
+    return guarded([&] {
+        if (!p || !res) invalid("NULL argument");
+        if ((x0_host == nullptr) != (y0_host == nullptr) && p->m > 0)
+            invalid("warm start needs both x0 and y0");
+        const double t0 = now_s();
+        pdlp_state S;
+        S.P = p;
+        pdlp_params_default(&S.prm);
+        if (params) S.prm = *params;
+        check_params(S.prm);
+        S.E = new Engine(p, p->scaled());
+        engine_initialize(&S, x0_host, y0_host);
+        double *ux = res->x, *uy = res->y, *ur = res->r;
+        std::memset(res, 0, sizeof(*res));
+        res->x = ux;
+        res->y = uy;
+        res->r = ur;
+        res->seconds_setup = now_s() - t0;
+        Ctx X{p, &S.prm, t0, res};
+        RunOut out;
+        int rc;
+        Engine &E = *S.E;
+        try {
+            rc = run_loop(X, E, S.prm.max_iters, TERM_FULL, S.prm.polish != 0, out);
+        } catch (...) {
+            delete X.sub;
+            delete X.store;
+            throw;
+        }
+        const int rc_mode = rc == RUN_POLISHED ? 0 : effective_rc_mode(S.prm);
+        Arena tmp;
+        double *rx = tmp.dev<double>(p->n), *ry = tmp.dev<double>(p->m), *rr = tmp.dev<double>(p->n);
+        if (!out.have) out.cand = Candidate{E.X(), E.Y(), E.AXc(), E.ATYc()};
+        KktOut k = E.kkt(out.cand.x, out.cand.y, out.cand.ax, out.cand.aty, rc_mode, rr, rx, ry);
+        if (ux) HIPCHECK(hipMemcpy(ux, rx, sizeof(double) * p->n, hipMemcpyDeviceToHost));
+        if (uy && p->m > 0) HIPCHECK(hipMemcpy(uy, ry, sizeof(double) * p->m, hipMemcpyDeviceToHost));
+        if (ur) HIPCHECK(hipMemcpy(ur, rr, sizeof(double) * p->n, hipMemcpyDeviceToHost));
+        res->status = rc == RUN_OK || rc == RUN_POLISHED ? PDLP_STATUS_OPTIMAL
+                      : rc == RUN_TIME                   ? PDLP_STATUS_TIME_LIMIT
+                      : rc == RUN_NUMERR                 ? PDLP_STATUS_NUMERICAL_ERROR
+                                                         : PDLP_STATUS_ITERATION_LIMIT;
+        res->polished = rc == RUN_POLISHED;
+        res->iterations = E.ctrl_h->k;
+        res->attempts = E.ctrl_h->attempts;
+        res->kkt_passes = E.kkt_passes;
+        res->restarts_i = E.restarts_i;
+        res->restarts_ii = E.restarts_ii;
+        res->restarts_iii = E.restarts_iii;
+        res->restarts = E.restarts_i + E.restarts_ii + E.restarts_iii;
+        res->primal_obj = k.primal_obj;
+        res->dual_obj = k.dual_obj;
+        res->rel_gap = k.rel_gap;
+        res->primal_res_abs = k.primal_res_abs;
+        res->primal_res_rel = k.primal_res_rel;
+        res->dual_res_abs = k.dual_res_abs;
+        res->dual_res_rel = k.dual_res_rel;
+        res->omega = E.ctrl_h->omega;
+        res->eta = E.ctrl_h->eta_hat;
+        delete X.sub;
+        delete X.store;
+        res->seconds = now_s() - t0;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,151 @@
+// Internal declarations shared by the kernel and host translation units of
+// the gfx950 PDLP library.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pdlp {
+
+constexpr int kThreads = 256;        // threads per workgroup (4 wave64)
+constexpr int kStage = 2048;         // LDS product stage of the CSR stream kernels (doubles)
+constexpr int kMaxBlockRows = 1024;  // rows per stream block
+constexpr int kGapPts = 32;          // abscissae per multisection pass of the gap search
+constexpr int kGapMaxPass = 24;
+
+// CSR matrix on the device with a row-block partition: block b covers rows
+// [blk[b], blk[b+1]); either its nonzeros fit the LDS stage (stream mode) or
+// it is a single long row (reduced across the whole workgroup).
+struct DCsr {
+    int32_t rows = 0, cols = 0;
+    int64_t nnz = 0;
+    int32_t *row_ptr = nullptr, *col = nullptr;
+    double *val = nullptr;
+    int32_t nblk = 0;
+    int32_t *blk = nullptr;
+    int32_t grid = 0;  // workgroups of the persistent stream kernels
+};
+
+// Scaled problem vectors seen by the iteration.
+struct Vecs {
+    const double *c, *lc, *uc, *lv, *uv;
+};
+
+// Double-buffered iterate: index `cur` (in Ctrl) is the accepted point,
+// cur^1 receives the candidate.
+struct Iter {
+    double *X[2], *Y[2], *AX[2], *ATY[2];
+    double *sx, *sy;
+};
+
+// Device control block of the step loop.  Written by the step-decision
+// kernel (one thread) and by the host between iteration blocks; every other
+// kernel only reads it, which is what lets a block of step attempts run
+// without host synchronization.
+struct Ctrl {
+    double eta;           // step size of the next attempt
+    double eta_hat;       // starting step size of the next accepted step
+    double omega;         // primal weight
+    double eta_used;      // step of the last accepted attempt (primal average)
+    double eta_avg_y;     // step pending for the dual average
+    double seta;          // sum of accepted steps since the restart
+    double last_eta_bar;
+    double red_exp, grow_exp;
+    double fixed_eta;
+    long long k, t, attempts, block_acc, block_target;
+    int cur;              // which buffer holds the accepted iterate
+    int stop;             // block target reached or numerical error
+    int need_primal;      // the next attempt starts with the standalone primal step
+    int run_at;           // last attempt accepted: run the A^T product
+    int pending_sy;       // dual average owes eta_avg_y * y_cur
+    int numerr;
+    int fixed_step;
+    int pad;
+};
+
+// Device-side state of one normalized-duality-gap evaluation.
+struct GapState {
+    double r2, r, omega, A0, Dinf;
+    double lo, hi;
+    double pts[kGapPts];
+    int npass, done, pathend, linear;
+    double s_star, Acoef, Bcoef, f, mu;
+    int bad;
+    int pad;
+};
+
+// Results of the termination evaluation (Section 6).
+struct KktOut {
+    double primal_obj, dual_obj, rel_gap;
+    double primal_res_abs, primal_res_rel, dual_res_abs, dual_res_rel;
+    double pad;
+};
+
+// ------------------------------------------------------------ launchers
+// All launchers enqueue on `s` and return hipGetLastError().
+
+// step attempt pieces
+hipError_t launch_primal(hipStream_t s, int n, Vecs v, Iter it, const Ctrl *ctrl, double *part,
+                         int grid);
+hipError_t launch_spmv_dual(hipStream_t s, const DCsr &A, Vecs v, Iter it, const Ctrl *ctrl,
+                            double *part);
+hipError_t launch_step_decide(hipStream_t s, Ctrl *ctrl, const double *part_dual, int gd,
+                              const double *part_ps, int gps, const double *part_pf, int gpf);
+hipError_t launch_spmv_primal(hipStream_t s, const DCsr &AT, Vecs v, Iter it, const Ctrl *ctrl,
+                              double *part);
+hipError_t launch_flush_sy(hipStream_t s, int m, Iter it, Ctrl *ctrl);
+
+// plain products and vector helpers
+hipError_t launch_spmv_plain(hipStream_t s, const DCsr &A, const double *x, double *out);
+hipError_t launch_scale_div(hipStream_t s, int64_t len, const double *a, const double *d,
+                            double *out);  // out = a / d
+hipError_t launch_scale_mul(hipStream_t s, int64_t len, const double *a, const double *d,
+                            double *out);  // out = a * d
+hipError_t launch_average(hipStream_t s, int64_t len, const double *sum, double seta,
+                          double *out);
+hipError_t launch_fill(hipStream_t s, int64_t len, double *a, double v);
+hipError_t launch_clamp0(hipStream_t s, int n, const double *lv, const double *uv, double *x);
+hipError_t launch_copy(hipStream_t s, int64_t len, const double *a, double *out);
+
+// reductions (deterministic): result written to out[0..]
+hipError_t launch_dist2(hipStream_t s, int64_t len, const double *a, const double *b, double *part,
+                        int grid, double *out);
+hipError_t launch_sum_max(hipStream_t s, const double *part, int grid, int nv, const int *is_max,
+                          double *out);
+
+// preconditioning
+hipError_t launch_row_norms(hipStream_t s, const DCsr &A, int use_inf, double *out);
+hipError_t launch_norm_to_factor(hipStream_t s, int len, double *nrm);  // sqrt, 0 -> 1
+hipError_t launch_scale_matrix(hipStream_t s, const DCsr &A, const double *rf, const double *cf);
+hipError_t launch_div_inplace(hipStream_t s, int len, double *d, const double *f);
+hipError_t launch_scale_vectors(hipStream_t s, int m, int n, const double *d1, const double *d2,
+                                const double *c, const double *lc, const double *uc,
+                                const double *lv, const double *uv, double *cs, double *lcs,
+                                double *ucs, double *lvs, double *uvs);
+hipError_t launch_absmax(hipStream_t s, int64_t len, const double *a, double *part, int grid,
+                         double *out);
+hipError_t launch_primal_weight_init(hipStream_t s, int m, int n, const double *c,
+                                     const double *lc, const double *uc, double *part, int grid,
+                                     double *out);  // out[0] = ||c||^2, out[1] = ||Combine||^2
+
+// transpose
+hipError_t launch_row_ids(hipStream_t s, int m, const int32_t *row_ptr, int32_t *rowid);
+hipError_t launch_iota(hipStream_t s, int64_t len, int32_t *a);
+hipError_t launch_transpose_finish(hipStream_t s, int64_t nnz, int n, const int32_t *sorted_cols,
+                                   const int32_t *perm, const int32_t *rowid, const double *val,
+                                   int32_t *t_row_ptr, int32_t *t_col, double *t_val);
+
+// termination evaluation (original units)
+hipError_t launch_kkt(hipStream_t s, int m, int n, const double *xs, const double *ys,
+                      const double *axs, const double *atys, const double *d1, const double *d2,
+                      const double *c, const double *lc, const double *uc, const double *lv,
+                      const double *uv, int mode, double obj_offset, double *part, int grid,
+                      double *r_out, double *x_out, double *y_out, KktOut *out);
+
+// normalized duality gap
+hipError_t launch_gap(hipStream_t s, int m, int n, Vecs v, const double *x, const double *y,
+                      const double *ax, const double *aty, const double *xr, const double *yr,
+                      double omega, double *part, int grid, GapState *gs);
+
+}  // namespace pdlp

@@ -1,0 +1,1193 @@
+// gfx950 kernels of the PDLP hot path (FP64 values, int32 indices).
+//
+// Step attempt (Algorithm 2 with the PDHG update of Section 2):
+//   k_primal        x' = proj_X(x - tau (c - A^T y))       (after a rejection or at block start)
+//   k_spmv_dual     A x' by CSR stream + dual step (case form), ||dy||^2, dy^T A dx partials
+//   k_step_decide   eta_bar, eta', accept/reject, counters    (one workgroup)
+//   k_spmv_primal   A^T y' by CSR stream + primal average + next x' (after an acceptance)
+// Every kernel reads the device control block and switches itself off for
+// work that a rejection or the end of an iteration block makes void, so a
+// whole block of attempts is enqueued without host synchronization.
+//
+// Reductions are deterministic: fixed grids, per-thread accumulation in a
+// fixed order, wave butterfly + LDS in a fixed order, and a one-workgroup
+// final pass in a fixed order.  No floating-point atomics anywhere.
+#include "pdlp_internal.h"
+
+#include <cmath>
+
+namespace pdlp {
+
+// ------------------------------------------------------------ reductions
+
+__device__ __forceinline__ double nan_max(double a, double b) {
+    if (a != a) return a;
+    if (b != b) return b;
+    return b > a ? b : a;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Reduce NV per-thread values over the workgroup; bit i of MAXMASK selects a
+// max instead of a sum for value i.  The result is valid in thread 0.
+// lds must hold (kThreads/64)*NV doubles.
+template <int NV, unsigned MAXMASK = 0u>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], double *lds) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = ((MAXMASK >> i) & 1u) ? wave_max(v[i]) : wave_sum(v[i]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) lds[wid * NV + i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double a = lds[i];
+            for (int w = 1; w < kThreads / 64; ++w)
+                a = ((MAXMASK >> i) & 1u) ? nan_max(a, lds[w * NV + i]) : a + lds[w * NV + i];
+            v[i] = a;
+        }
+    }
+    __syncthreads();
+}
+
+template <int NV, unsigned MAXMASK = 0u>
+__device__ __forceinline__ void write_partials(double (&v)[NV], double *lds, double *part) {
+    block_reduce<NV, MAXMASK>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) part[blockIdx.x * NV + i] = v[i];
+    }
+}
+
+__device__ __forceinline__ double clampd(double v, double lo, double hi) {
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// Dual update in case form (Section 2): with yhat = y - sigma A(2x' - x),
+// y' = yhat + sigma uc if yhat < -sigma uc; yhat + sigma lc if yhat > -sigma lc; else 0.
+__device__ __forceinline__ double dual_case(double yhat, double sigma, double lc, double uc) {
+    if (isfinite(uc)) {
+        const double su = sigma * uc;
+        if (yhat < -su) return yhat + su;
+    }
+    if (isfinite(lc)) {
+        const double sl = sigma * lc;
+        if (yhat > -sl) return yhat + sl;
+    }
+    return 0.0;
+}
+
+// ------------------------------------------------------- CSR stream SpMV
+//
+// Workgroup-per-row-block CSR product.  A short-row block stages its
+// products in LDS with fully coalesced loads of val/col (one gather of x per
+// nonzero), then one lane per row sums its slice in column order -- the
+// same order as a sequential row loop.  A long-row block (single row with
+// more nonzeros than the stage) is reduced across the workgroup.  The grid is
+// persistent: workgroup g handles blocks g, g + grid, ...
+
+template <int NACC, class Epi>
+__device__ __forceinline__ void stream_spmv(const DCsr &A, const double *__restrict__ x,
+                                            const Epi &epi, double (&acc)[NACC], double *prod,
+                                            double *red) {
+    constexpr int kPer = kStage / kThreads;
+    for (int b = blockIdx.x; b < A.nblk; b += gridDim.x) {
+        const int r0 = A.blk[b], r1 = A.blk[b + 1];
+        const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
+        const int len = e1 - e0;
+        if (len <= kStage) {
+            int ci[kPer];
+            double vv[kPer];
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int q = i * kThreads + threadIdx.x;
+                if (q < len) {
+                    ci[i] = __builtin_nontemporal_load(A.col + e0 + q);
+                    vv[i] = __builtin_nontemporal_load(A.val + e0 + q);
+                } else {
+                    ci[i] = 0;
+                    vv[i] = 0.0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int q = i * kThreads + threadIdx.x;
+                if (q < len) prod[q] = vv[i] * x[ci[i]];
+            }
+            __syncthreads();
+            for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
+                const int a = A.row_ptr[r] - e0, z = A.row_ptr[r + 1] - e0;
+                double s = 0.0;
+                for (int q = a; q < z; ++q) s += prod[q];
+                epi(r, s, acc);
+            }
+            __syncthreads();
+        } else {
+            double s = 0.0;
+            for (int e = e0 + threadIdx.x; e < e1; e += kThreads)
+                s += __builtin_nontemporal_load(A.val + e) * x[__builtin_nontemporal_load(A.col + e)];
+            double t[1] = {s};
+            block_reduce<1>(t, red);
+            if (threadIdx.x == 0) epi(r0, t[0], acc);
+        }
+    }
+}
+
+struct PlainEpi {
+    double *out;
+    template <int N>
+    __device__ __forceinline__ void operator()(int r, double s, double (&)[N]) const { out[r] = s; }
+};
+
+__global__ __launch_bounds__(kThreads) void k_spmv_plain(DCsr A, const double *__restrict__ x,
+                                                         double *__restrict__ out) {
+    __shared__ double prod[kStage];
+    __shared__ double red[kThreads / 64];
+    double acc[1] = {0.0};
+    PlainEpi epi{out};
+    stream_spmv<1>(A, x, epi, acc, prod, red);
+}
+
+// A x' + dual step.  acc[0] = ||y'-y||^2, acc[1] = (y'-y)^T (A x' - A x).
+struct DualEpi {
+    const double *y, *ax, *lc, *uc;
+    double *ax_new, *y_new, *sy;
+    double sigma, eta_avg;
+    int pend;
+    __device__ __forceinline__ void operator()(int r, double s, double (&acc)[2]) const {
+        ax_new[r] = s;
+        const double yr = y[r];
+        if (pend) sy[r] += eta_avg * yr;
+        const double axr = ax[r];
+        const double yhat = yr - sigma * (2.0 * s - axr);
+        const double yn = dual_case(yhat, sigma, lc[r], uc[r]);
+        y_new[r] = yn;
+        const double dy = yn - yr;
+        acc[0] += dy * dy;
+        acc[1] += dy * (s - axr);
+    }
+};
+
+__global__ __launch_bounds__(kThreads) void k_spmv_dual(DCsr A, Vecs v, Iter it, const Ctrl *ctrl,
+                                                        double *part) {
+    if (ctrl->stop) return;
+    __shared__ double prod[kStage];
+    __shared__ double red[2 * (kThreads / 64)];
+    const int cur = ctrl->cur;
+    DualEpi epi{it.Y[cur], it.AX[cur], v.lc, v.uc, it.AX[cur ^ 1], it.Y[cur ^ 1], it.sy,
+                ctrl->eta * ctrl->omega, ctrl->eta_avg_y, ctrl->pending_sy};
+    double acc[2] = {0.0, 0.0};
+    stream_spmv<2>(A, it.X[cur ^ 1], epi, acc, prod, red);
+    write_partials<2>(acc, red, part);
+}
+
+// A^T y' + primal average + next candidate x'.  acc[0] = ||x'-x||^2.
+struct PrimalEpi {
+    const double *x, *c, *lv, *uv;
+    double *aty, *x_new, *sx;
+    double eta_used, tau;
+    int next;
+    __device__ __forceinline__ void operator()(int j, double s, double (&acc)[1]) const {
+        aty[j] = s;
+        const double xj = x[j];
+        sx[j] += eta_used * xj;
+        if (next) {
+            const double g = c[j] - s;
+            const double xn = clampd(xj - tau * g, lv[j], uv[j]);
+            x_new[j] = xn;
+            const double d = xn - xj;
+            acc[0] += d * d;
+        }
+    }
+};
+
+__global__ __launch_bounds__(kThreads) void k_spmv_primal(DCsr AT, Vecs v, Iter it,
+                                                          const Ctrl *ctrl, double *part) {
+    if (!ctrl->run_at) return;
+    __shared__ double prod[kStage];
+    __shared__ double red[kThreads / 64];
+    const int cur = ctrl->cur;
+    const int next = !ctrl->stop;
+    PrimalEpi epi{it.X[cur], v.c, v.lv, v.uv, it.ATY[cur], it.X[cur ^ 1], it.sx,
+                  ctrl->eta_used, ctrl->eta / ctrl->omega, next};
+    double acc[1] = {0.0};
+    stream_spmv<1>(AT, it.Y[cur], epi, acc, prod, red);
+    if (next) write_partials<1>(acc, red, part);
+}
+
+// Standalone primal step: x' = proj_X(x - tau (c - A^T y)).
+__global__ __launch_bounds__(kThreads) void k_primal(int n, Vecs v, Iter it, const Ctrl *ctrl,
+                                                     double *part) {
+    if (ctrl->stop || !ctrl->need_primal) return;
+    __shared__ double red[kThreads / 64];
+    const int cur = ctrl->cur;
+    const double tau = ctrl->eta / ctrl->omega;
+    const double *x = it.X[cur], *aty = it.ATY[cur];
+    double *xn = it.X[cur ^ 1];
+    double acc[1] = {0.0};
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += gridDim.x * kThreads) {
+        const double xj = x[j];
+        const double g = v.c[j] - aty[j];
+        const double xv = clampd(xj - tau * g, v.lv[j], v.uv[j]);
+        xn[j] = xv;
+        const double d = xv - xj;
+        acc[0] += d * d;
+    }
+    write_partials<1>(acc, red, part);
+}
+
+// Algorithm 2 decision for one attempt (one workgroup).
+__global__ __launch_bounds__(kThreads) void k_step_decide(Ctrl *ctrl, const double *pd, int gd,
+                                                          const double *pps, int gps,
+                                                          const double *ppf, int gpf) {
+    __shared__ double red[3 * (kThreads / 64)];
+    if (ctrl->stop) {
+        if (threadIdx.x == 0) ctrl->run_at = 0;
+        return;
+    }
+    const int np = ctrl->need_primal;
+    const double *pp = np ? pps : ppf;
+    const int gp = np ? gps : gpf;
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < gp; i += kThreads) a[0] += pp[i];
+    for (int i = threadIdx.x; i < gd; i += kThreads) {
+        a[1] += pd[2 * i];
+        a[2] += pd[2 * i + 1];
+    }
+    block_reduce<3>(a, red);
+    if (threadIdx.x != 0) return;
+    Ctrl c = *ctrl;
+    const double eta = c.eta, omega = c.omega;
+    const double num = omega * a[0] + a[1] / omega;
+    const double den = 2.0 * fabs(a[2]);
+    c.attempts += 1;
+    if (!isfinite(num) || !isfinite(den)) {
+        c.numerr = 1;
+        c.stop = 1;
+        c.run_at = 0;
+        *ctrl = c;
+        return;
+    }
+    const double eta_bar = den > 0.0 ? num / den : INFINITY;
+    const double jj = (double)(c.attempts + 1);
+    const double e1 = (1.0 - pow(jj, -c.red_exp)) * eta_bar;
+    const double e2 = (1.0 + pow(jj, -c.grow_exp)) * eta;
+    const double eta_next = e1 < e2 ? e1 : e2;
+    c.last_eta_bar = eta_bar;
+    if (c.fixed_step || eta <= eta_bar) {
+        c.cur ^= 1;
+        c.k += 1;
+        c.t += 1;
+        c.block_acc += 1;
+        c.seta += eta;
+        c.eta_used = eta;
+        c.eta_avg_y = eta;
+        c.pending_sy = 1;
+        c.eta_hat = c.fixed_step ? c.fixed_eta : eta_next;
+        c.eta = c.eta_hat;
+        c.stop = c.block_acc >= c.block_target;
+        c.need_primal = c.stop;
+        c.run_at = 1;
+    } else {
+        c.eta = eta_next;
+        c.need_primal = 1;
+        c.run_at = 0;
+        c.pending_sy = 0;
+    }
+    *ctrl = c;
+}
+
+// Dual average owed by the last accepted step of a block.
+__global__ __launch_bounds__(kThreads) void k_flush_sy(int m, Iter it, Ctrl *ctrl) {
+    if (!ctrl->pending_sy) return;
+    const int cur = ctrl->cur;
+    const double e = ctrl->eta_avg_y;
+    const double *y = it.Y[cur];
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += gridDim.x * kThreads)
+        it.sy[i] += e * y[i];
+}
+
+__global__ void k_clear_pending(Ctrl *ctrl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctrl->pending_sy = 0;
+}
+
+// ------------------------------------------------------------ vector ops
+
+__global__ __launch_bounds__(kThreads) void k_div(int64_t len, const double *a, const double *d,
+                                                  double *out) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads)
+        out[i] = a[i] / d[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_mul(int64_t len, const double *a, const double *d,
+                                                  double *out) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads)
+        out[i] = a[i] * d[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_average(int64_t len, const double *sum, double seta,
+                                                      double *out) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads)
+        out[i] = sum[i] / seta;
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill(int64_t len, double *a, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads)
+        a[i] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy(int64_t len, const double *a, double *out) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads)
+        out[i] = a[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_clamp0(int n, const double *lv, const double *uv,
+                                                     double *x) {
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += gridDim.x * kThreads)
+        x[j] = clampd(0.0, lv[j], uv[j]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_dist2(int64_t len, const double *a, const double *b,
+                                                    double *part) {
+    __shared__ double red[kThreads / 64];
+    double acc[1] = {0.0};
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads) {
+        const double d = a[i] - b[i];
+        acc[0] += d * d;
+    }
+    write_partials<1>(acc, red, part);
+}
+
+__global__ __launch_bounds__(kThreads) void k_absmax(int64_t len, const double *a, double *part) {
+    __shared__ double red[kThreads / 64];
+    double acc[1] = {0.0};
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads)
+        acc[0] = nan_max(acc[0], fabs(a[i]));
+    write_partials<1, 1u>(acc, red, part);
+}
+
+// Final pass of a reduction: out[i] = sum or max over the grid of part[g*nv + i].
+__global__ __launch_bounds__(kThreads) void k_sum_max(const double *part, int grid, int nv,
+                                                      unsigned maxmask, double *out) {
+    __shared__ double red[8 * (kThreads / 64)];
+    double v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = 0.0;
+    for (int g = threadIdx.x; g < grid; g += kThreads) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            if (i < nv) {
+                const double p = part[g * nv + i];
+                v[i] = ((maxmask >> i) & 1u) ? nan_max(v[i], p) : v[i] + p;
+            }
+        }
+    }
+    // generic mask: reduce as sums and maxes separately
+    double s[8], mx[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        s[i] = ((maxmask >> i) & 1u) ? 0.0 : v[i];
+        mx[i] = ((maxmask >> i) & 1u) ? v[i] : 0.0;
+    }
+    block_reduce<8, 0u>(s, red);
+    block_reduce<8, 0xFFu>(mx, red);
+    if (threadIdx.x == 0)
+        for (int i = 0; i < nv; ++i) out[i] = ((maxmask >> i) & 1u) ? mx[i] : s[i];
+}
+
+// -------------------------------------------------------- preconditioning
+
+// Row norms of a CSR matrix, one lane per row, in column order (infinity
+// norm for Ruiz, 1-norm for Pock-Chambolle with alpha = 1).
+__global__ __launch_bounds__(kThreads) void k_row_norms(DCsr A, int use_inf, double *out) {
+    for (int r = blockIdx.x * kThreads + threadIdx.x; r < A.rows; r += gridDim.x * kThreads) {
+        double s = 0.0;
+        for (int e = A.row_ptr[r]; e < A.row_ptr[r + 1]; ++e) {
+            const double a = fabs(A.val[e]);
+            if (use_inf) {
+                if (a > s) s = a;
+            } else {
+                s += a;
+            }
+        }
+        out[r] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_norm_to_factor(int len, double *nrm) {
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < len; i += gridDim.x * kThreads)
+        nrm[i] = nrm[i] > 0.0 ? sqrt(nrm[i]) : 1.0;
+}
+
+// a_ij <- a_ij / (rf_i * cf_j)
+__global__ __launch_bounds__(kThreads) void k_scale_matrix(DCsr A, const double *rf,
+                                                           const double *cf) {
+    for (int r = blockIdx.x * kThreads + threadIdx.x; r < A.rows; r += gridDim.x * kThreads) {
+        const double f = rf[r];
+        for (int e = A.row_ptr[r]; e < A.row_ptr[r + 1]; ++e) A.val[e] = A.val[e] / (f * cf[A.col[e]]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_div_inplace(int len, double *d, const double *f) {
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < len; i += gridDim.x * kThreads)
+        d[i] = d[i] / f[i];
+}
+
+// c~ = D2 c, (lc~, uc~) = D1 (lc, uc), (lv~, uv~) = D2^-1 (lv, uv); infinities kept.
+__global__ __launch_bounds__(kThreads) void k_scale_vectors(int m, int n, const double *d1,
+                                                            const double *d2, const double *c,
+                                                            const double *lc, const double *uc,
+                                                            const double *lv, const double *uv,
+                                                            double *cs, double *lcs, double *ucs,
+                                                            double *lvs, double *uvs) {
+    const int stride = gridDim.x * kThreads;
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
+        cs[j] = d2[j] * c[j];
+        lvs[j] = isfinite(lv[j]) ? lv[j] / d2[j] : lv[j];
+        uvs[j] = isfinite(uv[j]) ? uv[j] / d2[j] : uv[j];
+    }
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
+        lcs[i] = isfinite(lc[i]) ? d1[i] * lc[i] : lc[i];
+        ucs[i] = isfinite(uc[i]) ? d1[i] * uc[i] : uc[i];
+    }
+}
+
+// ||c||^2 and ||Combine(lc, uc)||^2 (InitializePrimalWeight).
+__global__ __launch_bounds__(kThreads) void k_pw_init(int m, int n, const double *c,
+                                                      const double *lc, const double *uc,
+                                                      double *part) {
+    __shared__ double red[2 * (kThreads / 64)];
+    double acc[2] = {0.0, 0.0};
+    const int stride = gridDim.x * kThreads;
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) acc[0] += c[j] * c[j];
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
+        double v = 0.0;
+        const double a = isfinite(lc[i]) ? fabs(lc[i]) : 0.0;
+        const double b = isfinite(uc[i]) ? fabs(uc[i]) : 0.0;
+        if (a > v) v = a;
+        if (b > v) v = b;
+        acc[1] += v * v;
+    }
+    write_partials<2>(acc, red, part);
+}
+
+// -------------------------------------------------------------- transpose
+
+__global__ __launch_bounds__(kThreads) void k_row_ids(int m, const int32_t *row_ptr,
+                                                      int32_t *rowid) {
+    for (int r = blockIdx.x * kThreads + threadIdx.x; r < m; r += gridDim.x * kThreads)
+        for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) rowid[e] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_iota(int64_t len, int32_t *a) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads)
+        a[i] = (int32_t)i;
+}
+
+// A^T from a stable sort of A's entries by column: row_ptr by lower_bound,
+// col = original row, val gathered.
+__global__ __launch_bounds__(kThreads) void k_transpose_finish(int64_t nnz, int n,
+                                                               const int32_t *sorted_cols,
+                                                               const int32_t *perm,
+                                                               const int32_t *rowid,
+                                                               const double *val,
+                                                               int32_t *t_row_ptr, int32_t *t_col,
+                                                               double *t_val) {
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t j = blockIdx.x * (int64_t)kThreads + threadIdx.x; j <= n; j += stride) {
+        int64_t lo = 0, hi = nnz;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (sorted_cols[mid] < j) lo = mid + 1;
+            else hi = mid;
+        }
+        t_row_ptr[j] = (int32_t)lo;
+    }
+    for (int64_t p = blockIdx.x * (int64_t)kThreads + threadIdx.x; p < nnz; p += stride) {
+        const int32_t q = perm[p];
+        t_col[p] = rowid[q];
+        t_val[p] = val[q];
+    }
+}
+
+// ------------------------------------------------- termination evaluation
+//
+// Section 6, eq. "rescaled-termination-criteria", in original units from a
+// scaled point: x = D2 x~, y = D1 y~, A x = (A~ x~)/D1, A^T y = (A~^T y~)/D2.
+// Values: 0 primal abs (max), 1 primal rel (max), 2 dual abs (max),
+// 3 dual rel (max), 4 c^T x (sum), 5 dual objective terms (sum),
+// 6 non-finite count (sum).
+
+__global__ __launch_bounds__(kThreads) void k_kkt(int m, int n, const double *xs, const double *ys,
+                                                  const double *axs, const double *atys,
+                                                  const double *d1, const double *d2,
+                                                  const double *c, const double *lc,
+                                                  const double *uc, const double *lv,
+                                                  const double *uv, int mode, double *part,
+                                                  double *r_out, double *x_out, double *y_out) {
+    __shared__ double red[7 * (kThreads / 64)];
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int stride = gridDim.x * kThreads;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
+        const double y = d1[i] * ys[i];
+        const double ax = axs[i] / d1[i];
+        if (y_out) y_out[i] = y;
+        const double l = lc[i], u = uc[i];
+        double viol = 0.0;
+        if (isfinite(l) && l - ax > viol) viol = l - ax;
+        if (isfinite(u) && ax - u > viol) viol = ax - u;
+        const bool lb = isfinite(l) && l != 0.0, ub = isfinite(u) && u != 0.0;
+        double q;
+        if (lb && !ub) q = fabs(l);
+        else if (!lb && ub) q = fabs(u);
+        else if (lb && ub) q = fmax(fabs(l), fabs(u));
+        else q = 1.0;
+        acc[0] = nan_max(acc[0], viol);
+        acc[1] = nan_max(acc[1], viol / q);
+        if (ys[i] > 0.0) acc[5] += l * y;
+        else if (ys[i] < 0.0) acc[5] += u * y;
+        if (!isfinite(y) || !isfinite(ax)) acc[6] += 1.0;
+    }
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
+        const double x = d2[j] * xs[j];
+        const double aty = atys[j] / d2[j];
+        if (x_out) x_out[j] = x;
+        const double g = c[j] - aty;
+        const double l = lv[j], u = uv[j];
+        double r;
+        if (mode == 0) {
+            if (!isfinite(l) && !isfinite(u)) r = 0.0;
+            else if (!isfinite(l)) r = g < 0.0 ? g : 0.0;
+            else if (!isfinite(u)) r = g > 0.0 ? g : 0.0;
+            else r = g;
+        } else {
+            r = 0.0;
+            if (g > 0.0 && x - l <= fabs(x)) r = g;
+            if (g < 0.0 && u - x <= fabs(x)) r = g;
+        }
+        if (r_out) r_out[j] = r;
+        const double res = fabs(g - r);
+        const double sc = c[j] != 0.0 ? fabs(c[j]) : 1.0;
+        acc[2] = nan_max(acc[2], res);
+        acc[3] = nan_max(acc[3], res / sc);
+        acc[4] += c[j] * x;
+        if (r > 0.0) acc[5] += l * r;
+        else if (r < 0.0) acc[5] += u * r;
+        if (!isfinite(x) || !isfinite(aty)) acc[6] += 1.0;
+    }
+    write_partials<7, 0x0Fu>(acc, red, part);
+}
+
+__global__ void k_kkt_final(const double *part, int grid, double obj_offset, KktOut *out) {
+    __shared__ double red[7 * (kThreads / 64)];
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int g = threadIdx.x; g < grid; g += kThreads) {
+        for (int i = 0; i < 4; ++i) v[i] = nan_max(v[i], part[g * 7 + i]);
+        for (int i = 4; i < 7; ++i) v[i] += part[g * 7 + i];
+    }
+    block_reduce<7, 0x0Fu>(v, red);
+    if (threadIdx.x == 0) {
+        KktOut o;
+        o.primal_res_abs = v[0];
+        o.primal_res_rel = v[1];
+        o.dual_res_abs = v[2];
+        o.dual_res_rel = v[3];
+        o.primal_obj = v[4] + obj_offset;
+        o.dual_obj = v[5] + obj_offset;
+        const double den = fabs(o.primal_obj) + fabs(o.dual_obj);
+        o.rel_gap = den > 0.0 ? fabs(o.primal_obj - o.dual_obj) / den : 0.0;
+        if (v[6] > 0.0) o.rel_gap = NAN;
+        o.pad = v[6];
+        *out = o;
+    }
+}
+
+// -------------------------------------------------- normalized duality gap
+//
+// mu(z, z_ref) = (1/r) max { L(x, y^) - L(x^, y) : z^ in X x Y, ||z^ - z||_omega <= r },
+// r = ||z - z_ref||_omega (Section 3, "Adaptive restarts").  The maximizer is
+// the point of the proximal path
+//   x^_j(s) = clamp(x_j - s g_j / omega, lv_j, uv_j),  g = c - A^T y,
+//   y^_i(s) = y_i + s omega a_i if > 0; y_i + s omega b_i if < 0; else 0,
+//   a_i = lc_i - (A x)_i,  b_i = uc_i - (A x)_i,
+// at which D(s) = ||z^(s) - z||_omega^2 reaches r^2.  D is piecewise
+// D = A s^2 + B between breakpoints.  The search evaluates D at 32 abscissae
+// per pass (geometric first, then uniform inside the bracket) together with
+// the number of coordinates whose path segment changes between neighbouring
+// abscissae; once the bracket holding r^2 has no segment change, A and B are
+// read off at its midpoint and s* = sqrt((r^2 - B)/A) is exact.
+
+struct CoordX {
+    double x, gw, lv, uv, w;  // gw = g / omega, w = omega
+};
+
+__device__ __forceinline__ double y_path(double y, double s, double omega, bool af, double a,
+                                         bool bf, double b) {
+    if (af) {
+        const double v = y + s * omega * a;
+        if (v > 0.0) return v;
+    }
+    if (bf) {
+        const double v = y + s * omega * b;
+        if (v < 0.0) return v;
+    }
+    return 0.0;
+}
+
+// segment id of a y coordinate on the path: 0 slope a, 1 slope b, 2 at zero
+__device__ __forceinline__ int y_seg(double y, double s, double omega, bool af, double a, bool bf,
+                                     double b) {
+    if (af && y + s * omega * a > 0.0) return 0;
+    if (bf && y + s * omega * b < 0.0) return 1;
+    return 2;
+}
+
+__device__ __forceinline__ int x_seg(double x, double s, double gw, double lv, double uv) {
+    if (gw == 0.0) return 3;
+    const double v = x - s * gw;
+    if (v < lv) return 1;
+    if (v > uv) return 2;
+    return 0;
+}
+
+// setup: 0 r^2, 1 A0 (slope weight at s -> 0+), 2 D(inf), 3 non-finite count
+__global__ __launch_bounds__(kThreads) void k_gap_setup(int m, int n, Vecs v, const double *x,
+                                                        const double *y, const double *ax,
+                                                        const double *aty, const double *xr,
+                                                        const double *yr, double omega,
+                                                        double *part) {
+    __shared__ double red[4 * (kThreads / 64)];
+    double acc[4] = {0, 0, 0, 0};
+    const int stride = gridDim.x * kThreads;
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
+        const double xj = x[j];
+        const double g = v.c[j] - aty[j];
+        const double d = xj - xr[j];
+        acc[0] += omega * d * d;
+        const double lv = v.lv[j], uv = v.uv[j];
+        if (g > 0.0 && xj > lv) acc[1] += g * g / omega;
+        if (g < 0.0 && xj < uv) acc[1] += g * g / omega;
+        if (g > 0.0) {
+            const double e = xj - lv;
+            acc[2] += isfinite(lv) ? omega * e * e : INFINITY;
+        } else if (g < 0.0) {
+            const double e = uv - xj;
+            acc[2] += isfinite(uv) ? omega * e * e : INFINITY;
+        }
+        if (!isfinite(xj) || !isfinite(g)) acc[3] += 1.0;
+    }
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
+        const double yi = y[i];
+        const double d = yi - yr[i];
+        acc[0] += d * d / omega;
+        const bool af = isfinite(v.lc[i]), bf = isfinite(v.uc[i]);
+        const double a = af ? v.lc[i] - ax[i] : -INFINITY;
+        const double b = bf ? v.uc[i] - ax[i] : INFINITY;
+        // initial slope
+        if (yi > 0.0 && af) acc[1] += omega * a * a;
+        else if (yi < 0.0 && bf) acc[1] += omega * b * b;
+        else if (yi == 0.0) {
+            if (af && a > 0.0) acc[1] += omega * a * a;
+            else if (bf && b < 0.0) acc[1] += omega * b * b;
+        }
+        // end of path
+        double fin;
+        const bool up_forever = af && a > 0.0;
+        const bool down_forever = bf && b < 0.0;
+        if (yi > 0.0) {
+            if (up_forever) fin = INFINITY;
+            else if (af && a == 0.0) fin = 0.0;
+            else fin = down_forever ? INFINITY : yi * yi / omega;
+        } else if (yi < 0.0) {
+            if (down_forever) fin = INFINITY;
+            else if (bf && b == 0.0) fin = 0.0;
+            else fin = up_forever ? INFINITY : yi * yi / omega;
+        } else {
+            fin = (up_forever || down_forever) ? INFINITY : 0.0;
+        }
+        acc[2] += fin;
+        if (!isfinite(yi) || !isfinite(ax[i])) acc[3] += 1.0;
+    }
+    write_partials<4>(acc, red, part);
+}
+
+__global__ void k_gap_init(const double *part, int grid, double omega, GapState *gs) {
+    __shared__ double red[4 * (kThreads / 64)];
+    double v[4] = {0, 0, 0, 0};
+    for (int g = threadIdx.x; g < grid; g += kThreads)
+        for (int i = 0; i < 4; ++i) v[i] += part[g * 4 + i];
+    block_reduce<4>(v, red);
+    if (threadIdx.x != 0) return;
+    GapState s;
+    s.r2 = v[0];
+    s.r = sqrt(v[0]);
+    s.omega = omega;
+    s.A0 = v[1];
+    s.Dinf = v[2];
+    s.lo = 0.0;
+    s.hi = INFINITY;
+    s.npass = 0;
+    s.done = 0;
+    s.pathend = 0;
+    s.linear = 0;
+    s.s_star = 0.0;
+    s.Acoef = s.Bcoef = s.f = s.mu = 0.0;
+    s.bad = (v[3] > 0.0 || !isfinite(v[0]) || !isfinite(v[1])) ? 1 : 0;
+    s.pad = 0;
+    if (s.bad) {
+        s.done = 2;
+        s.mu = NAN;
+    } else if (!(s.r2 > 0.0) || !(s.A0 > 0.0)) {
+        s.done = 2;  // mu = 0: zero radius, or nothing on the path moves
+        s.mu = 0.0;
+    } else if (s.Dinf <= s.r2) {
+        s.done = 1;
+        s.pathend = 1;
+        s.s_star = 1e300;
+    } else {
+        const double sg = s.r / sqrt(s.A0);
+        double p = sg;
+        for (int i = 0; i < kGapPts; ++i) {
+            s.pts[i] = p;
+            p *= 4.0;
+        }
+    }
+    *gs = s;
+}
+
+// One multisection pass: D at pts[p] (values 0..31) and the number of
+// coordinates whose segment differs between pts[p] and pts[p+1] (32..62).
+constexpr int kGapNV = 2 * kGapPts - 1;
+
+__global__ __launch_bounds__(kThreads) void k_gap_pass(int m, int n, Vecs v, const double *x,
+                                                       const double *y, const double *ax,
+                                                       const double *aty, const GapState *gs,
+                                                       double *part) {
+    if (gs->done) return;
+    __shared__ double red[kGapNV * (kThreads / 64)];
+    __shared__ double pts[kGapPts];
+    if (threadIdx.x < kGapPts) pts[threadIdx.x] = gs->pts[threadIdx.x];
+    const double omega = gs->omega;
+    __syncthreads();
+    double acc[kGapNV];
+#pragma unroll
+    for (int i = 0; i < kGapNV; ++i) acc[i] = 0.0;
+    const int stride = gridDim.x * kThreads;
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
+        const double xj = x[j];
+        const double gw = (v.c[j] - aty[j]) / omega;
+        const double lv = v.lv[j], uv = v.uv[j];
+        int prev = -1;
+#pragma unroll
+        for (int p = 0; p < kGapPts; ++p) {
+            const double s = pts[p];
+            const double d = clampd(xj - s * gw, lv, uv) - xj;
+            acc[p] += omega * d * d;
+            const int sg = x_seg(xj, s, gw, lv, uv);
+            if (p > 0 && sg != prev) acc[kGapPts + p - 1] += 1.0;
+            prev = sg;
+        }
+    }
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
+        const double yi = y[i];
+        const bool af = isfinite(v.lc[i]), bf = isfinite(v.uc[i]);
+        const double a = af ? v.lc[i] - ax[i] : 0.0;
+        const double b = bf ? v.uc[i] - ax[i] : 0.0;
+        int prev = -1;
+#pragma unroll
+        for (int p = 0; p < kGapPts; ++p) {
+            const double s = pts[p];
+            const double d = y_path(yi, s, omega, af, a, bf, b) - yi;
+            acc[p] += d * d / omega;
+            const int sg = y_seg(yi, s, omega, af, a, bf, b);
+            if (p > 0 && sg != prev) acc[kGapPts + p - 1] += 1.0;
+            prev = sg;
+        }
+    }
+    write_partials<kGapNV>(acc, red, part);
+}
+
+__global__ __launch_bounds__(kThreads) void k_gap_select(const double *part, int grid,
+                                                         GapState *gs) {
+    if (gs->done) return;
+    __shared__ double tot[kGapNV];
+    if (threadIdx.x < kGapNV) {
+        double a = 0.0;
+        for (int g = 0; g < grid; ++g) a += part[g * kGapNV + threadIdx.x];
+        tot[threadIdx.x] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    GapState s = *gs;
+    int q = -1;
+    for (int p = 0; p < kGapPts; ++p)
+        if (tot[p] >= s.r2) {
+            q = p;
+            break;
+        }
+    s.npass += 1;
+    bool refine = true;
+    double count = 1.0;
+    if (q < 0) {
+        // all abscissae inside the ball: continue geometrically (never in linear mode)
+        s.lo = s.pts[kGapPts - 1];
+        double p = s.lo * 4.0;
+        for (int i = 0; i < kGapPts; ++i) {
+            s.pts[i] = p;
+            p *= 4.0;
+        }
+        refine = false;
+    } else if (q == 0) {
+        // bracket (lo, pts[0]] -- its inside has not been counted yet
+        s.hi = s.pts[0];
+        count = 1.0;
+    } else {
+        s.lo = s.pts[q - 1];
+        s.hi = s.pts[q];
+        count = tot[kGapPts + q - 1];
+    }
+    if (refine) {
+        if (count == 0.0) {
+            s.done = 1;
+        } else {
+            const double w = (s.hi - s.lo) / (double)(kGapPts - 1);
+            s.linear = 1;
+            for (int i = 0; i < kGapPts; ++i) s.pts[i] = s.lo + w * (double)i;
+            s.pts[kGapPts - 1] = s.hi;
+            if (!(w > 0.0) || s.pts[1] == s.lo) s.done = 1;  // cannot split further
+        }
+    }
+    if (s.npass >= kGapMaxPass) s.done = 1;
+    *gs = s;
+}
+
+// A and B of D(s) = A s^2 + B at the bracket midpoint.
+__global__ __launch_bounds__(kThreads) void k_gap_classify(int m, int n, Vecs v, const double *x,
+                                                           const double *y, const double *ax,
+                                                           const double *aty, const GapState *gs,
+                                                           double *part) {
+    if (gs->done != 1 || gs->pathend) return;
+    __shared__ double red[2 * (kThreads / 64)];
+    const double omega = gs->omega;
+    const double sm = 0.5 * (gs->lo + gs->hi);
+    double acc[2] = {0.0, 0.0};
+    const int stride = gridDim.x * kThreads;
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
+        const double xj = x[j];
+        const double g = v.c[j] - aty[j];
+        const double gw = g / omega;
+        const double lv = v.lv[j], uv = v.uv[j];
+        const double val = xj - sm * gw;
+        if (g != 0.0 && val > lv && val < uv) {
+            acc[0] += g * g / omega;
+        } else {
+            const double d = clampd(val, lv, uv) - xj;
+            acc[1] += omega * d * d;
+        }
+    }
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
+        const double yi = y[i];
+        const bool af = isfinite(v.lc[i]), bf = isfinite(v.uc[i]);
+        const double a = af ? v.lc[i] - ax[i] : 0.0;
+        const double b = bf ? v.uc[i] - ax[i] : 0.0;
+        const int sg = y_seg(yi, sm, omega, af, a, bf, b);
+        if (sg == 0) acc[0] += omega * a * a;
+        else if (sg == 1) acc[0] += omega * b * b;
+        else acc[1] += yi * yi / omega;
+    }
+    write_partials<2>(acc, red, part);
+}
+
+__global__ void k_gap_solve(const double *part, int grid, GapState *gs) {
+    if (gs->done != 1 || gs->pathend) return;
+    __shared__ double red[2 * (kThreads / 64)];
+    double v[2] = {0.0, 0.0};
+    for (int g = threadIdx.x; g < grid; g += kThreads) {
+        v[0] += part[g * 2];
+        v[1] += part[g * 2 + 1];
+    }
+    block_reduce<2>(v, red);
+    if (threadIdx.x != 0) return;
+    GapState s = *gs;
+    s.Acoef = v[0];
+    s.Bcoef = v[1];
+    double st;
+    if (s.Acoef > 0.0) {
+        st = sqrt((s.r2 - s.Bcoef) / s.Acoef);
+        if (!(st >= s.lo)) st = s.lo;
+        if (st > s.hi) st = s.hi;
+    } else {
+        st = s.lo > 0.0 ? s.lo : 0.5 * (s.lo + s.hi);
+    }
+    s.s_star = st;
+    *gs = s;
+}
+
+// f(z^(s*)) = -g^T (x^ - x) + sum_i [h_i(y^_i) - h_i(y_i)],
+// h_i(v) = v a_i for v > 0, v b_i for v < 0, 0 at 0.
+__global__ __launch_bounds__(kThreads) void k_gap_f(int m, int n, Vecs v, const double *x,
+                                                    const double *y, const double *ax,
+                                                    const double *aty, const GapState *gs,
+                                                    double *part) {
+    if (gs->done != 1) return;
+    __shared__ double red[kThreads / 64];
+    const double omega = gs->omega;
+    const double s = gs->s_star;
+    double acc[1] = {0.0};
+    const int stride = gridDim.x * kThreads;
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
+        const double xj = x[j];
+        const double g = v.c[j] - aty[j];
+        const double xh = clampd(xj - s * (g / omega), v.lv[j], v.uv[j]);
+        acc[0] += -g * (xh - xj);
+    }
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
+        const double yi = y[i];
+        const bool af = isfinite(v.lc[i]), bf = isfinite(v.uc[i]);
+        const double a = af ? v.lc[i] - ax[i] : 0.0;
+        const double b = bf ? v.uc[i] - ax[i] : 0.0;
+        const double yh = y_path(yi, s, omega, af, a, bf, b);
+        const double h1 = yh > 0.0 ? yh * a : (yh < 0.0 ? yh * b : 0.0);
+        const double h0 = yi > 0.0 ? yi * a : (yi < 0.0 ? yi * b : 0.0);
+        acc[0] += h1 - h0;
+    }
+    write_partials<1>(acc, red, part);
+}
+
+__global__ void k_gap_final(const double *part, int grid, GapState *gs) {
+    if (gs->done != 1) return;
+    __shared__ double red[kThreads / 64];
+    double v[1] = {0.0};
+    for (int g = threadIdx.x; g < grid; g += kThreads) v[0] += part[g];
+    block_reduce<1>(v, red);
+    if (threadIdx.x == 0) {
+        gs->f = v[0];
+        gs->mu = v[0] / gs->r;
+        gs->done = 3;
+    }
+}
+
+// --------------------------------------------------------------- launchers
+
+static inline int grid_for(int64_t len, int cap = 2048) {
+    int64_t g = (len + kThreads - 1) / kThreads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+hipError_t launch_primal(hipStream_t s, int n, Vecs v, Iter it, const Ctrl *ctrl, double *part,
+                         int grid) {
+    hipLaunchKernelGGL(k_primal, dim3(grid), dim3(kThreads), 0, s, n, v, it, ctrl, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_dual(hipStream_t s, const DCsr &A, Vecs v, Iter it, const Ctrl *ctrl,
+                            double *part) {
+    if (A.grid > 0)
+        hipLaunchKernelGGL(k_spmv_dual, dim3(A.grid), dim3(kThreads), 0, s, A, v, it, ctrl, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_step_decide(hipStream_t s, Ctrl *ctrl, const double *part_dual, int gd,
+                              const double *part_ps, int gps, const double *part_pf, int gpf) {
+    hipLaunchKernelGGL(k_step_decide, dim3(1), dim3(kThreads), 0, s, ctrl, part_dual, gd, part_ps,
+                       gps, part_pf, gpf);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_primal(hipStream_t s, const DCsr &AT, Vecs v, Iter it, const Ctrl *ctrl,
+                              double *part) {
+    if (AT.grid > 0)
+        hipLaunchKernelGGL(k_spmv_primal, dim3(AT.grid), dim3(kThreads), 0, s, AT, v, it, ctrl,
+                           part);
+    return hipGetLastError();
+}
+
+hipError_t launch_flush_sy(hipStream_t s, int m, Iter it, Ctrl *ctrl) {
+    if (m > 0) hipLaunchKernelGGL(k_flush_sy, dim3(grid_for(m)), dim3(kThreads), 0, s, m, it, ctrl);
+    hipLaunchKernelGGL(k_clear_pending, dim3(1), dim3(64), 0, s, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_plain(hipStream_t s, const DCsr &A, const double *x, double *out) {
+    if (A.grid > 0)
+        hipLaunchKernelGGL(k_spmv_plain, dim3(A.grid), dim3(kThreads), 0, s, A, x, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_div(hipStream_t s, int64_t len, const double *a, const double *d,
+                            double *out) {
+    if (len > 0) hipLaunchKernelGGL(k_div, dim3(grid_for(len)), dim3(kThreads), 0, s, len, a, d, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_mul(hipStream_t s, int64_t len, const double *a, const double *d,
+                            double *out) {
+    if (len > 0) hipLaunchKernelGGL(k_mul, dim3(grid_for(len)), dim3(kThreads), 0, s, len, a, d, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_average(hipStream_t s, int64_t len, const double *sum, double seta,
+                          double *out) {
+    if (len > 0)
+        hipLaunchKernelGGL(k_average, dim3(grid_for(len)), dim3(kThreads), 0, s, len, sum, seta, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(hipStream_t s, int64_t len, double *a, double v) {
+    if (len > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(len)), dim3(kThreads), 0, s, len, a, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(hipStream_t s, int64_t len, const double *a, double *out) {
+    if (len > 0) hipLaunchKernelGGL(k_copy, dim3(grid_for(len)), dim3(kThreads), 0, s, len, a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_clamp0(hipStream_t s, int n, const double *lv, const double *uv, double *x) {
+    if (n > 0) hipLaunchKernelGGL(k_clamp0, dim3(grid_for(n)), dim3(kThreads), 0, s, n, lv, uv, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_dist2(hipStream_t s, int64_t len, const double *a, const double *b, double *part,
+                        int grid, double *out) {
+    hipLaunchKernelGGL(k_dist2, dim3(grid), dim3(kThreads), 0, s, len, a, b, part);
+    hipLaunchKernelGGL(k_sum_max, dim3(1), dim3(kThreads), 0, s, part, grid, 1, 0u, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_max(hipStream_t s, const double *part, int grid, int nv, const int *is_max,
+                          double *out) {
+    unsigned mask = 0;
+    for (int i = 0; i < nv; ++i)
+        if (is_max[i]) mask |= 1u << i;
+    hipLaunchKernelGGL(k_sum_max, dim3(1), dim3(kThreads), 0, s, part, grid, nv, mask, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_absmax(hipStream_t s, int64_t len, const double *a, double *part, int grid,
+                         double *out) {
+    hipLaunchKernelGGL(k_absmax, dim3(grid), dim3(kThreads), 0, s, len, a, part);
+    hipLaunchKernelGGL(k_sum_max, dim3(1), dim3(kThreads), 0, s, part, grid, 1, 1u, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_primal_weight_init(hipStream_t s, int m, int n, const double *c,
+                                     const double *lc, const double *uc, double *part, int grid,
+                                     double *out) {
+    hipLaunchKernelGGL(k_pw_init, dim3(grid), dim3(kThreads), 0, s, m, n, c, lc, uc, part);
+    hipLaunchKernelGGL(k_sum_max, dim3(1), dim3(kThreads), 0, s, part, grid, 2, 0u, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_norms(hipStream_t s, const DCsr &A, int use_inf, double *out) {
+    if (A.rows > 0)
+        hipLaunchKernelGGL(k_row_norms, dim3(grid_for(A.rows, 65535)), dim3(kThreads), 0, s, A,
+                           use_inf, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_to_factor(hipStream_t s, int len, double *nrm) {
+    if (len > 0)
+        hipLaunchKernelGGL(k_norm_to_factor, dim3(grid_for(len)), dim3(kThreads), 0, s, len, nrm);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_matrix(hipStream_t s, const DCsr &A, const double *rf, const double *cf) {
+    if (A.rows > 0)
+        hipLaunchKernelGGL(k_scale_matrix, dim3(grid_for(A.rows, 65535)), dim3(kThreads), 0, s, A,
+                           rf, cf);
+    return hipGetLastError();
+}
+
+hipError_t launch_div_inplace(hipStream_t s, int len, double *d, const double *f) {
+    if (len > 0)
+        hipLaunchKernelGGL(k_div_inplace, dim3(grid_for(len)), dim3(kThreads), 0, s, len, d, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_vectors(hipStream_t s, int m, int n, const double *d1, const double *d2,
+                                const double *c, const double *lc, const double *uc,
+                                const double *lv, const double *uv, double *cs, double *lcs,
+                                double *ucs, double *lvs, double *uvs) {
+    hipLaunchKernelGGL(k_scale_vectors, dim3(grid_for(m > n ? m : n)), dim3(kThreads), 0, s, m, n,
+                       d1, d2, c, lc, uc, lv, uv, cs, lcs, ucs, lvs, uvs);
+    return hipGetLastError();
+}
+
+hipError_t launch_row_ids(hipStream_t s, int m, const int32_t *row_ptr, int32_t *rowid) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_row_ids, dim3(grid_for(m, 65535)), dim3(kThreads), 0, s, m, row_ptr,
+                           rowid);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(hipStream_t s, int64_t len, int32_t *a) {
+    if (len > 0) hipLaunchKernelGGL(k_iota, dim3(grid_for(len)), dim3(kThreads), 0, s, len, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_finish(hipStream_t s, int64_t nnz, int n, const int32_t *sorted_cols,
+                                   const int32_t *perm, const int32_t *rowid, const double *val,
+                                   int32_t *t_row_ptr, int32_t *t_col, double *t_val) {
+    const int64_t len = nnz > (int64_t)n + 1 ? nnz : (int64_t)n + 1;
+    hipLaunchKernelGGL(k_transpose_finish, dim3(grid_for(len, 65535)), dim3(kThreads), 0, s, nnz,
+                       n, sorted_cols, perm, rowid, val, t_row_ptr, t_col, t_val);
+    return hipGetLastError();
+}
+
+hipError_t launch_kkt(hipStream_t s, int m, int n, const double *xs, const double *ys,
+                      const double *axs, const double *atys, const double *d1, const double *d2,
+                      const double *c, const double *lc, const double *uc, const double *lv,
+                      const double *uv, int mode, double obj_offset, double *part, int grid,
+                      double *r_out, double *x_out, double *y_out, KktOut *out) {
+    hipLaunchKernelGGL(k_kkt, dim3(grid), dim3(kThreads), 0, s, m, n, xs, ys, axs, atys, d1, d2, c,
+                       lc, uc, lv, uv, mode, part, r_out, x_out, y_out);
+    hipLaunchKernelGGL(k_kkt_final, dim3(1), dim3(kThreads), 0, s, part, grid, obj_offset, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gap(hipStream_t s, int m, int n, Vecs v, const double *x, const double *y,
+                      const double *ax, const double *aty, const double *xr, const double *yr,
+                      double omega, double *part, int grid, GapState *gs) {
+    hipLaunchKernelGGL(k_gap_setup, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty, xr,
+                       yr, omega, part);
+    hipLaunchKernelGGL(k_gap_init, dim3(1), dim3(kThreads), 0, s, part, grid, omega, gs);
+    for (int p = 0; p < kGapMaxPass; ++p) {
+        hipLaunchKernelGGL(k_gap_pass, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty,
+                           gs, part);
+        hipLaunchKernelGGL(k_gap_select, dim3(1), dim3(kThreads), 0, s, part, grid, gs);
+    }
+    hipLaunchKernelGGL(k_gap_classify, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty,
+                       gs, part);
+    hipLaunchKernelGGL(k_gap_solve, dim3(1), dim3(kThreads), 0, s, part, grid, gs);
+    hipLaunchKernelGGL(k_gap_f, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty, gs,
+                       part);
+    hipLaunchKernelGGL(k_gap_final, dim3(1), dim3(kThreads), 0, s, part, grid, gs);
+    return hipGetLastError();
+}
+
+}  // namespace pdlp
