@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""PDLP throughput on one MI355X.
+
+Workload: the planted skewed LP with 20,000,000 rows, 25,000,000 columns and
+~125M nonzeros (power-law column degrees capped at 10,000, 5,000 dense rows,
+N(0,1) values, planted optimum), solved with the paper's settings for this
+instance class: relative feasibility 1e-8, relative gap 1e-2, feasibility
+polishing on.  Inputs are generated on the host, uploaded, transposed and
+preconditioned before the timed region (reported as setup).
+
+A step is one iteration block of the solver: 64 accepted PDHG iterations
+(Algorithm 2 attempts, rejections included) followed by the periodic check
+(average, two normalized duality gaps, termination test on the restart
+candidate, restart decision with the primal-weight update), plus any
+feasibility polishing that falls due.  value = accepted PDHG iterations
+(main + polishing) per second.
+
+The roofline object reports the dominant kernel, timed live with HIP events
+on the library's stream over the timed region, against its algorithmic
+bytes.  The CPU baseline times the FP64 oracle on a bounded sample of the
+same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PDHG iters/s + SpMV HBM GB/s at 125M nnz; batched LPs/s; bwd/fwd time at KKT tol"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(m, n, nnz):
+    """Bytes each fused kernel must move at least once per launch (FP64 values, int32 indices).
+
+    A x' + dual step, per row: row_ptr 4, y/Ax/lc/uc reads 32, A x'/y' writes 16,
+    dual-average read-modify-write 16 -> 68; per nonzero val+col 12; x' read once 8 n.
+    A^T y' + average + next primal step, per column: row_ptr 4, A^T y' write 8, x read 8,
+    primal-average read-modify-write 16, c/lv/uv reads 24, x' write 8 -> 68; per
+    nonzero 12; y' read once 8 m.
+    """
+    dual = 12 * nnz + 68 * m + 8 * n
+    primal = 12 * nnz + 68 * n + 8 * m
+    return dual, primal
+
+
+def cpu_baseline(lp, steps):
+    import oracle
+    t0 = time.perf_counter()
+    s = oracle.Solver(lp, oracle.Params(), scale=False)
+    log(f"oracle initialized in {time.perf_counter() - t0:.1f}s; timing {steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        s.step()
+    dt = time.perf_counter() - t0
+    return {"value": steps / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{steps} adaptive PDHG steps (Algorithm 2, accepted steps incl. any "
+                       f"rejected attempts) of the single-threaded FP64 oracle on the same "
+                       f"{lp.m}x{lp.n} LP (unscaled; restart/termination checks excluded); "
+                       f"{dt:.1f} s")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--m", type=int, default=20_000_000)
+    ap.add_argument("--n", type=int, default=25_000_000)
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import lpgen
+    import paper_2501_07018_amd as pd
+
+    t0 = time.perf_counter()
+    lp = lpgen.skewed_lp(args.m, args.n, verbose=True)
+    st = lp.stats()
+    log(f"generated {st} in {time.perf_counter() - t0:.1f}s")
+
+    prm = pd.pdlp_params_default(eps_feas=1e-8, eps_gap=1e-2, polish=1, profile=1)
+    t0 = time.perf_counter()
+    prob = pd.Problem(lp, prm)
+    state = prob.state(prm)
+    setup_s = time.perf_counter() - t0
+    log(f"problem on the GPU (upload, transpose, scaling, init) in {setup_s:.2f}s")
+
+    step_k = 64
+    for w in range(args.warmup):
+        r = state.solve(step_k)
+        log(f"warmup {w}: k={r['iterations']} gap={r['rel_gap']:.3e} pres={r['primal_res_rel']:.2e}")
+    state.kernel_stats(reset=True)
+    k0 = r["iterations"] if args.warmup else 0
+    polish_iters = 0
+    status = "ITERATION_LIMIT"
+    steps_done = 0
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = state.solve(step_k)
+        polish_iters += r["polish_iters"]
+        steps_done += 1
+        if r["status_name"] != "ITERATION_LIMIT":
+            status = r["status_name"]
+            break
+    elapsed = time.perf_counter() - t0
+    ks = state.kernel_stats()
+    iters = r["iterations"] - k0 + polish_iters
+    log(f"timed {steps_done} steps: {iters} iterations in {elapsed:.3f}s; last: k={r['iterations']} "
+        f"gap={r['rel_gap']:.3e} pres={r['primal_res_rel']:.2e} dres={r['dual_res_rel']:.2e} "
+        f"restarts={r['restarts']} polish_attempts={r['polish_attempts']}")
+    log(f"kernel stats: {ks}")
+
+    m, n, nnz = lp.m, lp.n, lp.nnz
+    b_dual, b_primal = algorithmic_bytes(m, n, nnz)
+    avg_dual = ks["dual_ms"] / max(ks["dual_launches"], 1)
+    avg_primal = ks["primal_ms"] / max(ks["primal_launches"], 1)
+    gbs_dual = b_dual / (avg_dual * 1e-3) / 1e9 if avg_dual > 0 else 0.0
+    gbs_primal = b_primal / (avg_primal * 1e-3) / 1e9 if avg_primal > 0 else 0.0
+    if ks["dual_ms"] >= ks["primal_ms"]:
+        dom = ("k_spmv_dual", gbs_dual, avg_dual, b_dual, ks["dual_launches"])
+    else:
+        dom = ("k_spmv_primal", gbs_primal, avg_primal, b_primal, ks["primal_launches"])
+    pair_gbs = (b_dual + b_primal) / ((avg_dual + avg_primal) * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": iters / elapsed,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": steps_done,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / max(steps_done, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"planted skewed LP {m}x{n}, {nnz} nonzeros (power-law column degrees "
+                         f"capped at 10,000, 5,000 dense rows); eps_feas 1e-8, eps_gap 1e-2, "
+                         f"polishing on; step = 64 accepted PDHG iterations + periodic check"),
+            "m": m, "n": n, "nnz": nnz, "iterations_per_step": step_k,
+            "status_at_end": status, "rel_gap_at_end": r["rel_gap"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dom[0],
+            "achieved": dom[1],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": dom[1] / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_ms": dom[2],
+            "algorithmic_bytes_per_launch": dom[3],
+            "launches": dom[4],
+        },
+        "spmv_pair": {"achieved_gbs": pair_gbs, "frac": pair_gbs / HBM_PEAK_GBS,
+                      "dual_ms": avg_dual, "primal_ms": avg_primal,
+                      "dual_gbs": gbs_dual, "primal_gbs": gbs_primal},
+        "kkt_passes_per_s": iters / elapsed,
+        "setup_s": setup_s,
+        "check_ms_per_step": ks["check_ms"] / max(steps_done, 1),
+    }
+    if not args.no_cpu_baseline:
+        try:
+            out["cpu_baseline"] = cpu_baseline(lp, args.cpu_steps)
+        except Exception as e:  # the baseline never blocks the GPU number
+            log(f"cpu baseline failed: {e!r}")
+            out["cpu_baseline"] = None
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

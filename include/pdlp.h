@@ -76,6 +76,9 @@ typedef struct pdlp_params {
     double theta, eps_zero;
     double red_exp, grow_exp;
     int32_t verbose;          /* 1: one line per check on stderr */
+    int32_t profile;          /* 1: time the step kernels with HIP events (pdlp_state_kernel_stats) */
+    int32_t reorder;          /* 1 (default): relabel rows/columns by decreasing length inside the
+                                 library (cache locality of the gathers); results are unaffected */
     int32_t reserved;
 } pdlp_params;
 
@@ -172,6 +175,25 @@ void pdlp_state_destroy(pdlp_state *s);
 /* Run exactly k more accepted steps with the restart checks of Algorithm 1
  * but no termination test or polishing; info may be NULL.  k >= 0. */
 int pdlp_iterate_k(pdlp_state *s, int64_t k, pdlp_iter_info *info);
+
+/* Continue the solve of pdlp_solve from the state for at most k more
+ * accepted steps: termination test at every check (and at the start when no
+ * step has been taken yet), feasibility polishing when params->polish.
+ * result as in pdlp_solve (status ITERATION_LIMIT when k steps passed
+ * without termination); its x, y, r buffers may be NULL. */
+int pdlp_state_solve(pdlp_state *s, int64_t k, pdlp_result *result);
+
+/* Per-kernel GPU time of the step loop, accumulated while params->profile
+ * is set: HIP events around every launch on the library's stream.  The
+ * "dual" kernel is A x' fused with the dual step, the "primal" kernel A^T y'
+ * fused with the primal average and the next primal step; launches count
+ * the ones that did work.  reset != 0 zeroes the counters after reading. */
+typedef struct pdlp_kernel_stats {
+    int64_t dual_launches, primal_launches, attempts;
+    double dual_ms, primal_ms, decide_ms, standalone_primal_ms;
+    double check_ms;          /* host wall time spent at block boundaries */
+} pdlp_kernel_stats;
+int pdlp_state_kernel_stats(pdlp_state *s, pdlp_kernel_stats *stats, int32_t reset);
 
 /* Copy the state out (get) or in (set); see pdlp_state_blob. */
 int pdlp_state_get(const pdlp_state *s, pdlp_state_blob *blob);

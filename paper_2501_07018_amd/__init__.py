@@ -43,7 +43,8 @@ class Params(C.Structure):
                 ("adaptive_restarts", C.c_int32), ("beta_suff", C.c_double),
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("theta", C.c_double),
                 ("eps_zero", C.c_double), ("red_exp", C.c_double), ("grow_exp", C.c_double),
-                ("verbose", C.c_int32), ("reserved", C.c_int32)]
+                ("verbose", C.c_int32), ("profile", C.c_int32), ("reorder", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -68,6 +69,13 @@ class IterInfo(C.Structure):
                 ("mu_ref", C.c_double), ("mu_c_prev", C.c_double)]
 
 
+class KernelStats(C.Structure):
+    _fields_ = [("dual_launches", C.c_int64), ("primal_launches", C.c_int64),
+                ("attempts", C.c_int64), ("dual_ms", C.c_double), ("primal_ms", C.c_double),
+                ("decide_ms", C.c_double), ("standalone_primal_ms", C.c_double),
+                ("check_ms", C.c_double)]
+
+
 class StateBlob(C.Structure):
     _fields_ = [(k, D) for k in ("x", "y", "ax", "aty", "x0", "y0", "sx", "sy")] + \
                [(k, C.c_double) for k in ("seta", "omega", "eta_hat", "mu_ref", "mu_c_prev",
@@ -81,7 +89,8 @@ _lib = None
 EXPORTS = ("pdlp_problem_create", "pdlp_problem_destroy", "pdlp_problem_dims",
            "pdlp_problem_get_scaled", "pdlp_spmv", "pdlp_params_default", "pdlp_solve",
            "pdlp_state_create", "pdlp_state_destroy", "pdlp_iterate_k", "pdlp_state_get",
-           "pdlp_state_set", "pdlp_norm_gap", "pdlp_last_error")
+           "pdlp_state_set", "pdlp_norm_gap", "pdlp_last_error", "pdlp_state_solve",
+           "pdlp_state_kernel_stats")
 
 
 def lib() -> C.CDLL:
@@ -111,6 +120,8 @@ def lib() -> C.CDLL:
     L.pdlp_state_get.argtypes = [vp, C.POINTER(StateBlob)]
     L.pdlp_state_set.argtypes = [vp, C.POINTER(StateBlob)]
     L.pdlp_norm_gap.argtypes = [vp, D, D, D, D, D, D, C.c_double, D]
+    L.pdlp_state_solve.argtypes = [vp, C.c_int64, C.POINTER(Result)]
+    L.pdlp_state_kernel_stats.argtypes = [vp, C.POINTER(KernelStats), C.c_int32]
     L.pdlp_last_error.argtypes = []
     L.pdlp_last_error.restype = C.c_char_p
     _lib = L
@@ -220,6 +231,25 @@ def pdlp_iterate_k(s, k) -> dict:
     return {f: getattr(info, f) for f, _ in IterInfo._fields_}
 
 
+def pdlp_state_solve(s, k, m=None, n=None, want_solution=False) -> dict:
+    res = Result()
+    arrs = {}
+    if want_solution:
+        arrs = {"x": np.empty(n), "y": np.empty(m), "r": np.empty(n)}
+        res.x, res.y, res.r = _d(arrs["x"]), _d(arrs["y"]), _d(arrs["r"])
+    _check(lib().pdlp_state_solve(s, int(k), C.byref(res)))
+    d = {f: getattr(res, f) for f, _ in Result._fields_ if f not in ("x", "y", "r")}
+    d["status_name"] = STATUS.get(d["status"], str(d["status"]))
+    d.update(arrs)
+    return d
+
+
+def pdlp_state_kernel_stats(s, reset=False) -> dict:
+    st = KernelStats()
+    _check(lib().pdlp_state_kernel_stats(s, C.byref(st), int(bool(reset))))
+    return {f: getattr(st, f) for f, _ in KernelStats._fields_}
+
+
 def pdlp_state_get(s, m, n) -> dict:
     arrs = {k: np.empty(n) for k in ("x", "aty", "x0", "sx")}
     arrs.update({k: np.empty(m) for k in ("y", "ax", "y0", "sy")})
@@ -290,6 +320,12 @@ class State:
 
     def iterate(self, k) -> dict:
         return pdlp_iterate_k(self.s, k)
+
+    def solve(self, k, want_solution=False) -> dict:
+        return pdlp_state_solve(self.s, k, self.prob.m, self.prob.n, want_solution)
+
+    def kernel_stats(self, reset=False) -> dict:
+        return pdlp_state_kernel_stats(self.s, reset)
 
     def get(self) -> dict:
         return pdlp_state_get(self.s, self.prob.m, self.prob.n)

@@ -25,6 +25,11 @@
 #include "pdlp.h"
 #include "pdlp_internal.h"
 
+// Workgroups of the persistent CSR stream kernels (8 per CU on 256 CUs).
+#ifndef PDLP_STREAM_GRID_CAP
+#define PDLP_STREAM_GRID_CAP 2048
+#endif
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -66,6 +71,21 @@ struct Arena {
         ptrs.push_back(p);
         return static_cast<T *>(p);
     }
+#ifdef PDLP_PROBE_UNCACHED_MATRIX
+    // experiment only: uncached matrix arrays, never freed (process lifetime)
+    template <class T>
+    T *dev_uncached(size_t count) {
+        void *p = nullptr;
+        HIPCHECK(hipExtMallocWithFlags(&p, std::max<size_t>(count, 1) * sizeof(T),
+                                       hipDeviceMallocUncached));
+        return static_cast<T *>(p);
+    }
+#else
+    template <class T>
+    T *dev_uncached(size_t count) {
+        return dev<T>(count);
+    }
+#endif
     template <class T>
     T *host(size_t count) {
         void *p = nullptr;
@@ -104,30 +124,53 @@ int red_grid(int64_t len) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
 }
 
-// Row blocks for the CSR stream kernels: consecutive rows whose nonzeros
-// fit the LDS stage (at most kMaxBlockRows rows), or one long row alone.
+// Row blocks of the CSR stream kernels (see DCsr): stream blocks of rows
+// with at most kMedRow nonzeros that fit the LDS stage, wave blocks of up
+// to kWaveRows medium rows, and single long rows.
 std::vector<int32_t> make_blocks(const int32_t *rp, int32_t rows) {
     std::vector<int32_t> blk;
     blk.push_back(0);
     int32_t r = 0;
+    auto L = [&](int32_t i) { return rp[i + 1] - rp[i]; };
     while (r < rows) {
-        const int32_t len = rp[r + 1] - rp[r];
-        if (len > pdlp::kStage) {
+        const int32_t len = L(r);
+        if (len > pdlp::kWaveMax) {
             ++r;
-            blk.push_back(r);
-            continue;
-        }
-        const int32_t start = r;
-        int64_t nz = 0;
-        while (r < rows && r - start < pdlp::kMaxBlockRows) {
-            const int32_t l = rp[r + 1] - rp[r];
-            if (l > pdlp::kStage || nz + l > pdlp::kStage) break;
-            nz += l;
-            ++r;
+        } else if (len > pdlp::kMedRow) {
+            const int32_t start = r;
+            while (r < rows && r - start < pdlp::kWaveRows && L(r) > pdlp::kMedRow &&
+                   L(r) <= pdlp::kWaveMax)
+                ++r;
+        } else {
+            const int32_t start = r;
+            int64_t nz = 0;
+            while (r < rows && r - start < pdlp::kMaxBlockRows) {
+                const int32_t l = L(r);
+                if (l > pdlp::kMedRow || nz + l > pdlp::kStage) break;
+                nz += l;
+                ++r;
+            }
         }
         blk.push_back(r);
     }
     return blk;
+}
+
+// Stable order of indices by decreasing count (counting sort): order[new] = old.
+std::vector<int32_t> order_by_count(const std::vector<int32_t> &cnt, bool reorder) {
+    const int32_t len = (int32_t)cnt.size();
+    std::vector<int32_t> order(len);
+    if (!reorder) {
+        for (int32_t i = 0; i < len; ++i) order[i] = i;
+        return order;
+    }
+    int32_t mx = 0;
+    for (int32_t c : cnt) mx = std::max(mx, c);
+    std::vector<int64_t> start((size_t)mx + 2, 0);
+    for (int32_t c : cnt) start[(size_t)(mx - c) + 1] += 1;
+    for (size_t k = 1; k < start.size(); ++k) start[k] += start[k - 1];
+    for (int32_t i = 0; i < len; ++i) order[start[(size_t)(mx - cnt[i])]++] = i;
+    return order;
 }
 
 }  // namespace
@@ -148,6 +191,9 @@ struct pdlp_problem {
     double obj_offset = 0.0;
     double *red_part = nullptr;  // partials of generic reductions
     int red_cap = 0;
+    // internal row/column labels: row_order[new] = caller's row, col_order likewise;
+    // orig_pos[new entry] = caller's entry index
+    int32_t *row_order = nullptr, *col_order = nullptr, *orig_pos = nullptr;
     double *res_d = nullptr, *res_h = nullptr;  // small reduction results
     pdlp_params scale_params;
 
@@ -196,11 +242,15 @@ void upload_blocks(pdlp_problem *P, DCsr &M, const int32_t *rp_host) {
     M.blk = P->arena.dev<int32_t>(blk.size());
     HIPCHECK(hipMemcpyAsync(M.blk, blk.data(), blk.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, P->stream));
-    M.grid = std::min<int32_t>(M.nblk, 2048);
+    M.grid = std::min<int32_t>(M.nblk, PDLP_STREAM_GRID_CAP);
     HIPCHECK(hipStreamSynchronize(P->stream));
 }
 
-void build_transpose(pdlp_problem *P) {
+// A^T from the caller-order entries: a stable radix sort by new column label
+// keeps, inside every row of A^T, the caller's row order (the summation
+// order of a sequential A^T y); columns of A^T carry the new row labels.
+void build_transpose(pdlp_problem *P, const int32_t *rp0, const int32_t *col0, const double *val0,
+                     const int32_t *new_row, const int32_t *new_col) {
     hipStream_t s = P->stream;
     const int64_t nnz = P->nnz;
     DCsr &T = P->AT;
@@ -208,19 +258,21 @@ void build_transpose(pdlp_problem *P) {
     T.cols = P->m;
     T.nnz = nnz;
     T.row_ptr = P->arena.dev<int32_t>((size_t)P->n + 1);
-    T.col = P->arena.dev<int32_t>(nnz);
-    T.val = P->arena.dev<double>(nnz);
+    T.col = P->arena.dev_uncached<int32_t>(nnz);
+    T.val = P->arena.dev_uncached<double>(nnz);
     if (nnz == 0) {
         HIPCHECK(hipMemsetAsync(T.row_ptr, 0, sizeof(int32_t) * ((size_t)P->n + 1), s));
+        HIPCHECK(hipStreamSynchronize(s));
         return;
     }
     Arena tmp;
     int32_t *rowid = tmp.dev<int32_t>(nnz);
+    uint32_t *keys_in = tmp.dev<uint32_t>(nnz);
     uint32_t *keys_out = tmp.dev<uint32_t>(nnz);
-    const uint32_t *keys_in = reinterpret_cast<const uint32_t *>(P->A.col);
     int32_t *vals_in = tmp.dev<int32_t>(nnz);
     int32_t *vals_out = tmp.dev<int32_t>(nnz);
-    HIPCHECK(pdlp::launch_row_ids(s, P->m, P->A.row_ptr, rowid));
+    HIPCHECK(pdlp::launch_row_ids_mapped(s, P->m, rp0, new_row, rowid));
+    HIPCHECK(pdlp::launch_relabel(s, nnz, col0, new_col, keys_in));
     HIPCHECK(pdlp::launch_iota(s, nnz, vals_in));
     int end_bit = 1;
     while (end_bit < 31 && (1LL << end_bit) <= (long long)P->n) ++end_bit;
@@ -231,9 +283,30 @@ void build_transpose(pdlp_problem *P) {
     HIPCHECK(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in,
                                                 vals_out, (int)nnz, 0, end_bit, s));
     HIPCHECK(pdlp::launch_transpose_finish(s, nnz, P->n, reinterpret_cast<const int32_t *>(keys_out),
-                                           vals_out, rowid, P->A.val,
-                                           T.row_ptr, T.col, T.val));
+                                           vals_out, rowid, val0, T.row_ptr, T.col, T.val));
     HIPCHECK(hipStreamSynchronize(s));
+}
+
+// host vector in caller order -> device vector in internal order (dst[i] = src[perm[i]])
+void upload_perm(pdlp_problem *P, const double *host, int64_t len, const int32_t *perm,
+                 double *dst) {
+    if (len <= 0) return;
+    Arena tmp;
+    double *t = tmp.dev<double>(len);
+    HIPCHECK(hipMemcpyAsync(t, host, sizeof(double) * len, hipMemcpyHostToDevice, P->stream));
+    HIPCHECK(pdlp::launch_gather(P->stream, len, perm, t, dst));
+    HIPCHECK(hipStreamSynchronize(P->stream));
+}
+
+// device vector in internal order -> host vector in caller order (host[perm[i]] = src[i])
+void download_unperm(pdlp_problem *P, const double *src, int64_t len, const int32_t *perm,
+                     double *host) {
+    if (len <= 0 || !host) return;
+    Arena tmp;
+    double *t = tmp.dev<double>(len);
+    HIPCHECK(pdlp::launch_scatter(P->stream, len, perm, src, t));
+    HIPCHECK(hipMemcpyAsync(host, t, sizeof(double) * len, hipMemcpyDeviceToHost, P->stream));
+    HIPCHECK(hipStreamSynchronize(P->stream));
 }
 
 double reduce_result(pdlp_problem *P, int idx = 0) {
@@ -300,6 +373,10 @@ struct Engine {
     // host-side counters of Algorithm 1
     long long n_outer = 0, kkt_passes = 0, restarts_i = 0, restarts_ii = 0, restarts_iii = 0;
     double mu_ref = INFINITY, mu_c_prev = INFINITY;
+    // optional HIP-event timing of the step kernels
+    bool profile = false;
+    std::vector<hipEvent_t> ev;
+    pdlp_kernel_stats kst{};
 
     Engine(pdlp_problem *p, Vecs vv) : P(p), v(vv), m(p->m), n(p->n) {
         for (int b = 0; b < 2; ++b) {
@@ -333,6 +410,9 @@ struct Engine {
         ggrid = red_grid((int64_t)m + n);
         gap_part = arena.dev<double>((size_t)ggrid * (2 * pdlp::kGapPts));
         std::memset(ctrl_h, 0, sizeof(Ctrl));
+    }
+    ~Engine() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     }
 
     hipStream_t s() const { return P->stream; }
@@ -387,11 +467,20 @@ struct Engine {
         mu_c_prev = INFINITY;
     }
 
-    void enqueue_attempt() {
-        HIPCHECK(pdlp::launch_primal(s(), n, v, it, ctrl_d, part_ps, gps));
-        HIPCHECK(pdlp::launch_spmv_dual(s(), P->A, v, it, ctrl_d, part_dual));
-        HIPCHECK(pdlp::launch_step_decide(s(), ctrl_d, part_dual, gd, part_ps, gps, part_pf, gpf));
-        HIPCHECK(pdlp::launch_spmv_primal(s(), P->AT, v, it, ctrl_d, part_pf));
+    // One step attempt: four predicated launches; with profiling each launch
+    // records its own start/stop events (8 per attempt).
+    void enqueue_attempt(hipEvent_t *e) {
+        HIPCHECK(pdlp::launch_primal(s(), n, v, it, ctrl_d, part_ps, gps, e ? e + 0 : nullptr));
+        HIPCHECK(pdlp::launch_spmv_dual(s(), P->A, v, it, ctrl_d, part_dual, e ? e + 2 : nullptr));
+        HIPCHECK(pdlp::launch_step_decide(s(), ctrl_d, part_dual, gd, part_ps, gps, part_pf, gpf,
+                                          e ? e + 4 : nullptr));
+        HIPCHECK(pdlp::launch_spmv_primal(s(), P->AT, v, it, ctrl_d, part_pf, e ? e + 6 : nullptr));
+    }
+
+    float ev_ms(int a, int b) {
+        float t = 0.f;
+        HIPCHECK(hipEventElapsedTime(&t, ev[a], ev[b]));
+        return t;
     }
 
     // Exactly `target` accepted steps (or a numerical error).
@@ -407,8 +496,29 @@ struct Engine {
         for (;;) {
             long long n_att = remaining + remaining / 8 + 1;
             if (n_att > 4096) n_att = 4096;
-            for (long long a = 0; a < n_att; ++a) enqueue_attempt();
+            const long long att0 = c.attempts, acc0 = c.block_acc;
+            if (profile) {
+                while ((long long)ev.size() < 8 * n_att) {
+                    hipEvent_t e;
+                    HIPCHECK(hipEventCreate(&e));
+                    ev.push_back(e);
+                }
+            }
+            for (long long a = 0; a < n_att; ++a) enqueue_attempt(profile ? &ev[8 * a] : nullptr);
             pull();
+            if (profile) {
+                const long long ran = c.attempts - att0;
+                for (long long a = 0; a < ran; ++a) {
+                    const int b = (int)(8 * a);
+                    kst.standalone_primal_ms += ev_ms(b, b + 1);
+                    kst.dual_ms += ev_ms(b + 2, b + 3);
+                    kst.decide_ms += ev_ms(b + 4, b + 5);
+                    kst.primal_ms += ev_ms(b + 6, b + 7);
+                }
+                kst.attempts += ran;
+                kst.dual_launches += ran;
+                kst.primal_launches += c.block_acc - acc0;
+            }
             if (c.stop) break;
             remaining = target - c.block_acc;
         }
@@ -485,15 +595,24 @@ long long next_art(long long k, long long t, double beta, long long cap) {
     return std::min(cap, k + d);
 }
 
+// Buffers of feasibility polishing, created on first use and kept.
+struct PolishBufs {
+    Engine *sub = nullptr;
+    Arena *store = nullptr;
+    double *pol_x = nullptr, *pol_ax = nullptr, *pol_y = nullptr, *pol_aty = nullptr;
+    double *zero_m = nullptr;
+    ~PolishBufs() {
+        delete sub;
+        delete store;
+    }
+};
+
 struct Ctx {
     pdlp_problem *P;
     const pdlp_params *prm;
     double t_start;
     pdlp_result *res;
-    Engine *sub = nullptr;  // polishing engine (lazy)
-    Arena *store = nullptr; // polishing result buffers
-    double *pol_x = nullptr, *pol_ax = nullptr, *pol_y = nullptr, *pol_aty = nullptr;
-    double *zero_m = nullptr;
+    PolishBufs *pb;
 };
 
 int run_loop(Ctx &X, Engine &E, long long max_k, int term_mode, bool allow_polish, RunOut &out);
@@ -507,17 +626,19 @@ bool feasibility_polish(Ctx &X, Engine &E, RunOut &out) {
     const pdlp_params &prm = *X.prm;
     const long long cap = E.ctrl_h->k / 8;
     X.res->polish_attempts += 1;
-    if (!X.sub) {
-        X.store = new Arena();
-        X.pol_x = X.store->dev<double>(P->n);
-        X.pol_aty = X.store->dev<double>(P->n);
-        X.pol_y = X.store->dev<double>(P->m);
-        X.pol_ax = X.store->dev<double>(P->m);
-        X.zero_m = X.store->dev<double>(P->m);
-        HIPCHECK(pdlp::launch_fill(P->stream, P->m, X.zero_m, 0.0));
-        X.sub = new Engine(P, P->scaled());
+    PolishBufs &B = *X.pb;
+    if (!B.sub) {
+        B.store = new Arena();
+        B.pol_x = B.store->dev<double>(P->n);
+        B.pol_aty = B.store->dev<double>(P->n);
+        B.pol_y = B.store->dev<double>(P->m);
+        B.pol_ax = B.store->dev<double>(P->m);
+        B.zero_m = B.store->dev<double>(P->m);
+        HIPCHECK(pdlp::launch_fill(P->stream, P->m, B.zero_m, 0.0));
+        B.sub = new Engine(P, P->scaled());
     }
-    Engine &S = *X.sub;
+    Engine &S = *B.sub;
+    S.profile = false;
     pdlp_params p2 = prm;
     p2.polish = 0;
     p2.reduced_cost_mode = 0;
@@ -527,14 +648,14 @@ bool feasibility_polish(Ctx &X, Engine &E, RunOut &out) {
     // primal feasibility problem
     S.v = Vecs{P->zero_n, P->lcs, P->ucs, P->lvs, P->uvs};
     S.init(E.ctrl_h->omega, E.ctrl_h->eta_hat, prm);
-    S.set_point(E.xb, X.zero_m);
+    S.set_point(E.xb, B.zero_m);
     RunOut o1;
     int rc = run_loop(X2, S, cap, TERM_PRIMAL, false, o1);
     X.res->polish_iters += S.ctrl_h->k;
     E.kkt_passes += S.kkt_passes;
     if (rc == RUN_OK) {
-        HIPCHECK(pdlp::launch_copy(P->stream, P->n, o1.cand.x, X.pol_x));
-        HIPCHECK(pdlp::launch_copy(P->stream, P->m, o1.cand.ax, X.pol_ax));
+        HIPCHECK(pdlp::launch_copy(P->stream, P->n, o1.cand.x, B.pol_x));
+        HIPCHECK(pdlp::launch_copy(P->stream, P->m, o1.cand.ax, B.pol_ax));
         // dual feasibility problem
         S.v = Vecs{P->cs, P->lc0, P->uc0, P->lv0, P->uv0};
         S.init(E.ctrl_h->omega, E.ctrl_h->eta_hat, prm);
@@ -544,11 +665,11 @@ bool feasibility_polish(Ctx &X, Engine &E, RunOut &out) {
         X.res->polish_iters += S.ctrl_h->k;
         E.kkt_passes += S.kkt_passes;
         if (rc == RUN_OK) {
-            HIPCHECK(pdlp::launch_copy(P->stream, P->m, o2.cand.y, X.pol_y));
-            HIPCHECK(pdlp::launch_copy(P->stream, P->n, o2.cand.aty, X.pol_aty));
-            KktOut k = E.kkt(X.pol_x, X.pol_y, X.pol_ax, X.pol_aty, 0);
+            HIPCHECK(pdlp::launch_copy(P->stream, P->m, o2.cand.y, B.pol_y));
+            HIPCHECK(pdlp::launch_copy(P->stream, P->n, o2.cand.aty, B.pol_aty));
+            KktOut k = E.kkt(B.pol_x, B.pol_y, B.pol_ax, B.pol_aty, 0);
             if (term_met(prm, TERM_FULL, k)) {
-                out.cand = Candidate{X.pol_x, X.pol_y, X.pol_ax, X.pol_aty};
+                out.cand = Candidate{B.pol_x, B.pol_y, B.pol_ax, B.pol_aty};
                 out.kkt = k;
                 out.have = true;
                 ok = true;
@@ -571,7 +692,7 @@ int run_loop(Ctx &X, Engine &E, long long max_k, int term_mode, bool allow_polis
     long long next_polish = prm.polish_first > 0 ? prm.polish_first : 100;
     while (allow_polish && next_polish <= C.k) next_polish *= 2;
 
-    if (term_mode != TERM_NONE) {
+    if (term_mode != TERM_NONE && (C.k == 0 || C.k >= max_k)) {
         out.cand = Candidate{E.X(), E.Y(), E.AXc(), E.ATYc()};
         out.kkt = E.kkt(out.cand.x, out.cand.y, out.cand.ax, out.cand.aty, rc_mode);
         out.have = true;
@@ -586,6 +707,11 @@ int run_loop(Ctx &X, Engine &E, long long max_k, int term_mode, bool allow_polis
         if (allow_polish && prm.polish) kb = std::min(kb, next_polish);
         E.run_block(kb - C.k);
         if (C.numerr) return RUN_NUMERR;
+        struct CheckTimer {
+            Engine &e;
+            double t0;
+            ~CheckTimer() { e.kst.check_ms += 1e3 * (now_s() - t0); }
+        } check_timer{E, now_s()};
 
         const bool full = (C.k % prm.check_every) == 0;
         const bool art = (double)C.t >= prm.beta_art * (double)C.k;
@@ -680,6 +806,7 @@ struct pdlp_state {
     pdlp_problem *P = nullptr;
     pdlp_params prm{};
     Engine *E = nullptr;
+    PolishBufs pb;
     ~pdlp_state() { delete E; }
 };
 
@@ -731,8 +858,8 @@ void engine_initialize(pdlp_state *S, const double *x0_host, const double *y0_ho
     double *xs = tmp.dev<double>(P->n), *ys = tmp.dev<double>(P->m);
     if (x0_host && y0_host) {
         // warm start (unscaled) -> x~ = x / D2, y~ = y / D1, then project
-        HIPCHECK(hipMemcpyAsync(xs, x0_host, sizeof(double) * P->n, hipMemcpyHostToDevice, s));
-        HIPCHECK(hipMemcpyAsync(ys, y0_host, sizeof(double) * P->m, hipMemcpyHostToDevice, s));
+        upload_perm(P, x0_host, P->n, P->col_order, xs);
+        upload_perm(P, y0_host, P->m, P->row_order, ys);
         HIPCHECK(pdlp::launch_scale_div(s, P->n, xs, P->d2, xs));
         HIPCHECK(pdlp::launch_scale_div(s, P->m, ys, P->d1, ys));
     } else {
@@ -771,6 +898,7 @@ void pdlp_params_default(pdlp_params *p) {
     p->red_exp = 0.3;
     p->grow_exp = 0.6;
     p->verbose = 0;
+    p->reorder = 1;
 }
 
 int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
@@ -796,52 +924,83 @@ int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
             P->stream = static_cast<hipStream_t>(hip_stream);
             hipStream_t s = P->stream;
             Arena &a = P->arena;
+            // internal labels: rows by decreasing length, columns by decreasing degree
+            std::vector<int32_t> rlen(m), cdeg(n, 0);
+            for (int32_t i = 0; i < m; ++i) rlen[i] = row_ptr[i + 1] - row_ptr[i];
+            for (int64_t e = 0; e < nnz; ++e) cdeg[col[e]] += 1;
+            const std::vector<int32_t> row_order = order_by_count(rlen, prm.reorder != 0);
+            const std::vector<int32_t> col_order = order_by_count(cdeg, prm.reorder != 0);
+            std::vector<int32_t> new_row(m), new_col(n), new_rp((size_t)m + 1);
+            for (int32_t i = 0; i < m; ++i) new_row[row_order[i]] = i;
+            for (int32_t j = 0; j < n; ++j) new_col[col_order[j]] = j;
+            new_rp[0] = 0;
+            for (int32_t i = 0; i < m; ++i) new_rp[i + 1] = new_rp[i] + rlen[row_order[i]];
+            P->row_order = a.dev<int32_t>(m);
+            P->col_order = a.dev<int32_t>(n);
+            P->orig_pos = a.dev<int32_t>(nnz);
+            if (m > 0)
+                HIPCHECK(hipMemcpyAsync(P->row_order, row_order.data(), sizeof(int32_t) * m,
+                                        hipMemcpyHostToDevice, s));
+            HIPCHECK(hipMemcpyAsync(P->col_order, col_order.data(), sizeof(int32_t) * n,
+                                    hipMemcpyHostToDevice, s));
             DCsr &A = P->A;
             A.rows = m;
             A.cols = n;
             A.nnz = nnz;
             A.row_ptr = a.dev<int32_t>((size_t)m + 1);
-            A.col = a.dev<int32_t>(nnz);
-            A.val = a.dev<double>(nnz);
-            HIPCHECK(hipMemcpyAsync(A.row_ptr, row_ptr, sizeof(int32_t) * ((size_t)m + 1),
+            A.col = a.dev_uncached<int32_t>(nnz);
+            A.val = a.dev_uncached<double>(nnz);
+            HIPCHECK(hipMemcpyAsync(A.row_ptr, new_rp.data(), sizeof(int32_t) * ((size_t)m + 1),
                                     hipMemcpyHostToDevice, s));
-            if (nnz > 0) {
-                HIPCHECK(hipMemcpyAsync(A.col, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
-                HIPCHECK(hipMemcpyAsync(A.val, val, sizeof(double) * nnz, hipMemcpyHostToDevice, s));
+            {
+                // caller-order CSR on the device for the relabelling and the transpose
+                Arena tmp;
+                int32_t *rp0 = tmp.dev<int32_t>((size_t)m + 1), *col0 = tmp.dev<int32_t>(nnz);
+                double *val0 = tmp.dev<double>(nnz);
+                int32_t *nr = tmp.dev<int32_t>(m), *nc = tmp.dev<int32_t>(n);
+                HIPCHECK(hipMemcpyAsync(rp0, row_ptr, sizeof(int32_t) * ((size_t)m + 1),
+                                        hipMemcpyHostToDevice, s));
+                if (nnz > 0) {
+                    HIPCHECK(hipMemcpyAsync(col0, col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+                    HIPCHECK(hipMemcpyAsync(val0, val, sizeof(double) * nnz, hipMemcpyHostToDevice, s));
+                }
+                if (m > 0)
+                    HIPCHECK(hipMemcpyAsync(nr, new_row.data(), sizeof(int32_t) * m,
+                                            hipMemcpyHostToDevice, s));
+                HIPCHECK(hipMemcpyAsync(nc, new_col.data(), sizeof(int32_t) * n,
+                                        hipMemcpyHostToDevice, s));
+                HIPCHECK(pdlp::launch_permute_rows(s, m, P->row_order, rp0, col0, val0, nc,
+                                                   A.row_ptr, A.col, A.val, P->orig_pos));
+                build_transpose(P, rp0, col0, val0, nr, nc);
             }
             double **vecs_n[] = {&P->c, &P->lv, &P->uv, &P->cs, &P->lvs, &P->uvs, &P->d2,
                                  &P->zero_n, &P->lv0, &P->uv0};
             for (auto pp : vecs_n) *pp = a.dev<double>(n);
             double **vecs_m[] = {&P->lc, &P->uc, &P->lcs, &P->ucs, &P->d1, &P->lc0, &P->uc0};
             for (auto pp : vecs_m) *pp = a.dev<double>(m);
-            HIPCHECK(hipMemcpyAsync(P->c, c, sizeof(double) * n, hipMemcpyHostToDevice, s));
-            HIPCHECK(hipMemcpyAsync(P->lv, lv, sizeof(double) * n, hipMemcpyHostToDevice, s));
-            HIPCHECK(hipMemcpyAsync(P->uv, uv, sizeof(double) * n, hipMemcpyHostToDevice, s));
-            if (m > 0) {
-                HIPCHECK(hipMemcpyAsync(P->lc, lc, sizeof(double) * m, hipMemcpyHostToDevice, s));
-                HIPCHECK(hipMemcpyAsync(P->uc, uc, sizeof(double) * m, hipMemcpyHostToDevice, s));
-            }
+            upload_perm(P, c, n, P->col_order, P->c);
+            upload_perm(P, lv, n, P->col_order, P->lv);
+            upload_perm(P, uv, n, P->col_order, P->uv);
+            upload_perm(P, lc, m, P->row_order, P->lc);
+            upload_perm(P, uc, m, P->row_order, P->uc);
             // dual-feasibility bounds: every finite bound set to 0 (Algorithm 4)
             {
                 std::vector<double> t((size_t)std::max(m, n));
-                for (int32_t j = 0; j < n; ++j) t[j] = std::isfinite(lv[j]) ? 0.0 : lv[j];
-                HIPCHECK(hipMemcpy(P->lv0, t.data(), sizeof(double) * n, hipMemcpyHostToDevice));
-                for (int32_t j = 0; j < n; ++j) t[j] = std::isfinite(uv[j]) ? 0.0 : uv[j];
-                HIPCHECK(hipMemcpy(P->uv0, t.data(), sizeof(double) * n, hipMemcpyHostToDevice));
-                if (m > 0) {
-                    for (int32_t i = 0; i < m; ++i) t[i] = std::isfinite(lc[i]) ? 0.0 : lc[i];
-                    HIPCHECK(hipMemcpy(P->lc0, t.data(), sizeof(double) * m, hipMemcpyHostToDevice));
-                    for (int32_t i = 0; i < m; ++i) t[i] = std::isfinite(uc[i]) ? 0.0 : uc[i];
-                    HIPCHECK(hipMemcpy(P->uc0, t.data(), sizeof(double) * m, hipMemcpyHostToDevice));
-                }
+                auto zeroed = [&](const double *src, int64_t len, const int32_t *perm, double *dst) {
+                    for (int64_t k = 0; k < len; ++k) t[k] = std::isfinite(src[k]) ? 0.0 : src[k];
+                    upload_perm(P, t.data(), len, perm, dst);
+                };
+                zeroed(lv, n, P->col_order, P->lv0);
+                zeroed(uv, n, P->col_order, P->uv0);
+                zeroed(lc, m, P->row_order, P->lc0);
+                zeroed(uc, m, P->row_order, P->uc0);
             }
             HIPCHECK(pdlp::launch_fill(s, n, P->zero_n, 0.0));
             P->red_cap = 1024 * 8;
             P->red_part = a.dev<double>(P->red_cap);
             P->res_d = a.dev<double>(8);
             P->res_h = a.host<double>(8);
-            build_transpose(P);
-            upload_blocks(P, A, row_ptr);
+            upload_blocks(P, A, new_rp.data());
             {
                 std::vector<int32_t> trp((size_t)n + 1);
                 HIPCHECK(hipMemcpy(trp.data(), P->AT.row_ptr, sizeof(int32_t) * ((size_t)n + 1),
@@ -868,22 +1027,19 @@ int pdlp_problem_dims(const pdlp_problem *p, int32_t *m, int32_t *n, int64_t *nn
     });
 }
 
-int pdlp_problem_get_scaled(const pdlp_problem *p, double *d1, double *d2, double *val, double *c,
+int pdlp_problem_get_scaled(const pdlp_problem *pc, double *d1, double *d2, double *val, double *c,
                             double *lc, double *uc, double *lv, double *uv) {
     return guarded([&] {
+        auto *p = const_cast<pdlp_problem *>(pc);
         if (!p) invalid("problem is NULL");
-        auto get = [&](double *dst, const double *src, int64_t len) {
-            if (dst && len > 0)
-                HIPCHECK(hipMemcpy(dst, src, sizeof(double) * len, hipMemcpyDeviceToHost));
-        };
-        get(d1, p->d1, p->m);
-        get(d2, p->d2, p->n);
-        get(val, p->A.val, p->nnz);
-        get(c, p->cs, p->n);
-        get(lc, p->lcs, p->m);
-        get(uc, p->ucs, p->m);
-        get(lv, p->lvs, p->n);
-        get(uv, p->uvs, p->n);
+        download_unperm(p, p->d1, p->m, p->row_order, d1);
+        download_unperm(p, p->d2, p->n, p->col_order, d2);
+        download_unperm(p, p->cs, p->n, p->col_order, c);
+        download_unperm(p, p->lcs, p->m, p->row_order, lc);
+        download_unperm(p, p->ucs, p->m, p->row_order, uc);
+        download_unperm(p, p->lvs, p->n, p->col_order, lv);
+        download_unperm(p, p->uvs, p->n, p->col_order, uv);
+        download_unperm(p, p->A.val, p->nnz, p->orig_pos, val);
     });
 }
 
@@ -900,8 +1056,9 @@ int pdlp_spmv(const pdlp_problem *pc, int32_t transpose, int32_t scaled, const d
         hipStream_t s = p->stream;
         Arena tmp;
         double *xi = tmp.dev<double>(in_len), *yo = tmp.dev<double>(out_len);
-        if (in_len > 0)
-            HIPCHECK(hipMemcpyAsync(xi, x_host, sizeof(double) * in_len, hipMemcpyHostToDevice, s));
+        const int32_t *pin = transpose ? p->row_order : p->col_order;
+        const int32_t *pout = transpose ? p->col_order : p->row_order;
+        upload_perm(p, x_host, in_len, pin, xi);
         if (!scaled) HIPCHECK(pdlp::launch_scale_div(s, in_len, xi, din, xi));
         hipEvent_t e0, e1;
         HIPCHECK(hipEventCreate(&e0));
@@ -916,9 +1073,7 @@ int pdlp_spmv(const pdlp_problem *pc, int32_t transpose, int32_t scaled, const d
         (void)hipEventDestroy(e1);
         if (ms) *ms = el / repeat;
         if (!scaled) HIPCHECK(pdlp::launch_scale_div(s, out_len, yo, dout, yo));
-        if (out_len > 0)
-            HIPCHECK(hipMemcpyAsync(out_host, yo, sizeof(double) * out_len, hipMemcpyDeviceToHost, s));
-        HIPCHECK(hipStreamSynchronize(s));
+        download_unperm(p, yo, out_len, pout, out_host);
     });
 }
 
@@ -938,8 +1093,7 @@ int pdlp_norm_gap(const pdlp_problem *pc, const double *x, const double *y, cons
         for (int i = 0; i < 6; ++i) {
             const int len = i < 3 ? n : m;
             d[i] = tmp.dev<double>(len);
-            if (len > 0)
-                HIPCHECK(hipMemcpyAsync(d[i], h[i], sizeof(double) * len, hipMemcpyHostToDevice, s));
+            upload_perm(p, h[i], len, i < 3 ? p->col_order : p->row_order, d[i]);
         }
         const int grid = red_grid((int64_t)m + n);
         double *part = tmp.dev<double>((size_t)grid * 2 * pdlp::kGapPts);
@@ -964,6 +1118,7 @@ int pdlp_state_create(pdlp_problem *p, const pdlp_params *params, pdlp_state **o
             if (params) S->prm = *params;
             check_params(S->prm);
             S->E = new Engine(p, p->scaled());
+            S->E->profile = S->prm.profile != 0;
             engine_initialize(S, nullptr, nullptr);
         } catch (...) {
             delete S;
@@ -981,7 +1136,7 @@ int pdlp_iterate_k(pdlp_state *S, int64_t k, pdlp_iter_info *info) {
         Engine &E = *S->E;
         pdlp_result dummy;
         std::memset(&dummy, 0, sizeof dummy);
-        Ctx X{S->P, &S->prm, now_s(), &dummy};
+        Ctx X{S->P, &S->prm, now_s(), &dummy, &S->pb};
         RunOut out;
         const int rc = run_loop(X, E, E.ctrl_h->k + k, TERM_NONE, false, out);
         if (rc == RUN_NUMERR) throw LibError(PDLP_ERR_STATE, "numerical error during iterations");
@@ -1011,18 +1166,15 @@ int pdlp_state_get(const pdlp_state *S, pdlp_state_blob *b) {
         if (!S || !b) invalid("NULL argument");
         Engine &E = *S->E;
         const int m = E.m, n = E.n;
-        auto get = [&](double *dst, const double *src, int len) {
-            if (dst && len > 0)
-                HIPCHECK(hipMemcpy(dst, src, sizeof(double) * len, hipMemcpyDeviceToHost));
-        };
-        get(b->x, E.X(), n);
-        get(b->y, E.Y(), m);
-        get(b->ax, E.AXc(), m);
-        get(b->aty, E.ATYc(), n);
-        get(b->x0, E.x0, n);
-        get(b->y0, E.y0, m);
-        get(b->sx, E.it.sx, n);
-        get(b->sy, E.it.sy, m);
+        pdlp_problem *P = S->P;
+        download_unperm(P, E.X(), n, P->col_order, b->x);
+        download_unperm(P, E.Y(), m, P->row_order, b->y);
+        download_unperm(P, E.AXc(), m, P->row_order, b->ax);
+        download_unperm(P, E.ATYc(), n, P->col_order, b->aty);
+        download_unperm(P, E.x0, n, P->col_order, b->x0);
+        download_unperm(P, E.y0, m, P->row_order, b->y0);
+        download_unperm(P, E.it.sx, n, P->col_order, b->sx);
+        download_unperm(P, E.it.sy, m, P->row_order, b->sy);
         const Ctrl &C = *E.ctrl_h;
         b->seta = C.seta;
         b->omega = C.omega;
@@ -1050,17 +1202,15 @@ int pdlp_state_set(pdlp_state *S, const pdlp_state_blob *b) {
             invalid("state blob arrays must not be NULL");
         Ctrl &C = *E.ctrl_h;
         C.cur = 0;
-        auto put = [&](double *dst, const double *src, int len) {
-            if (len > 0) HIPCHECK(hipMemcpy(dst, src, sizeof(double) * len, hipMemcpyHostToDevice));
-        };
-        put(E.it.X[0], b->x, n);
-        put(E.it.Y[0], b->y, m);
-        put(E.it.AX[0], b->ax, m);
-        put(E.it.ATY[0], b->aty, n);
-        put(E.x0, b->x0, n);
-        put(E.y0, b->y0, m);
-        put(E.it.sx, b->sx, n);
-        put(E.it.sy, b->sy, m);
+        pdlp_problem *P = S->P;
+        upload_perm(P, b->x, n, P->col_order, E.it.X[0]);
+        upload_perm(P, b->y, m, P->row_order, E.it.Y[0]);
+        upload_perm(P, b->ax, m, P->row_order, E.it.AX[0]);
+        upload_perm(P, b->aty, n, P->col_order, E.it.ATY[0]);
+        upload_perm(P, b->x0, n, P->col_order, E.x0);
+        upload_perm(P, b->y0, m, P->row_order, E.y0);
+        upload_perm(P, b->sx, n, P->col_order, E.it.sx);
+        upload_perm(P, b->sy, m, P->row_order, E.it.sy);
         C.seta = b->seta;
         C.omega = b->omega;
         C.eta_hat = b->eta_hat;
@@ -1081,6 +1231,66 @@ int pdlp_state_set(pdlp_state *S, const pdlp_state_blob *b) {
     });
 }
 
+}  // extern "C"
+
+
+namespace {
+
+// Run the solver of pdlp_solve on a state for at most k more accepted steps.
+void state_solve(pdlp_state *S, long long k, pdlp_result *res, double t0, double setup_s) {
+    pdlp_problem *p = S->P;
+    Engine &E = *S->E;
+    double *ux = res->x, *uy = res->y, *ur = res->r;
+    std::memset(res, 0, sizeof(*res));
+    res->x = ux;
+    res->y = uy;
+    res->r = ur;
+    res->seconds_setup = setup_s;
+    Ctx X{p, &S->prm, t0, res, &S->pb};
+    RunOut out;
+    const long long cap = std::min<long long>(S->prm.max_iters, E.ctrl_h->k + k);
+    const int rc = run_loop(X, E, cap, TERM_FULL, S->prm.polish != 0, out);
+    const int rc_mode = rc == RUN_POLISHED ? 0 : effective_rc_mode(S->prm);
+    KktOut kk;
+    if (ux || uy || ur || !out.have || rc == RUN_NUMERR) {
+        if (!out.have || rc == RUN_NUMERR) out.cand = Candidate{E.X(), E.Y(), E.AXc(), E.ATYc()};
+        Arena tmp;
+        double *rx = tmp.dev<double>(p->n), *ry = tmp.dev<double>(p->m), *rr = tmp.dev<double>(p->n);
+        kk = E.kkt(out.cand.x, out.cand.y, out.cand.ax, out.cand.aty, rc_mode, rr, rx, ry);
+        download_unperm(p, rx, p->n, p->col_order, ux);
+        download_unperm(p, ry, p->m, p->row_order, uy);
+        download_unperm(p, rr, p->n, p->col_order, ur);
+    } else {
+        kk = out.kkt;
+    }
+    res->status = rc == RUN_OK || rc == RUN_POLISHED ? PDLP_STATUS_OPTIMAL
+                  : rc == RUN_TIME                   ? PDLP_STATUS_TIME_LIMIT
+                  : rc == RUN_NUMERR                 ? PDLP_STATUS_NUMERICAL_ERROR
+                                                     : PDLP_STATUS_ITERATION_LIMIT;
+    res->polished = rc == RUN_POLISHED;
+    res->iterations = E.ctrl_h->k;
+    res->attempts = E.ctrl_h->attempts;
+    res->kkt_passes = E.kkt_passes;
+    res->restarts_i = E.restarts_i;
+    res->restarts_ii = E.restarts_ii;
+    res->restarts_iii = E.restarts_iii;
+    res->restarts = E.restarts_i + E.restarts_ii + E.restarts_iii;
+    res->primal_obj = kk.primal_obj;
+    res->dual_obj = kk.dual_obj;
+    res->rel_gap = kk.rel_gap;
+    res->primal_res_abs = kk.primal_res_abs;
+    res->primal_res_rel = kk.primal_res_rel;
+    res->dual_res_abs = kk.dual_res_abs;
+    res->dual_res_rel = kk.dual_res_rel;
+    res->omega = E.ctrl_h->omega;
+    res->eta = E.ctrl_h->eta_hat;
+    res->seconds = now_s() - t0;
+}
+
+}  // namespace
+
+extern "C" {
+
 int pdlp_solve(pdlp_problem *p, const pdlp_params *params, const double *x0_host,
                const double *y0_host, pdlp_result *res) {
     return guarded([&] {
@@ -1094,56 +1304,25 @@ int pdlp_solve(pdlp_problem *p, const pdlp_params *params, const double *x0_host
         if (params) S.prm = *params;
         check_params(S.prm);
         S.E = new Engine(p, p->scaled());
+        S.E->profile = S.prm.profile != 0;
         engine_initialize(&S, x0_host, y0_host);
-        double *ux = res->x, *uy = res->y, *ur = res->r;
-        std::memset(res, 0, sizeof(*res));
-        res->x = ux;
-        res->y = uy;
-        res->r = ur;
-        res->seconds_setup = now_s() - t0;
-        Ctx X{p, &S.prm, t0, res};
-        RunOut out;
-        int rc;
-        Engine &E = *S.E;
-        try {
-            rc = run_loop(X, E, S.prm.max_iters, TERM_FULL, S.prm.polish != 0, out);
-        } catch (...) {
-            delete X.sub;
-            delete X.store;
-            throw;
-        }
-        const int rc_mode = rc == RUN_POLISHED ? 0 : effective_rc_mode(S.prm);
-        Arena tmp;
-        double *rx = tmp.dev<double>(p->n), *ry = tmp.dev<double>(p->m), *rr = tmp.dev<double>(p->n);
-        if (!out.have) out.cand = Candidate{E.X(), E.Y(), E.AXc(), E.ATYc()};
-        KktOut k = E.kkt(out.cand.x, out.cand.y, out.cand.ax, out.cand.aty, rc_mode, rr, rx, ry);
-        if (ux) HIPCHECK(hipMemcpy(ux, rx, sizeof(double) * p->n, hipMemcpyDeviceToHost));
-        if (uy && p->m > 0) HIPCHECK(hipMemcpy(uy, ry, sizeof(double) * p->m, hipMemcpyDeviceToHost));
-        if (ur) HIPCHECK(hipMemcpy(ur, rr, sizeof(double) * p->n, hipMemcpyDeviceToHost));
-        res->status = rc == RUN_OK || rc == RUN_POLISHED ? PDLP_STATUS_OPTIMAL
-                      : rc == RUN_TIME                   ? PDLP_STATUS_TIME_LIMIT
-                      : rc == RUN_NUMERR                 ? PDLP_STATUS_NUMERICAL_ERROR
-                                                         : PDLP_STATUS_ITERATION_LIMIT;
-        res->polished = rc == RUN_POLISHED;
-        res->iterations = E.ctrl_h->k;
-        res->attempts = E.ctrl_h->attempts;
-        res->kkt_passes = E.kkt_passes;
-        res->restarts_i = E.restarts_i;
-        res->restarts_ii = E.restarts_ii;
-        res->restarts_iii = E.restarts_iii;
-        res->restarts = E.restarts_i + E.restarts_ii + E.restarts_iii;
-        res->primal_obj = k.primal_obj;
-        res->dual_obj = k.dual_obj;
-        res->rel_gap = k.rel_gap;
-        res->primal_res_abs = k.primal_res_abs;
-        res->primal_res_rel = k.primal_res_rel;
-        res->dual_res_abs = k.dual_res_abs;
-        res->dual_res_rel = k.dual_res_rel;
-        res->omega = E.ctrl_h->omega;
-        res->eta = E.ctrl_h->eta_hat;
-        delete X.sub;
-        delete X.store;
-        res->seconds = now_s() - t0;
+        const long long k = S.prm.max_iters;
+        state_solve(&S, k, res, t0, now_s() - t0);
+    });
+}
+
+int pdlp_state_solve(pdlp_state *S, int64_t k, pdlp_result *res) {
+    return guarded([&] {
+        if (!S || !res || k < 0) invalid("bad state, result or k < 0");
+        state_solve(S, k, res, now_s(), 0.0);
+    });
+}
+
+int pdlp_state_kernel_stats(pdlp_state *S, pdlp_kernel_stats *st, int32_t reset) {
+    return guarded([&] {
+        if (!S || !st) invalid("NULL argument");
+        *st = S->E->kst;
+        if (reset) std::memset(&S->E->kst, 0, sizeof(pdlp_kernel_stats));
     });
 }
 

@@ -9,14 +9,23 @@
 namespace pdlp {
 
 constexpr int kThreads = 256;        // threads per workgroup (4 wave64)
-constexpr int kStage = 2048;         // LDS product stage of the CSR stream kernels (doubles)
+#ifndef PDLP_STAGE
+#define PDLP_STAGE 2048
+#endif
+constexpr int kStage = PDLP_STAGE;   // LDS product stage of the CSR stream kernels (doubles)
 constexpr int kMaxBlockRows = 1024;  // rows per stream block
+constexpr int kMedRow = 64;          // rows longer than this leave the stream path ...
+constexpr int kWaveMax = 1024;       // ... for one wave per row up to this length, then a workgroup
+constexpr int kWaveRows = kThreads / 64;
 constexpr int kGapPts = 32;          // abscissae per multisection pass of the gap search
 constexpr int kGapMaxPass = 24;
 
 // CSR matrix on the device with a row-block partition: block b covers rows
-// [blk[b], blk[b+1]); either its nonzeros fit the LDS stage (stream mode) or
-// it is a single long row (reduced across the whole workgroup).
+// [blk[b], blk[b+1]) and is one of
+//   stream: rows of at most kMedRow nonzeros whose nonzeros fit the LDS stage;
+//   wave:   up to kWaveRows rows of (kMedRow, kWaveMax] nonzeros, one wave each;
+//   long:   a single row of more than kWaveMax nonzeros (whole workgroup).
+// Entries inside a row may appear in any column order.
 struct DCsr {
     int32_t rows = 0, cols = 0;
     int64_t nnz = 0;
@@ -85,15 +94,16 @@ struct KktOut {
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `s` and return hipGetLastError().
 
-// step attempt pieces
+// step attempt pieces; ev (optional) = {start, stop} events recorded by the launch itself
 hipError_t launch_primal(hipStream_t s, int n, Vecs v, Iter it, const Ctrl *ctrl, double *part,
-                         int grid);
+                         int grid, hipEvent_t *ev = nullptr);
 hipError_t launch_spmv_dual(hipStream_t s, const DCsr &A, Vecs v, Iter it, const Ctrl *ctrl,
-                            double *part);
+                            double *part, hipEvent_t *ev = nullptr);
 hipError_t launch_step_decide(hipStream_t s, Ctrl *ctrl, const double *part_dual, int gd,
-                              const double *part_ps, int gps, const double *part_pf, int gpf);
+                              const double *part_ps, int gps, const double *part_pf, int gpf,
+                              hipEvent_t *ev = nullptr);
 hipError_t launch_spmv_primal(hipStream_t s, const DCsr &AT, Vecs v, Iter it, const Ctrl *ctrl,
-                              double *part);
+                              double *part, hipEvent_t *ev = nullptr);
 hipError_t launch_flush_sy(hipStream_t s, int m, Iter it, Ctrl *ctrl);
 
 // plain products and vector helpers
@@ -107,6 +117,11 @@ hipError_t launch_average(hipStream_t s, int64_t len, const double *sum, double 
 hipError_t launch_fill(hipStream_t s, int64_t len, double *a, double v);
 hipError_t launch_clamp0(hipStream_t s, int n, const double *lv, const double *uv, double *x);
 hipError_t launch_copy(hipStream_t s, int64_t len, const double *a, double *out);
+// out[i] = in[perm[i]] (gather) / out[perm[i]] = in[i] (scatter)
+hipError_t launch_gather(hipStream_t s, int64_t len, const int32_t *perm, const double *in,
+                         double *out);
+hipError_t launch_scatter(hipStream_t s, int64_t len, const int32_t *perm, const double *in,
+                          double *out);
 
 // reductions (deterministic): result written to out[0..]
 hipError_t launch_dist2(hipStream_t s, int64_t len, const double *a, const double *b, double *part,
@@ -129,8 +144,21 @@ hipError_t launch_primal_weight_init(hipStream_t s, int m, int n, const double *
                                      const double *lc, const double *uc, double *part, int grid,
                                      double *out);  // out[0] = ||c||^2, out[1] = ||Combine||^2
 
-// transpose
+// transpose and relabelling
 hipError_t launch_row_ids(hipStream_t s, int m, const int32_t *row_ptr, int32_t *rowid);
+// rowid[e] = new_row[r] for the entries e of old row r
+hipError_t launch_row_ids_mapped(hipStream_t s, int m, const int32_t *row_ptr,
+                                 const int32_t *new_row, int32_t *rowid);
+// key[e] = new_col[col[e]]
+hipError_t launch_relabel(hipStream_t s, int64_t nnz, const int32_t *col, const int32_t *new_col,
+                          uint32_t *key);
+// rows of the relabelled matrix: new row r' is old row row_order[r'] with its entries in stored
+// order and columns relabelled; orig_pos[e'] = old entry index
+hipError_t launch_permute_rows(hipStream_t s, int m, const int32_t *row_order,
+                               const int32_t *old_rp, const int32_t *old_col,
+                               const double *old_val, const int32_t *new_col,
+                               const int32_t *new_rp, int32_t *ncol, double *nval,
+                               int32_t *orig_pos);
 hipError_t launch_iota(hipStream_t s, int64_t len, int32_t *a);
 hipError_t launch_transpose_finish(hipStream_t s, int64_t nnz, int n, const int32_t *sorted_cols,
                                    const int32_t *perm, const int32_t *rowid, const double *val,

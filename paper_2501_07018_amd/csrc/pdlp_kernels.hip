@@ -14,6 +14,8 @@
 // final pass in a fixed order.  No floating-point atomics anywhere.
 #include "pdlp_internal.h"
 
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 namespace pdlp {
@@ -91,33 +93,62 @@ __device__ __forceinline__ double dual_case(double yhat, double sigma, double lc
     return 0.0;
 }
 
+// Matrix streams (values, column indices) are read once per product: load
+// them with the non-temporal hint so they do not displace the gathered
+// vector from the caches.
+#ifndef PDLP_NT_STREAM
+#define PDLP_NT_STREAM 1
+#endif
+template <class T>
+__device__ __forceinline__ T stream_load(const T *p) {
+#if PDLP_NT_STREAM
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
+
 // ------------------------------------------------------- CSR stream SpMV
 //
 // Workgroup-per-row-block CSR product.  A short-row block stages its
 // products in LDS with fully coalesced loads of val/col (one gather of x per
-// nonzero), then one lane per row sums its slice in column order -- the
-// same order as a sequential row loop.  A long-row block (single row with
-// more nonzeros than the stage) is reduced across the workgroup.  The grid is
-// persistent: workgroup g handles blocks g, g + grid, ...
+// nonzero), then one lane per row sums its slice in stored order -- the
+// same order as a sequential row loop.  Medium rows get one wave each
+// (lane-strided partial sums, butterfly reduction); a long row is reduced
+// across the workgroup.  The grid is persistent: workgroup g handles blocks
+// g, g + grid, ...
 
 template <int NACC, class Epi>
 __device__ __forceinline__ void stream_spmv(const DCsr &A, const double *__restrict__ x,
                                             const Epi &epi, double (&acc)[NACC], double *prod,
                                             double *red) {
     constexpr int kPer = kStage / kThreads;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     for (int b = blockIdx.x; b < A.nblk; b += gridDim.x) {
         const int r0 = A.blk[b], r1 = A.blk[b + 1];
         const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
         const int len = e1 - e0;
-        if (len <= kStage) {
+        const int len0 = A.row_ptr[r0 + 1] - e0;
+        if (len0 > kMedRow && len0 <= kWaveMax) {
+            // wave block: row r0 + wid
+            const int r = r0 + wid;
+            if (r < r1) {
+                const int a = A.row_ptr[r], z = A.row_ptr[r + 1];
+                double s = 0.0;
+                for (int e = a + lane; e < z; e += 64)
+                    s += stream_load(A.val + e) * x[stream_load(A.col + e)];
+                s = wave_sum(s);
+                if (lane == 0) epi(r, s, acc);
+            }
+        } else if (len <= kStage && len0 <= kMedRow) {
             int ci[kPer];
             double vv[kPer];
 #pragma unroll
             for (int i = 0; i < kPer; ++i) {
                 const int q = i * kThreads + threadIdx.x;
                 if (q < len) {
-                    ci[i] = __builtin_nontemporal_load(A.col + e0 + q);
-                    vv[i] = __builtin_nontemporal_load(A.val + e0 + q);
+                    ci[i] = stream_load(A.col + e0 + q);
+                    vv[i] = stream_load(A.val + e0 + q);
                 } else {
                     ci[i] = 0;
                     vv[i] = 0.0;
@@ -139,7 +170,7 @@ __device__ __forceinline__ void stream_spmv(const DCsr &A, const double *__restr
         } else {
             double s = 0.0;
             for (int e = e0 + threadIdx.x; e < e1; e += kThreads)
-                s += __builtin_nontemporal_load(A.val + e) * x[__builtin_nontemporal_load(A.col + e)];
+                s += stream_load(A.val + e) * x[stream_load(A.col + e)];
             double t[1] = {s};
             block_reduce<1>(t, red);
             if (threadIdx.x == 0) epi(r0, t[0], acc);
@@ -360,6 +391,20 @@ __global__ __launch_bounds__(kThreads) void k_copy(int64_t len, const double *a,
         out[i] = a[i];
 }
 
+__global__ __launch_bounds__(kThreads) void k_gather(int64_t len, const int32_t *perm,
+                                                     const double *in, double *out) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads)
+        out[i] = in[perm[i]];
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(int64_t len, const int32_t *perm,
+                                                      const double *in, double *out) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads)
+        out[perm[i]] = in[i];
+}
+
 __global__ __launch_bounds__(kThreads) void k_clamp0(int n, const double *lv, const double *uv,
                                                      double *x) {
     for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += gridDim.x * kThreads)
@@ -500,6 +545,40 @@ __global__ __launch_bounds__(kThreads) void k_row_ids(int m, const int32_t *row_
         for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) rowid[e] = r;
 }
 
+__global__ __launch_bounds__(kThreads) void k_row_ids_mapped(int m, const int32_t *row_ptr,
+                                                             const int32_t *new_row,
+                                                             int32_t *rowid) {
+    for (int r = blockIdx.x * kThreads + threadIdx.x; r < m; r += gridDim.x * kThreads) {
+        const int32_t nr = new_row[r];
+        for (int e = row_ptr[r]; e < row_ptr[r + 1]; ++e) rowid[e] = nr;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_relabel(int64_t nnz, const int32_t *col,
+                                                      const int32_t *new_col, uint32_t *key) {
+    for (int64_t e = blockIdx.x * (int64_t)kThreads + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * kThreads)
+        key[e] = (uint32_t)new_col[col[e]];
+}
+
+__global__ __launch_bounds__(kThreads) void k_permute_rows(int m, const int32_t *row_order,
+                                                           const int32_t *old_rp,
+                                                           const int32_t *old_col,
+                                                           const double *old_val,
+                                                           const int32_t *new_col,
+                                                           const int32_t *new_rp, int32_t *ncol,
+                                                           double *nval, int32_t *orig_pos) {
+    for (int r = blockIdx.x * kThreads + threadIdx.x; r < m; r += gridDim.x * kThreads) {
+        const int32_t o = row_order[r];
+        const int32_t a = old_rp[o], len = old_rp[o + 1] - a, d = new_rp[r];
+        for (int k = 0; k < len; ++k) {
+            ncol[d + k] = new_col[old_col[a + k]];
+            nval[d + k] = old_val[a + k];
+            orig_pos[d + k] = a + k;
+        }
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_iota(int64_t len, int32_t *a) {
     for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
          i += (int64_t)gridDim.x * kThreads)
@@ -632,47 +711,93 @@ __global__ void k_kkt_final(const double *part, int grid, double obj_offset, Kkt
 //   x^_j(s) = clamp(x_j - s g_j / omega, lv_j, uv_j),  g = c - A^T y,
 //   y^_i(s) = y_i + s omega a_i if > 0; y_i + s omega b_i if < 0; else 0,
 //   a_i = lc_i - (A x)_i,  b_i = uc_i - (A x)_i,
-// at which D(s) = ||z^(s) - z||_omega^2 reaches r^2.  D is piecewise
-// D = A s^2 + B between breakpoints.  The search evaluates D at 32 abscissae
-// per pass (geometric first, then uniform inside the bracket) together with
-// the number of coordinates whose path segment changes between neighbouring
-// abscissae; once the bracket holding r^2 has no segment change, A and B are
-// read off at its midpoint and s* = sqrt((r^2 - B)/A) is exact.
+// at which D(s) = ||z^(s) - z||_omega^2 reaches r^2.
+//
+// Each coordinate's share of D is piecewise with at most two breakpoints,
+//   D_i(s) = a1 s^2 (s < b1),  c (b1 <= s < b2),  a3 s^2 (s >= b2),
+// and its share of the objective is linear on the same pieces,
+//   f_i(s) = f1 s,  f0,  f3 s + f3b.
+// The search evaluates D at 32 abscissae per pass (geometric first, then
+// uniform inside the bracket) together with S(s) = sum of segment indices,
+// whose difference between neighbouring abscissae counts the breakpoints in
+// between.  Once the bracket holding r^2 has none, D = A s^2 + B and
+// f = F1 s + F0 there, so s* = sqrt((r^2 - B)/A) and mu = (F1 s* + F0)/r.
 
-struct CoordX {
-    double x, gw, lv, uv, w;  // gw = g / omega, w = omega
+struct Seg {
+    double b1, b2, a1, c, a3, f1, f0, f3, f3b;
 };
 
-__device__ __forceinline__ double y_path(double y, double s, double omega, bool af, double a,
-                                         bool bf, double b) {
-    if (af) {
-        const double v = y + s * omega * a;
-        if (v > 0.0) return v;
+__device__ __forceinline__ Seg seg_x(double x, double g, double lv, double uv, double omega) {
+    Seg q;
+    q.b2 = INFINITY;
+    q.a3 = 0.0;
+    q.f3 = 0.0;
+    q.f3b = 0.0;
+    if (g == 0.0) {
+        q.b1 = INFINITY;
+        q.a1 = q.c = q.f1 = q.f0 = 0.0;
+        return q;
     }
-    if (bf) {
-        const double v = y + s * omega * b;
-        if (v < 0.0) return v;
+    const double dist = g > 0.0 ? x - lv : uv - x;  // may be +inf
+    q.a1 = g * g / omega;
+    q.f1 = q.a1;
+    q.b1 = omega * dist / fabs(g);
+    q.c = isfinite(dist) ? omega * dist * dist : INFINITY;
+    q.f0 = isfinite(dist) ? fabs(g) * dist : INFINITY;
+    return q;
+}
+
+// y in Y; af/bf: lc/uc finite; a/b: slopes for positive/negative y^.
+__device__ __forceinline__ Seg seg_y(double y, bool af, double a, bool bf, double b, double omega) {
+    Seg q;
+    q.b1 = q.b2 = INFINITY;
+    q.a1 = q.c = q.a3 = q.f1 = q.f0 = q.f3 = q.f3b = 0.0;
+    if (y > 0.0) {
+        if (af && a > 0.0) {          // moves up without end
+            q.a1 = q.f1 = omega * a * a;
+        } else if (af && a == 0.0) {  // static
+        } else {
+            q.a1 = q.f1 = af ? omega * a * a : 0.0;
+            q.b1 = af ? y / (omega * (-a)) : 0.0;  // reaches 0
+            q.c = y * y / omega;
+            q.f0 = af ? -a * y : 0.0;
+            if (bf && b < 0.0) {                   // leaves 0 downwards
+                q.b2 = y / (omega * (-b));
+                q.a3 = q.f3 = omega * b * b;
+                q.f3b = (b - (af ? a : 0.0)) * y;
+            }
+        }
+    } else if (y < 0.0) {
+        if (bf && b < 0.0) {
+            q.a1 = q.f1 = omega * b * b;
+        } else if (bf && b == 0.0) {
+        } else {
+            q.a1 = q.f1 = bf ? omega * b * b : 0.0;
+            q.b1 = bf ? -y / (omega * b) : 0.0;
+            q.c = y * y / omega;
+            q.f0 = bf ? -b * y : 0.0;
+            if (af && a > 0.0) {
+                q.b2 = -y / (omega * a);
+                q.a3 = q.f3 = omega * a * a;
+                q.f3b = (a - (bf ? b : 0.0)) * y;
+            }
+        }
+    } else {
+        if (af && a > 0.0) q.a1 = q.f1 = omega * a * a;
+        else if (bf && b < 0.0) q.a1 = q.f1 = omega * b * b;
     }
-    return 0.0;
+    return q;
 }
 
-// segment id of a y coordinate on the path: 0 slope a, 1 slope b, 2 at zero
-__device__ __forceinline__ int y_seg(double y, double s, double omega, bool af, double a, bool bf,
-                                     double b) {
-    if (af && y + s * omega * a > 0.0) return 0;
-    if (bf && y + s * omega * b < 0.0) return 1;
-    return 2;
+__device__ __forceinline__ Seg coord_seg(int idx, int n, Vecs v, const double *x, const double *y,
+                                         const double *ax, const double *aty, double omega) {
+    if (idx < n) return seg_x(x[idx], v.c[idx] - aty[idx], v.lv[idx], v.uv[idx], omega);
+    const int i = idx - n;
+    const bool af = isfinite(v.lc[i]), bf = isfinite(v.uc[i]);
+    return seg_y(y[i], af, af ? v.lc[i] - ax[i] : 0.0, bf, bf ? v.uc[i] - ax[i] : 0.0, omega);
 }
 
-__device__ __forceinline__ int x_seg(double x, double s, double gw, double lv, double uv) {
-    if (gw == 0.0) return 3;
-    const double v = x - s * gw;
-    if (v < lv) return 1;
-    if (v > uv) return 2;
-    return 0;
-}
-
-// setup: 0 r^2, 1 A0 (slope weight at s -> 0+), 2 D(inf), 3 non-finite count
+// setup: 0 r^2, 1 A0 (weight of coordinates moving at s -> 0+), 2 D(inf), 3 non-finite count
 __global__ __launch_bounds__(kThreads) void k_gap_setup(int m, int n, Vecs v, const double *x,
                                                         const double *y, const double *ax,
                                                         const double *aty, const double *xr,
@@ -680,55 +805,22 @@ __global__ __launch_bounds__(kThreads) void k_gap_setup(int m, int n, Vecs v, co
                                                         double *part) {
     __shared__ double red[4 * (kThreads / 64)];
     double acc[4] = {0, 0, 0, 0};
-    const int stride = gridDim.x * kThreads;
-    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
-        const double xj = x[j];
-        const double g = v.c[j] - aty[j];
-        const double d = xj - xr[j];
-        acc[0] += omega * d * d;
-        const double lv = v.lv[j], uv = v.uv[j];
-        if (g > 0.0 && xj > lv) acc[1] += g * g / omega;
-        if (g < 0.0 && xj < uv) acc[1] += g * g / omega;
-        if (g > 0.0) {
-            const double e = xj - lv;
-            acc[2] += isfinite(lv) ? omega * e * e : INFINITY;
-        } else if (g < 0.0) {
-            const double e = uv - xj;
-            acc[2] += isfinite(uv) ? omega * e * e : INFINITY;
-        }
-        if (!isfinite(xj) || !isfinite(g)) acc[3] += 1.0;
-    }
-    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
-        const double yi = y[i];
-        const double d = yi - yr[i];
-        acc[0] += d * d / omega;
-        const bool af = isfinite(v.lc[i]), bf = isfinite(v.uc[i]);
-        const double a = af ? v.lc[i] - ax[i] : -INFINITY;
-        const double b = bf ? v.uc[i] - ax[i] : INFINITY;
-        // initial slope
-        if (yi > 0.0 && af) acc[1] += omega * a * a;
-        else if (yi < 0.0 && bf) acc[1] += omega * b * b;
-        else if (yi == 0.0) {
-            if (af && a > 0.0) acc[1] += omega * a * a;
-            else if (bf && b < 0.0) acc[1] += omega * b * b;
-        }
-        // end of path
-        double fin;
-        const bool up_forever = af && a > 0.0;
-        const bool down_forever = bf && b < 0.0;
-        if (yi > 0.0) {
-            if (up_forever) fin = INFINITY;
-            else if (af && a == 0.0) fin = 0.0;
-            else fin = down_forever ? INFINITY : yi * yi / omega;
-        } else if (yi < 0.0) {
-            if (down_forever) fin = INFINITY;
-            else if (bf && b == 0.0) fin = 0.0;
-            else fin = up_forever ? INFINITY : yi * yi / omega;
+    const int total = n + m;
+    for (int idx = blockIdx.x * kThreads + threadIdx.x; idx < total; idx += gridDim.x * kThreads) {
+        double d, zi;
+        if (idx < n) {
+            zi = x[idx];
+            d = zi - xr[idx];
+            acc[0] += omega * d * d;
         } else {
-            fin = (up_forever || down_forever) ? INFINITY : 0.0;
+            zi = y[idx - n];
+            d = zi - yr[idx - n];
+            acc[0] += d * d / omega;
         }
-        acc[2] += fin;
-        if (!isfinite(yi) || !isfinite(ax[i])) acc[3] += 1.0;
+        const Seg q = coord_seg(idx, n, v, x, y, ax, aty, omega);
+        if (q.b1 > 0.0) acc[1] += q.a1;
+        acc[2] += isfinite(q.b2) ? INFINITY : (isfinite(q.b1) ? q.c : (q.a1 > 0.0 ? INFINITY : 0.0));
+        if (!isfinite(zi) || !isfinite(q.a1)) acc[3] += 1.0;
     }
     write_partials<4>(acc, red, part);
 }
@@ -763,23 +855,18 @@ __global__ void k_gap_init(const double *part, int grid, double omega, GapState 
         s.done = 2;  // mu = 0: zero radius, or nothing on the path moves
         s.mu = 0.0;
     } else if (s.Dinf <= s.r2) {
-        s.done = 1;
+        s.done = 1;  // the whole path lies inside the ball: evaluate at its end
         s.pathend = 1;
-        s.s_star = 1e300;
     } else {
         const double sg = s.r / sqrt(s.A0);
-        double p = sg;
-        for (int i = 0; i < kGapPts; ++i) {
-            s.pts[i] = p;
-            p *= 4.0;
-        }
+        for (int i = 0; i < kGapPts; ++i) s.pts[i] = sg * exp2(0.5 * i);
     }
     *gs = s;
 }
 
-// One multisection pass: D at pts[p] (values 0..31) and the number of
-// coordinates whose segment differs between pts[p] and pts[p+1] (32..62).
-constexpr int kGapNV = 2 * kGapPts - 1;
+// One multisection pass: D at pts[p] (values 0..31) and S = sum of segment
+// indices at pts[p] (values 32..63).
+constexpr int kGapNV = 2 * kGapPts;
 
 __global__ __launch_bounds__(kThreads) void k_gap_pass(int m, int n, Vecs v, const double *x,
                                                        const double *y, const double *ax,
@@ -787,57 +874,58 @@ __global__ __launch_bounds__(kThreads) void k_gap_pass(int m, int n, Vecs v, con
                                                        double *part) {
     if (gs->done) return;
     __shared__ double red[kGapNV * (kThreads / 64)];
-    __shared__ double pts[kGapPts];
-    if (threadIdx.x < kGapPts) pts[threadIdx.x] = gs->pts[threadIdx.x];
+    __shared__ double pts[kGapPts], pts2[kGapPts];
+    if (threadIdx.x < kGapPts) {
+        const double s = gs->pts[threadIdx.x];
+        pts[threadIdx.x] = s;
+        pts2[threadIdx.x] = s * s;
+    }
     const double omega = gs->omega;
     __syncthreads();
-    double acc[kGapNV];
+    double acc[kGapPts];
+    int cnt[kGapPts];
 #pragma unroll
-    for (int i = 0; i < kGapNV; ++i) acc[i] = 0.0;
-    const int stride = gridDim.x * kThreads;
-    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
-        const double xj = x[j];
-        const double gw = (v.c[j] - aty[j]) / omega;
-        const double lv = v.lv[j], uv = v.uv[j];
-        int prev = -1;
+    for (int i = 0; i < kGapPts; ++i) {
+        acc[i] = 0.0;
+        cnt[i] = 0;
+    }
+    const int total = n + m;
+    for (int idx = blockIdx.x * kThreads + threadIdx.x; idx < total; idx += gridDim.x * kThreads) {
+        const Seg q = coord_seg(idx, n, v, x, y, ax, aty, omega);
 #pragma unroll
         for (int p = 0; p < kGapPts; ++p) {
             const double s = pts[p];
-            const double d = clampd(xj - s * gw, lv, uv) - xj;
-            acc[p] += omega * d * d;
-            const int sg = x_seg(xj, s, gw, lv, uv);
-            if (p > 0 && sg != prev) acc[kGapPts + p - 1] += 1.0;
-            prev = sg;
+            const bool s1 = s >= q.b1, s2 = s >= q.b2;
+            acc[p] += s2 ? q.a3 * pts2[p] : (s1 ? q.c : q.a1 * pts2[p]);
+            cnt[p] += (int)s1 + (int)s2;
         }
     }
-    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
-        const double yi = y[i];
-        const bool af = isfinite(v.lc[i]), bf = isfinite(v.uc[i]);
-        const double a = af ? v.lc[i] - ax[i] : 0.0;
-        const double b = bf ? v.uc[i] - ax[i] : 0.0;
-        int prev = -1;
+    double all[kGapNV];
 #pragma unroll
-        for (int p = 0; p < kGapPts; ++p) {
-            const double s = pts[p];
-            const double d = y_path(yi, s, omega, af, a, bf, b) - yi;
-            acc[p] += d * d / omega;
-            const int sg = y_seg(yi, s, omega, af, a, bf, b);
-            if (p > 0 && sg != prev) acc[kGapPts + p - 1] += 1.0;
-            prev = sg;
-        }
+    for (int i = 0; i < kGapPts; ++i) {
+        all[i] = acc[i];
+        all[kGapPts + i] = (double)cnt[i];
     }
-    write_partials<kGapNV>(acc, red, part);
+    write_partials<kGapNV>(all, red, part);
 }
 
 __global__ __launch_bounds__(kThreads) void k_gap_select(const double *part, int grid,
                                                          GapState *gs) {
     if (gs->done) return;
+    // value i is summed by the four lanes i, i+64, i+128, i+192 (grid slices
+    // g = t/64 mod 4), then combined in a fixed order
+    __shared__ double quarter[4][kGapNV];
     __shared__ double tot[kGapNV];
-    if (threadIdx.x < kGapNV) {
+    {
+        const int i = threadIdx.x % kGapNV, q = threadIdx.x / kGapNV;
         double a = 0.0;
-        for (int g = 0; g < grid; ++g) a += part[g * kGapNV + threadIdx.x];
-        tot[threadIdx.x] = a;
+        for (int g = q; g < grid; g += 4) a += part[g * kGapNV + i];
+        quarter[q][i] = a;
     }
+    __syncthreads();
+    if (threadIdx.x < kGapNV)
+        tot[threadIdx.x] = ((quarter[0][threadIdx.x] + quarter[1][threadIdx.x]) +
+                            quarter[2][threadIdx.x]) + quarter[3][threadIdx.x];
     __syncthreads();
     if (threadIdx.x != 0) return;
     GapState s = *gs;
@@ -853,11 +941,7 @@ __global__ __launch_bounds__(kThreads) void k_gap_select(const double *part, int
     if (q < 0) {
         // all abscissae inside the ball: continue geometrically (never in linear mode)
         s.lo = s.pts[kGapPts - 1];
-        double p = s.lo * 4.0;
-        for (int i = 0; i < kGapPts; ++i) {
-            s.pts[i] = p;
-            p *= 4.0;
-        }
+        for (int i = 0; i < kGapPts; ++i) s.pts[i] = s.lo * exp2(0.5 * (i + 1));
         refine = false;
     } else if (q == 0) {
         // bracket (lo, pts[0]] -- its inside has not been counted yet
@@ -866,7 +950,7 @@ __global__ __launch_bounds__(kThreads) void k_gap_select(const double *part, int
     } else {
         s.lo = s.pts[q - 1];
         s.hi = s.pts[q];
-        count = tot[kGapPts + q - 1];
+        count = tot[kGapPts + q] - tot[kGapPts + q - 1];
     }
     if (refine) {
         if (count == 0.0) {
@@ -883,110 +967,61 @@ __global__ __launch_bounds__(kThreads) void k_gap_select(const double *part, int
     *gs = s;
 }
 
-// A and B of D(s) = A s^2 + B at the bracket midpoint.
+// Coefficients of D = A s^2 + B and f = F1 s + F0 on the final bracket
+// (evaluated at its midpoint, or at the end of the path).
 __global__ __launch_bounds__(kThreads) void k_gap_classify(int m, int n, Vecs v, const double *x,
                                                            const double *y, const double *ax,
                                                            const double *aty, const GapState *gs,
                                                            double *part) {
-    if (gs->done != 1 || gs->pathend) return;
-    __shared__ double red[2 * (kThreads / 64)];
+    if (gs->done != 1) return;
+    __shared__ double red[4 * (kThreads / 64)];
     const double omega = gs->omega;
-    const double sm = 0.5 * (gs->lo + gs->hi);
-    double acc[2] = {0.0, 0.0};
-    const int stride = gridDim.x * kThreads;
-    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
-        const double xj = x[j];
-        const double g = v.c[j] - aty[j];
-        const double gw = g / omega;
-        const double lv = v.lv[j], uv = v.uv[j];
-        const double val = xj - sm * gw;
-        if (g != 0.0 && val > lv && val < uv) {
-            acc[0] += g * g / omega;
+    const double sm = gs->pathend ? 1e300 : 0.5 * (gs->lo + gs->hi);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int total = n + m;
+    for (int idx = blockIdx.x * kThreads + threadIdx.x; idx < total; idx += gridDim.x * kThreads) {
+        const Seg q = coord_seg(idx, n, v, x, y, ax, aty, omega);
+        if (sm >= q.b2) {
+            acc[0] += q.a3;
+            acc[2] += q.f3;
+            acc[3] += q.f3b;
+        } else if (sm >= q.b1) {
+            acc[1] += q.c;
+            acc[3] += q.f0;
         } else {
-            const double d = clampd(val, lv, uv) - xj;
-            acc[1] += omega * d * d;
+            acc[0] += q.a1;
+            acc[2] += q.f1;
         }
     }
-    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
-        const double yi = y[i];
-        const bool af = isfinite(v.lc[i]), bf = isfinite(v.uc[i]);
-        const double a = af ? v.lc[i] - ax[i] : 0.0;
-        const double b = bf ? v.uc[i] - ax[i] : 0.0;
-        const int sg = y_seg(yi, sm, omega, af, a, bf, b);
-        if (sg == 0) acc[0] += omega * a * a;
-        else if (sg == 1) acc[0] += omega * b * b;
-        else acc[1] += yi * yi / omega;
-    }
-    write_partials<2>(acc, red, part);
+    write_partials<4>(acc, red, part);
 }
 
 __global__ void k_gap_solve(const double *part, int grid, GapState *gs) {
-    if (gs->done != 1 || gs->pathend) return;
-    __shared__ double red[2 * (kThreads / 64)];
-    double v[2] = {0.0, 0.0};
-    for (int g = threadIdx.x; g < grid; g += kThreads) {
-        v[0] += part[g * 2];
-        v[1] += part[g * 2 + 1];
-    }
-    block_reduce<2>(v, red);
+    if (gs->done != 1) return;
+    __shared__ double red[4 * (kThreads / 64)];
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int g = threadIdx.x; g < grid; g += kThreads)
+        for (int i = 0; i < 4; ++i) v[i] += part[g * 4 + i];
+    block_reduce<4>(v, red);
     if (threadIdx.x != 0) return;
     GapState s = *gs;
     s.Acoef = v[0];
     s.Bcoef = v[1];
     double st;
-    if (s.Acoef > 0.0) {
+    if (s.pathend) {
+        st = 0.0;  // nothing moves at the end of the path: f = F0
+    } else if (s.Acoef > 0.0) {
         st = sqrt((s.r2 - s.Bcoef) / s.Acoef);
         if (!(st >= s.lo)) st = s.lo;
         if (st > s.hi) st = s.hi;
     } else {
-        st = s.lo > 0.0 ? s.lo : 0.5 * (s.lo + s.hi);
+        st = s.lo;
     }
     s.s_star = st;
+    s.f = v[2] * st + v[3];
+    s.mu = s.f / s.r;
+    s.done = 3;
     *gs = s;
-}
-
-// f(z^(s*)) = -g^T (x^ - x) + sum_i [h_i(y^_i) - h_i(y_i)],
-// h_i(v) = v a_i for v > 0, v b_i for v < 0, 0 at 0.
-__global__ __launch_bounds__(kThreads) void k_gap_f(int m, int n, Vecs v, const double *x,
-                                                    const double *y, const double *ax,
-                                                    const double *aty, const GapState *gs,
-                                                    double *part) {
-    if (gs->done != 1) return;
-    __shared__ double red[kThreads / 64];
-    const double omega = gs->omega;
-    const double s = gs->s_star;
-    double acc[1] = {0.0};
-    const int stride = gridDim.x * kThreads;
-    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
-        const double xj = x[j];
-        const double g = v.c[j] - aty[j];
-        const double xh = clampd(xj - s * (g / omega), v.lv[j], v.uv[j]);
-        acc[0] += -g * (xh - xj);
-    }
-    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
-        const double yi = y[i];
-        const bool af = isfinite(v.lc[i]), bf = isfinite(v.uc[i]);
-        const double a = af ? v.lc[i] - ax[i] : 0.0;
-        const double b = bf ? v.uc[i] - ax[i] : 0.0;
-        const double yh = y_path(yi, s, omega, af, a, bf, b);
-        const double h1 = yh > 0.0 ? yh * a : (yh < 0.0 ? yh * b : 0.0);
-        const double h0 = yi > 0.0 ? yi * a : (yi < 0.0 ? yi * b : 0.0);
-        acc[0] += h1 - h0;
-    }
-    write_partials<1>(acc, red, part);
-}
-
-__global__ void k_gap_final(const double *part, int grid, GapState *gs) {
-    if (gs->done != 1) return;
-    __shared__ double red[kThreads / 64];
-    double v[1] = {0.0};
-    for (int g = threadIdx.x; g < grid; g += kThreads) v[0] += part[g];
-    block_reduce<1>(v, red);
-    if (threadIdx.x == 0) {
-        gs->f = v[0];
-        gs->mu = v[0] / gs->r;
-        gs->done = 3;
-    }
 }
 
 // --------------------------------------------------------------- launchers
@@ -998,31 +1033,39 @@ static inline int grid_for(int64_t len, int cap = 2048) {
     return (int)g;
 }
 
+// With events, the launch records its own start/stop timestamps in the
+// dispatch (no extra packets on the stream), for kernel timing.
+#define PDLP_LAUNCH(kern, grid, ev, s, ...)                                                  \
+    do {                                                                                     \
+        if (ev)                                                                              \
+            hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, (ev)[0], (ev)[1], 0, \
+                                  __VA_ARGS__);                                              \
+        else                                                                                 \
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), 0, s, __VA_ARGS__);         \
+    } while (0)
+
 hipError_t launch_primal(hipStream_t s, int n, Vecs v, Iter it, const Ctrl *ctrl, double *part,
-                         int grid) {
-    hipLaunchKernelGGL(k_primal, dim3(grid), dim3(kThreads), 0, s, n, v, it, ctrl, part);
+                         int grid, hipEvent_t *ev) {
+    PDLP_LAUNCH(k_primal, grid, ev, s, n, v, it, ctrl, part);
     return hipGetLastError();
 }
 
 hipError_t launch_spmv_dual(hipStream_t s, const DCsr &A, Vecs v, Iter it, const Ctrl *ctrl,
-                            double *part) {
-    if (A.grid > 0)
-        hipLaunchKernelGGL(k_spmv_dual, dim3(A.grid), dim3(kThreads), 0, s, A, v, it, ctrl, part);
+                            double *part, hipEvent_t *ev) {
+    if (A.grid > 0) PDLP_LAUNCH(k_spmv_dual, A.grid, ev, s, A, v, it, ctrl, part);
     return hipGetLastError();
 }
 
 hipError_t launch_step_decide(hipStream_t s, Ctrl *ctrl, const double *part_dual, int gd,
-                              const double *part_ps, int gps, const double *part_pf, int gpf) {
-    hipLaunchKernelGGL(k_step_decide, dim3(1), dim3(kThreads), 0, s, ctrl, part_dual, gd, part_ps,
-                       gps, part_pf, gpf);
+                              const double *part_ps, int gps, const double *part_pf, int gpf,
+                              hipEvent_t *ev) {
+    PDLP_LAUNCH(k_step_decide, 1, ev, s, ctrl, part_dual, gd, part_ps, gps, part_pf, gpf);
     return hipGetLastError();
 }
 
 hipError_t launch_spmv_primal(hipStream_t s, const DCsr &AT, Vecs v, Iter it, const Ctrl *ctrl,
-                              double *part) {
-    if (AT.grid > 0)
-        hipLaunchKernelGGL(k_spmv_primal, dim3(AT.grid), dim3(kThreads), 0, s, AT, v, it, ctrl,
-                           part);
+                              double *part, hipEvent_t *ev) {
+    if (AT.grid > 0) PDLP_LAUNCH(k_spmv_primal, AT.grid, ev, s, AT, v, it, ctrl, part);
     return hipGetLastError();
 }
 
@@ -1064,6 +1107,20 @@ hipError_t launch_fill(hipStream_t s, int64_t len, double *a, double v) {
 
 hipError_t launch_copy(hipStream_t s, int64_t len, const double *a, double *out) {
     if (len > 0) hipLaunchKernelGGL(k_copy, dim3(grid_for(len)), dim3(kThreads), 0, s, len, a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(hipStream_t s, int64_t len, const int32_t *perm, const double *in,
+                         double *out) {
+    if (len > 0)
+        hipLaunchKernelGGL(k_gather, dim3(grid_for(len)), dim3(kThreads), 0, s, len, perm, in, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(hipStream_t s, int64_t len, const int32_t *perm, const double *in,
+                          double *out) {
+    if (len > 0)
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(len)), dim3(kThreads), 0, s, len, perm, in, out);
     return hipGetLastError();
 }
 
@@ -1145,6 +1202,34 @@ hipError_t launch_row_ids(hipStream_t s, int m, const int32_t *row_ptr, int32_t 
     return hipGetLastError();
 }
 
+hipError_t launch_row_ids_mapped(hipStream_t s, int m, const int32_t *row_ptr,
+                                 const int32_t *new_row, int32_t *rowid) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_row_ids_mapped, dim3(grid_for(m, 65535)), dim3(kThreads), 0, s, m,
+                           row_ptr, new_row, rowid);
+    return hipGetLastError();
+}
+
+hipError_t launch_relabel(hipStream_t s, int64_t nnz, const int32_t *col, const int32_t *new_col,
+                          uint32_t *key) {
+    if (nnz > 0)
+        hipLaunchKernelGGL(k_relabel, dim3(grid_for(nnz, 65535)), dim3(kThreads), 0, s, nnz, col,
+                           new_col, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_rows(hipStream_t s, int m, const int32_t *row_order,
+                               const int32_t *old_rp, const int32_t *old_col,
+                               const double *old_val, const int32_t *new_col,
+                               const int32_t *new_rp, int32_t *ncol, double *nval,
+                               int32_t *orig_pos) {
+    if (m > 0)
+        hipLaunchKernelGGL(k_permute_rows, dim3(grid_for(m, 65535)), dim3(kThreads), 0, s, m,
+                           row_order, old_rp, old_col, old_val, new_col, new_rp, ncol, nval,
+                           orig_pos);
+    return hipGetLastError();
+}
+
 hipError_t launch_iota(hipStream_t s, int64_t len, int32_t *a) {
     if (len > 0) hipLaunchKernelGGL(k_iota, dim3(grid_for(len)), dim3(kThreads), 0, s, len, a);
     return hipGetLastError();
@@ -1184,9 +1269,6 @@ hipError_t launch_gap(hipStream_t s, int m, int n, Vecs v, const double *x, cons
     hipLaunchKernelGGL(k_gap_classify, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty,
                        gs, part);
     hipLaunchKernelGGL(k_gap_solve, dim3(1), dim3(kThreads), 0, s, part, grid, gs);
-    hipLaunchKernelGGL(k_gap_f, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty, gs,
-                       part);
-    hipLaunchKernelGGL(k_gap_final, dim3(1), dim3(kThreads), 0, s, part, grid, gs);
     return hipGetLastError();
 }
 
