@@ -135,6 +135,11 @@ def main():
     else:
         dom = ("k_spmv_primal", gbs_primal, avg_primal, b_primal, ks["primal_launches"])
     pair_gbs = (b_dual + b_primal) / ((avg_dual + avg_primal) * 1e-3) / 1e9
+    # achievable device rates: streaming copy, and random FP64 gathers from
+    # an array the size of each product's gathered vector
+    rates_n = pd.pdlp_measure_device_rates(2 << 30, n)
+    rates_m = pd.pdlp_measure_device_rates(2 << 30, m)
+    log(f"device rates: {rates_n} (gather domain n), {rates_m} (gather domain m)")
 
     out = {
         "metric": METRIC,
@@ -171,6 +176,16 @@ def main():
         "spmv_pair": {"achieved_gbs": pair_gbs, "frac": pair_gbs / HBM_PEAK_GBS,
                       "dual_ms": avg_dual, "primal_ms": avg_primal,
                       "dual_gbs": gbs_dual, "primal_gbs": gbs_primal},
+        "device_rates": {
+            "copy_gbs": rates_n["copy_gbs"],
+            "random_gather_gps_domain_n": rates_n["gather_gps"],
+            "random_gather_gps_domain_m": rates_m["gather_gps"],
+            "random_gather_gps_l2_resident": rates_n["gather_l2_gps"],
+            "note": ("each nonzero of A x' and A^T y' gathers one FP64 word at a random index; "
+                     "nnz / random_gather_gps bounds a product from below when the gathers miss L2"),
+            "dual_gather_floor_ms": nnz / rates_n["gather_gps"] / 1e6,
+            "primal_gather_floor_ms": nnz / rates_m["gather_gps"] / 1e6,
+        },
         "kkt_passes_per_s": iters / elapsed,
         "setup_s": setup_s,
         "check_ms_per_step": ks["check_ms"] / max(steps_done, 1),

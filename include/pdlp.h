@@ -206,6 +206,18 @@ int pdlp_norm_gap(const pdlp_problem *p, const double *x, const double *y, const
                   const double *aty, const double *xr, const double *yr, double omega,
                   double *mu);
 
+/* Achievable device rates for the roofline of the sparse products, measured
+ * on the library's default stream: a streaming copy of `copy_bytes` bytes
+ * (read + write GB/s) and random FP64 gathers from an array of `gather_len`
+ * doubles (indices from a fixed hash, 125M gathers; G gathers/s).  Allocates
+ * and frees its own buffers. */
+typedef struct pdlp_device_rates {
+    double copy_gbs;          /* bytes read + written per second / 1e9 */
+    double gather_gps;        /* random 8-byte gathers per second / 1e9 */
+    double gather_l2_gps;     /* the same from a 1 MiB array (cache-resident) */
+} pdlp_device_rates;
+int pdlp_measure_device_rates(int64_t copy_bytes, int64_t gather_len, pdlp_device_rates *out);
+
 /* Message for the last error on this thread ("" if none). */
 const char *pdlp_last_error(void);
 

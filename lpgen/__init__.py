@@ -29,6 +29,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import sys
 
 import numpy as np
 import scipy.sparse as sp
@@ -230,7 +231,7 @@ def planted_skewed(m: int, n: int, seed: int, mean_degree: float = 5.0,
     rows[is_dense] = dense_set[rng.integers(0, n_dense, size=nd)]
     del is_dense
     if verbose:
-        print(f"[lpgen] skewed: degrees drawn, nnz0={nnz0} ({time.time()-t0:.1f}s)", flush=True)
+        print(f"[lpgen] skewed: degrees drawn, nnz0={nnz0} ({time.time()-t0:.1f}s)", file=sys.stderr, flush=True)
     key = cols * np.int64(m) + rows
     del rows, cols
     key.sort()
@@ -246,14 +247,14 @@ def planted_skewed(m: int, n: int, seed: int, mean_degree: float = 5.0,
     np.cumsum(np.bincount(cols, minlength=n), out=colptr[1:])
     del cols
     if verbose:
-        print(f"[lpgen] skewed: sorted/deduplicated, nnz={rows.size} ({time.time()-t0:.1f}s)", flush=True)
+        print(f"[lpgen] skewed: sorted/deduplicated, nnz={rows.size} ({time.time()-t0:.1f}s)", file=sys.stderr, flush=True)
     vals = rng.standard_normal(rows.size)
     row_ptr, col, val = _csr_from_csc(m, n, colptr, rows, vals)
     del rows, vals, colptr
     A = sp.csr_matrix((val, col, row_ptr), shape=(m, n))
     x, y, r, c, lc, uc, lv, uv, p = _plant(rng, A, m, n)
     if verbose:
-        print(f"[lpgen] skewed: planted ({time.time()-t0:.1f}s)", flush=True)
+        print(f"[lpgen] skewed: planted ({time.time()-t0:.1f}s)", file=sys.stderr, flush=True)
     return LP(m, n, row_ptr, col, val, c, lc, uc, lv, uv, 0.0, x, y, r, p,
               name or f"planted_skewed_{m}x{n}")
 

@@ -76,6 +76,11 @@ class KernelStats(C.Structure):
                 ("check_ms", C.c_double)]
 
 
+class DeviceRates(C.Structure):
+    _fields_ = [("copy_gbs", C.c_double), ("gather_gps", C.c_double),
+                ("gather_l2_gps", C.c_double)]
+
+
 class StateBlob(C.Structure):
     _fields_ = [(k, D) for k in ("x", "y", "ax", "aty", "x0", "y0", "sx", "sy")] + \
                [(k, C.c_double) for k in ("seta", "omega", "eta_hat", "mu_ref", "mu_c_prev",
@@ -90,7 +95,7 @@ EXPORTS = ("pdlp_problem_create", "pdlp_problem_destroy", "pdlp_problem_dims",
            "pdlp_problem_get_scaled", "pdlp_spmv", "pdlp_params_default", "pdlp_solve",
            "pdlp_state_create", "pdlp_state_destroy", "pdlp_iterate_k", "pdlp_state_get",
            "pdlp_state_set", "pdlp_norm_gap", "pdlp_last_error", "pdlp_state_solve",
-           "pdlp_state_kernel_stats")
+           "pdlp_state_kernel_stats", "pdlp_measure_device_rates")
 
 
 def lib() -> C.CDLL:
@@ -122,6 +127,7 @@ def lib() -> C.CDLL:
     L.pdlp_norm_gap.argtypes = [vp, D, D, D, D, D, D, C.c_double, D]
     L.pdlp_state_solve.argtypes = [vp, C.c_int64, C.POINTER(Result)]
     L.pdlp_state_kernel_stats.argtypes = [vp, C.POINTER(KernelStats), C.c_int32]
+    L.pdlp_measure_device_rates.argtypes = [C.c_int64, C.c_int64, C.POINTER(DeviceRates)]
     L.pdlp_last_error.argtypes = []
     L.pdlp_last_error.restype = C.c_char_p
     _lib = L
@@ -274,6 +280,12 @@ def pdlp_norm_gap(h, x, y, ax, aty, xr, yr, omega) -> float:
     _check(lib().pdlp_norm_gap(h, _d(x), _d(y), _d(ax), _d(aty), _d(xr), _d(yr), float(omega),
                                C.byref(mu)))
     return mu.value
+
+
+def pdlp_measure_device_rates(copy_bytes=2 << 30, gather_len=25_000_000) -> dict:
+    r = DeviceRates()
+    _check(lib().pdlp_measure_device_rates(int(copy_bytes), int(gather_len), C.byref(r)))
+    return {f: getattr(r, f) for f, _ in DeviceRates._fields_}
 
 
 def pdlp_last_error() -> str:

@@ -1318,6 +1318,50 @@ int pdlp_state_solve(pdlp_state *S, int64_t k, pdlp_result *res) {
     });
 }
 
+int pdlp_measure_device_rates(int64_t copy_bytes, int64_t gather_len, pdlp_device_rates *out) {
+    return guarded([&] {
+        if (!out || copy_bytes < (1 << 20) || gather_len < 1 || gather_len > (int64_t)UINT32_MAX)
+            invalid("bad arguments");
+        hipStream_t s = nullptr;
+        Arena tmp;
+        const int64_t len = copy_bytes / 16 * 2;  // doubles, even
+        double *a = tmp.dev<double>(len), *b = tmp.dev<double>(len);
+        HIPCHECK(pdlp::launch_fill(s, len, a, 1.0));
+        const int64_t ng = 125000000;
+        const int grid = 2048;
+        uint32_t *idx = tmp.dev<uint32_t>(ng);
+        double *x = tmp.dev<double>(gather_len), *o = tmp.dev<double>((size_t)grid * kThreads);
+        HIPCHECK(pdlp::launch_fill(s, gather_len, x, 1.0));
+        hipEvent_t e0, e1;
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        auto best_ms = [&](auto &&launch) {
+            float best = 1e30f;
+            for (int rep = 0; rep < 5; ++rep) {
+                HIPCHECK(hipEventRecord(e0, s));
+                HIPCHECK(launch());
+                HIPCHECK(hipEventRecord(e1, s));
+                HIPCHECK(hipEventSynchronize(e1));
+                float t = 0.f;
+                HIPCHECK(hipEventElapsedTime(&t, e0, e1));
+                best = std::min(best, t);
+            }
+            return (double)best;
+        };
+        const double tc = best_ms([&] { return pdlp::launch_rate_copy(s, len, a, b); });
+        out->copy_gbs = 2.0 * len * sizeof(double) / (tc * 1e-3) / 1e9;
+        HIPCHECK(pdlp::launch_rate_idx(s, ng, (uint32_t)gather_len, idx));
+        const double tg = best_ms([&] { return pdlp::launch_rate_gather(s, ng, idx, x, o, grid); });
+        out->gather_gps = ng / (tg * 1e-3) / 1e9;
+        HIPCHECK(pdlp::launch_rate_idx(s, ng, (uint32_t)std::min<int64_t>(gather_len, 131072), idx));
+        const double tl = best_ms([&] { return pdlp::launch_rate_gather(s, ng, idx, x, o, grid); });
+        out->gather_l2_gps = ng / (tl * 1e-3) / 1e9;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCHECK(hipStreamSynchronize(s));
+    });
+}
+
 int pdlp_state_kernel_stats(pdlp_state *S, pdlp_kernel_stats *st, int32_t reset) {
     return guarded([&] {
         if (!S || !st) invalid("NULL argument");

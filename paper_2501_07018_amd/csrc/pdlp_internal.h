@@ -19,6 +19,7 @@ constexpr int kWaveMax = 1024;       // ... for one wave per row up to this leng
 constexpr int kWaveRows = kThreads / 64;
 constexpr int kGapPts = 32;          // abscissae per multisection pass of the gap search
 constexpr int kGapMaxPass = 24;
+constexpr int kGapNewton = 12;       // active-set steps before the multisection fallback
 
 // CSR matrix on the device with a row-block partition: block b covers rows
 // [blk[b], blk[b+1]) and is one of
@@ -81,7 +82,10 @@ struct GapState {
     int npass, done, pathend, linear;
     double s_star, Acoef, Bcoef, f, mu;
     int bad;
-    int pad;
+    int newton;           // 1 while the active-set iteration runs
+    double s_cur, s_prev, D_prev;
+    int nsteps;
+    int pad2;
 };
 
 // Results of the termination evaluation (Section 6).
@@ -175,5 +179,11 @@ hipError_t launch_kkt(hipStream_t s, int m, int n, const double *xs, const doubl
 hipError_t launch_gap(hipStream_t s, int m, int n, Vecs v, const double *x, const double *y,
                       const double *ax, const double *aty, const double *xr, const double *yr,
                       double omega, double *part, int grid, GapState *gs);
+
+// device-rate probes (timed by the caller)
+hipError_t launch_rate_copy(hipStream_t s, int64_t len, const double *a, double *b);
+hipError_t launch_rate_idx(hipStream_t s, int64_t n, uint32_t domain, uint32_t *idx);
+hipError_t launch_rate_gather(hipStream_t s, int64_t n, const uint32_t *idx, const double *x,
+                              double *out, int grid);
 
 }  // namespace pdlp

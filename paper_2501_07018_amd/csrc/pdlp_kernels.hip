@@ -847,7 +847,7 @@ __global__ void k_gap_init(const double *part, int grid, double omega, GapState 
     s.s_star = 0.0;
     s.Acoef = s.Bcoef = s.f = s.mu = 0.0;
     s.bad = (v[3] > 0.0 || !isfinite(v[0]) || !isfinite(v[1])) ? 1 : 0;
-    s.pad = 0;
+
     if (s.bad) {
         s.done = 2;
         s.mu = NAN;
@@ -861,6 +861,105 @@ __global__ void k_gap_init(const double *part, int grid, double omega, GapState 
         const double sg = s.r / sqrt(s.A0);
         for (int i = 0; i < kGapPts; ++i) s.pts[i] = sg * exp2(0.5 * i);
     }
+    // active-set iteration: the first abscissa is the step from s -> 0+
+    s.newton = s.done ? 0 : 1;
+    s.s_prev = 2.2250738585072014e-308;
+    s.D_prev = 0.0;
+    s.s_cur = s.done ? 0.0 : s.r / sqrt(s.A0);
+    s.nsteps = 0;
+    s.pad2 = 0;
+    *gs = s;
+}
+
+// Active-set step: at s = s_cur, D(s), the coefficients A, B of the segment
+// containing s, the objective pieces F1, F0, and the number of coordinates
+// whose segment differs between s_prev and s_cur.
+__global__ __launch_bounds__(kThreads) void k_gap_step(int m, int n, Vecs v, const double *x,
+                                                       const double *y, const double *ax,
+                                                       const double *aty, const GapState *gs,
+                                                       double *part) {
+    if (gs->done || !gs->newton) return;
+    __shared__ double red[6 * (kThreads / 64)];
+    const double omega = gs->omega, sc = gs->s_cur, sp = gs->s_prev;
+    const double sc2 = sc * sc;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const int total = n + m;
+    for (int idx = blockIdx.x * kThreads + threadIdx.x; idx < total; idx += gridDim.x * kThreads) {
+        const Seg q = coord_seg(idx, n, v, x, y, ax, aty, omega);
+        const int gc = (int)(sc >= q.b1) + (int)(sc >= q.b2);
+        const int gp = (int)(sp >= q.b1) + (int)(sp >= q.b2);
+        if (gc == 2) {
+            acc[0] += q.a3 * sc2;
+            acc[1] += q.a3;
+            acc[3] += q.f3;
+            acc[4] += q.f3b;
+        } else if (gc == 1) {
+            acc[0] += q.c;
+            acc[2] += q.c;
+            acc[4] += q.f0;
+        } else {
+            acc[0] += q.a1 * sc2;
+            acc[1] += q.a1;
+            acc[3] += q.f1;
+        }
+        if (gc != gp) acc[5] += 1.0;
+    }
+    write_partials<6>(acc, red, part);
+}
+
+__global__ void k_gap_update(const double *part, int grid, GapState *gs) {
+    if (gs->done || !gs->newton) return;
+    __shared__ double red[6 * (kThreads / 64)];
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    for (int g = threadIdx.x; g < grid; g += kThreads)
+        for (int i = 0; i < 6; ++i) v[i] += part[g * 6 + i];
+    block_reduce<6>(v, red);
+    if (threadIdx.x != 0) return;
+    GapState s = *gs;
+    const double Dk = v[0], A = v[1], B = v[2], F1 = v[3], F0 = v[4], cnt = v[5];
+    const double sc = s.s_cur;
+    if (Dk < s.r2) s.lo = fmax(s.lo, sc);
+    else s.hi = fmin(s.hi, sc);
+    s.nsteps += 1;
+    // root of D = A s^2 + B on the segment holding s_cur
+    double st = A > 0.0 ? sqrt((s.r2 - B) / A) : NAN;
+    const double a = fmin(s.s_prev, sc), b = fmax(s.s_prev, sc);
+    const bool at_root = fabs(st - sc) <= 1e-13 * sc;  // D(s_cur) = r^2 on its own segment
+    if (at_root || (cnt == 0.0 && st >= a * (1.0 - 1e-12) && st <= b * (1.0 + 1e-12))) {
+        // the root of the segment holding s_cur is s_cur itself, or there is no
+        // breakpoint between s_prev and s_cur and the root lies there: exact
+        // up to rounding
+        st = at_root ? sc : fmin(fmax(st, a), b);
+        s.s_star = st;
+        s.Acoef = A;
+        s.Bcoef = B;
+        s.f = F1 * st + F0;
+        s.mu = s.f / s.r;
+        s.done = 3;
+        s.newton = 0;
+        *gs = s;
+        return;
+    }
+    double nxt = A > 0.0 ? st : INFINITY;
+    if (!(nxt > s.lo && nxt < s.hi) || nxt == sc)
+        nxt = isfinite(s.hi) ? 0.5 * (s.lo + s.hi) : 2.0 * fmax(s.lo, sc);
+    s.s_prev = sc;
+    s.D_prev = Dk;
+    s.s_cur = nxt;
+    if (s.nsteps >= kGapNewton || !(s.hi > s.lo)) {
+        // hand the bracket to the multisection search
+        s.newton = 0;
+        if (isfinite(s.hi)) {
+            const double w = (s.hi - s.lo) / (double)(kGapPts - 1);
+            for (int i = 0; i < kGapPts; ++i) s.pts[i] = s.lo + w * (double)i;
+            s.pts[kGapPts - 1] = s.hi;
+            s.linear = 1;
+            if (!(w > 0.0)) s.done = 1;
+        } else {
+            const double b0 = s.lo > 0.0 ? s.lo : sc;
+            for (int i = 0; i < kGapPts; ++i) s.pts[i] = b0 * exp2(0.5 * (i + 1));
+        }
+    }
     *gs = s;
 }
 
@@ -872,7 +971,7 @@ __global__ __launch_bounds__(kThreads) void k_gap_pass(int m, int n, Vecs v, con
                                                        const double *y, const double *ax,
                                                        const double *aty, const GapState *gs,
                                                        double *part) {
-    if (gs->done) return;
+    if (gs->done || gs->newton) return;
     __shared__ double red[kGapNV * (kThreads / 64)];
     __shared__ double pts[kGapPts], pts2[kGapPts];
     if (threadIdx.x < kGapPts) {
@@ -911,7 +1010,7 @@ __global__ __launch_bounds__(kThreads) void k_gap_pass(int m, int n, Vecs v, con
 
 __global__ __launch_bounds__(kThreads) void k_gap_select(const double *part, int grid,
                                                          GapState *gs) {
-    if (gs->done) return;
+    if (gs->done || gs->newton) return;
     // value i is summed by the four lanes i, i+64, i+128, i+192 (grid slices
     // g = t/64 mod 4), then combined in a fixed order
     __shared__ double quarter[4][kGapNV];
@@ -1022,6 +1121,46 @@ __global__ void k_gap_solve(const double *part, int grid, GapState *gs) {
     s.mu = s.f / s.r;
     s.done = 3;
     *gs = s;
+}
+
+// ------------------------------------------------------------ rate probes
+
+__global__ __launch_bounds__(kThreads) void k_rate_copy(int64_t len2, const double2 *a,
+                                                        double2 *b) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len2;
+         i += (int64_t)gridDim.x * kThreads)
+        b[i] = a[i];
+}
+
+__global__ __launch_bounds__(kThreads) void k_rate_idx(int64_t n, uint32_t domain, uint32_t *idx) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        uint64_t h = (uint64_t)i * 0x9E3779B97F4A7C15ull;
+        h ^= h >> 29;
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 32;
+        idx[i] = (uint32_t)(h % domain);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_rate_gather(int64_t n, const uint32_t *idx,
+                                                          const double *x, double *out) {
+    constexpr int kPer = 8;
+    double s = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads * kPer;
+    for (int64_t base = (int64_t)blockIdx.x * kThreads * kPer + threadIdx.x; base < n;
+         base += stride) {
+        uint32_t k[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int64_t i = base + (int64_t)j * kThreads;
+            k[j] = i < n ? __builtin_nontemporal_load(idx + i) : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if (base + (int64_t)j * kThreads < n) s += x[k[j]];
+    }
+    out[blockIdx.x * kThreads + threadIdx.x] = s;
 }
 
 // --------------------------------------------------------------- launchers
@@ -1255,12 +1394,34 @@ hipError_t launch_kkt(hipStream_t s, int m, int n, const double *xs, const doubl
     return hipGetLastError();
 }
 
+hipError_t launch_rate_copy(hipStream_t s, int64_t len, const double *a, double *b) {
+    hipLaunchKernelGGL(k_rate_copy, dim3(4096), dim3(kThreads), 0, s, len / 2,
+                       reinterpret_cast<const double2 *>(a), reinterpret_cast<double2 *>(b));
+    return hipGetLastError();
+}
+
+hipError_t launch_rate_idx(hipStream_t s, int64_t n, uint32_t domain, uint32_t *idx) {
+    hipLaunchKernelGGL(k_rate_idx, dim3(4096), dim3(kThreads), 0, s, n, domain, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_rate_gather(hipStream_t s, int64_t n, const uint32_t *idx, const double *x,
+                              double *out, int grid) {
+    hipLaunchKernelGGL(k_rate_gather, dim3(grid), dim3(kThreads), 0, s, n, idx, x, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_gap(hipStream_t s, int m, int n, Vecs v, const double *x, const double *y,
                       const double *ax, const double *aty, const double *xr, const double *yr,
                       double omega, double *part, int grid, GapState *gs) {
     hipLaunchKernelGGL(k_gap_setup, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty, xr,
                        yr, omega, part);
     hipLaunchKernelGGL(k_gap_init, dim3(1), dim3(kThreads), 0, s, part, grid, omega, gs);
+    for (int p = 0; p < kGapNewton; ++p) {
+        hipLaunchKernelGGL(k_gap_step, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty,
+                           gs, part);
+        hipLaunchKernelGGL(k_gap_update, dim3(1), dim3(kThreads), 0, s, part, grid, gs);
+    }
     for (int p = 0; p < kGapMaxPass; ++p) {
         hipLaunchKernelGGL(k_gap_pass, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty,
                            gs, part);

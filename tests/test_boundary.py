@@ -33,7 +33,7 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header(tmp_path):
     structs = {"pdlp_params": pd.Params, "pdlp_result": pd.Result,
                "pdlp_iter_info": pd.IterInfo, "pdlp_state_blob": pd.StateBlob,
-               "pdlp_kernel_stats": pd.KernelStats}
+               "pdlp_kernel_stats": pd.KernelStats, "pdlp_device_rates": pd.DeviceRates}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "pdlp.h"', "int main(void){"]
     for cname, py in structs.items():
         src.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
