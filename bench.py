@@ -34,6 +34,27 @@ sys.path.insert(0, ROOT)
 METRIC = "PDHG iters/s + SpMV HBM GB/s at 125M nnz; batched LPs/s; bwd/fwd time at KKT tol"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the fused products on this workload, from two
+# rocprofv3 counter runs of this script (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000;
+# factors from a copy kernel of known size; see profiles/k_spmv_pair_skewed_20Mx25M.md).
+# Valid only for the kernel source they were taken on (hash of the hot-path
+# region of the kernels and constants); reported as null otherwise.
+TRAFFIC_RECORD = {
+    "hot_source": "4d154ae9979947ad",
+    "k_spmv_dual": 12496203049,
+    "k_spmv_primal": 18287447559,
+}
+
+
+def hot_source_hash():
+    import hashlib
+    base = os.path.join(ROOT, "paper_2501_07018_amd", "csrc")
+    k = open(os.path.join(base, "pdlp_kernels.hip")).read()
+    h = open(os.path.join(base, "pdlp_internal.h")).read()
+    a = k.split("// [hot-path kernels begin]")[1].split("// [hot-path kernels end]")[0]
+    b = h.split("// [hot-path constants begin]")[1].split("// [hot-path constants end]")[0]
+    return hashlib.sha256((a + b).encode()).hexdigest()[:16]
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -168,7 +189,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": dom[1] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": (TRAFFIC_RECORD[dom[0]] if hot_source_hash() == TRAFFIC_RECORD["hot_source"]
+                        else None),
             "avg_launch_ms": dom[2],
             "algorithmic_bytes_per_launch": dom[3],
             "launches": dom[4],

@@ -8,6 +8,7 @@
 
 namespace pdlp {
 
+// [hot-path constants begin]
 constexpr int kThreads = 256;        // threads per workgroup (4 wave64)
 #ifndef PDLP_STAGE
 #define PDLP_STAGE 2048
@@ -17,6 +18,7 @@ constexpr int kMaxBlockRows = 1024;  // rows per stream block
 constexpr int kMedRow = 64;          // rows longer than this leave the stream path ...
 constexpr int kWaveMax = 1024;       // ... for one wave per row up to this length, then a workgroup
 constexpr int kWaveRows = kThreads / 64;
+// [hot-path constants end]
 constexpr int kGapPts = 32;          // abscissae per multisection pass of the gap search
 constexpr int kGapMaxPass = 24;
 constexpr int kGapNewton = 12;       // active-set steps before the multisection fallback

@@ -93,6 +93,7 @@ __device__ __forceinline__ double dual_case(double yhat, double sigma, double lc
     return 0.0;
 }
 
+// [hot-path kernels begin]
 // Matrix streams (values, column indices) are read once per product: load
 // them with the non-temporal hint so they do not displace the gathered
 // vector from the caches.
@@ -259,6 +260,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv_primal(DCsr AT, Vecs v, Iter 
     stream_spmv<1>(AT, it.Y[cur], epi, acc, prod, red);
     if (next) write_partials<1>(acc, red, part);
 }
+
+// [hot-path kernels end]
 
 // Standalone primal step: x' = proj_X(x - tau (c - A^T y)).
 __global__ __launch_bounds__(kThreads) void k_primal(int n, Vecs v, Iter it, const Ctrl *ctrl,
