@@ -49,11 +49,12 @@ TRAFFIC_RECORD = {
 def hot_source_hash():
     import hashlib
     base = os.path.join(ROOT, "paper_2501_07018_amd", "csrc")
-    k = open(os.path.join(base, "pdlp_kernels.hip")).read()
-    h = open(os.path.join(base, "pdlp_internal.h")).read()
-    a = k.split("// [hot-path kernels begin]")[1].split("// [hot-path kernels end]")[0]
-    b = h.split("// [hot-path constants begin]")[1].split("// [hot-path constants end]")[0]
-    return hashlib.sha256((a + b).encode()).hexdigest()[:16]
+    def region(fname, tag):
+        text = open(os.path.join(base, fname)).read()
+        return text.split(f"// [hot-path {tag} begin]")[1].split(f"// [hot-path {tag} end]")[0]
+    parts = (region("pdlp_kernels.hip", "kernels"), region("pdlp_device.h", "device"),
+             region("pdlp_internal.h", "constants"))
+    return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 
 def log(msg):

@@ -1,0 +1,173 @@
+// Host-side plumbing shared by the single-LP and the batched drivers of the
+// gfx950 PDLP library: error handling, device allocations, the problem object
+// and problem creation.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdint>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "pdlp.h"
+#include "pdlp_internal.h"
+
+namespace pdlp {
+namespace host {
+
+extern thread_local std::string g_last_error;
+
+struct LibError : std::runtime_error {
+    int code;
+    LibError(int c, const std::string &msg) : std::runtime_error(msg), code(c) {}
+};
+
+[[noreturn]] inline void hip_fail(hipError_t e, const char *what, int line) {
+    const int code = (e == hipErrorOutOfMemory) ? PDLP_ERR_OUT_OF_MEMORY : PDLP_ERR_HIP;
+    throw LibError(code, std::string(what) + " failed (line " + std::to_string(line) +
+                             "): " + hipGetErrorString(e));
+}
+
+#define HIPCHECK(expr)                                       \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) hip_fail(e_, #expr, __LINE__); \
+    } while (0)
+
+[[noreturn]] inline void invalid(const std::string &msg) { throw LibError(PDLP_ERR_INVALID_ARGUMENT, msg); }
+
+// Device allocations owned by an object, freed together.
+struct Arena {
+    std::vector<void *> ptrs;
+    std::vector<void *> pinned;
+    template <class T>
+    T *dev(size_t count) {
+        void *p = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            throw LibError(e == hipErrorOutOfMemory ? PDLP_ERR_OUT_OF_MEMORY : PDLP_ERR_HIP,
+                           "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
+                               hipGetErrorString(e));
+        }
+        ptrs.push_back(p);
+        return static_cast<T *>(p);
+    }
+#ifdef PDLP_PROBE_UNCACHED_MATRIX
+    // experiment only: uncached matrix arrays, never freed (process lifetime)
+    template <class T>
+    T *dev_uncached(size_t count) {
+        void *p = nullptr;
+        HIPCHECK(hipExtMallocWithFlags(&p, std::max<size_t>(count, 1) * sizeof(T),
+                                       hipDeviceMallocUncached));
+        return static_cast<T *>(p);
+    }
+#else
+    template <class T>
+    T *dev_uncached(size_t count) {
+        return dev<T>(count);
+    }
+#endif
+    template <class T>
+    T *host(size_t count) {
+        void *p = nullptr;
+        HIPCHECK(hipHostMalloc(&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
+        pinned.push_back(p);
+        return static_cast<T *>(p);
+    }
+    void release(void *p) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) {
+            (void)hipFree(p);
+            ptrs.erase(it);
+        }
+    }
+    ~Arena() {
+        for (void *p : ptrs) (void)hipFree(p);
+        for (void *p : pinned) (void)hipHostFree(p);
+    }
+};
+
+inline double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+inline int red_grid(int64_t len) {
+    int64_t g = (len + pdlp::kThreads - 1) / pdlp::kThreads;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
+}
+
+template <class F>
+int guarded(F &&f) {
+    try {
+        g_last_error.clear();
+        f();
+        return PDLP_OK;
+    } catch (const LibError &e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return PDLP_ERR_OUT_OF_MEMORY;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return PDLP_ERR_HIP;
+    }
+}
+
+inline void check_params(const pdlp_params &p) {
+    if (!(p.check_every >= 1)) invalid("check_every must be >= 1");
+    if (p.ruiz_iters < 0) invalid("ruiz_iters must be >= 0");
+    if (!(p.eps_feas >= 0.0) || !(p.eps_gap >= 0.0)) invalid("tolerances must be >= 0");
+    if (p.max_iters < 0) invalid("max_iters must be >= 0");
+    if (!(p.theta >= 0.0 && p.theta <= 1.0)) invalid("theta must lie in [0, 1]");
+    if (!(p.beta_art > 0.0)) invalid("beta_art must be > 0");
+}
+
+// Smallest k' > k with (double)(t + k' - k) >= beta * (double)k' (restart
+// condition (iii) of Section 3), capped at cap.
+long long next_art(long long k, long long t, double beta, long long cap);
+
+}  // namespace host
+}  // namespace pdlp
+
+// Device copy of a problem (the C ABI's opaque pdlp_problem).
+struct pdlp_problem {
+    int32_t m = 0, n = 0;
+    int64_t nnz = 0;
+    hipStream_t stream = nullptr;
+    pdlp::host::Arena arena;
+    pdlp::DCsr A, AT;
+    double *d1 = nullptr, *d2 = nullptr;                                // scaling
+    double *c = nullptr, *lc = nullptr, *uc = nullptr, *lv = nullptr, *uv = nullptr;  // original
+    double *cs = nullptr, *lcs = nullptr, *ucs = nullptr, *lvs = nullptr, *uvs = nullptr;
+    double *zero_n = nullptr;                                            // c = 0 (primal polish)
+    double *lc0 = nullptr, *uc0 = nullptr, *lv0 = nullptr, *uv0 = nullptr;  // finite bounds -> 0
+    double obj_offset = 0.0;
+    double *red_part = nullptr;  // partials of generic reductions
+    int red_cap = 0;
+    // internal row/column labels: row_order[new] = caller's row, col_order likewise;
+    // orig_pos[new entry] = caller's entry index
+    int32_t *row_order = nullptr, *col_order = nullptr, *orig_pos = nullptr;
+    std::vector<int32_t> blkA, blkT;  // host copies of the row-block partitions
+    double *res_d = nullptr, *res_h = nullptr;  // small reduction results
+    pdlp_params scale_params;
+
+    pdlp::Vecs scaled() const { return pdlp::Vecs{cs, lcs, ucs, lvs, uvs}; }
+};
+
+// Problem creation shared by single problems and batches (row_breaks /
+// col_breaks: first rows / columns of the instances of a batch, which row
+// blocks may not straddle; a batch keeps the caller's labels).
+pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col, const double *val, const double *c,
+                             const double *lc, const double *uc, const double *lv,
+                             const double *uv, double obj_offset, const pdlp_params *params,
+                             void *hip_stream, const std::vector<int32_t> *row_breaks,
+                             const std::vector<int32_t> *col_breaks);

@@ -22,89 +22,22 @@
 #include <string>
 #include <vector>
 
-#include "pdlp.h"
-#include "pdlp_internal.h"
+#include "pdlp_host.h"
 
 // Workgroups of the persistent CSR stream kernels (8 per CU on 256 CUs).
 #ifndef PDLP_STREAM_GRID_CAP
 #define PDLP_STREAM_GRID_CAP 2048
 #endif
 
-namespace {
-
+namespace pdlp {
+namespace host {
 thread_local std::string g_last_error;
+}  // namespace host
+}  // namespace pdlp
 
-struct LibError : std::runtime_error {
-    int code;
-    LibError(int c, const std::string &msg) : std::runtime_error(msg), code(c) {}
-};
+using namespace pdlp::host;
 
-void hip_fail(hipError_t e, const char *what, int line) {
-    const int code = (e == hipErrorOutOfMemory) ? PDLP_ERR_OUT_OF_MEMORY : PDLP_ERR_HIP;
-    throw LibError(code, std::string(what) + " failed (line " + std::to_string(line) +
-                             "): " + hipGetErrorString(e));
-}
-
-#define HIPCHECK(expr)                                       \
-    do {                                                     \
-        hipError_t e_ = (expr);                              \
-        if (e_ != hipSuccess) hip_fail(e_, #expr, __LINE__); \
-    } while (0)
-
-void invalid(const std::string &msg) { throw LibError(PDLP_ERR_INVALID_ARGUMENT, msg); }
-
-// Device allocations owned by an object, freed together.
-struct Arena {
-    std::vector<void *> ptrs;
-    std::vector<void *> pinned;
-    template <class T>
-    T *dev(size_t count) {
-        void *p = nullptr;
-        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-        hipError_t e = hipMalloc(&p, bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            throw LibError(e == hipErrorOutOfMemory ? PDLP_ERR_OUT_OF_MEMORY : PDLP_ERR_HIP,
-                           "hipMalloc of " + std::to_string(bytes) + " bytes failed: " +
-                               hipGetErrorString(e));
-        }
-        ptrs.push_back(p);
-        return static_cast<T *>(p);
-    }
-#ifdef PDLP_PROBE_UNCACHED_MATRIX
-    // experiment only: uncached matrix arrays, never freed (process lifetime)
-    template <class T>
-    T *dev_uncached(size_t count) {
-        void *p = nullptr;
-        HIPCHECK(hipExtMallocWithFlags(&p, std::max<size_t>(count, 1) * sizeof(T),
-                                       hipDeviceMallocUncached));
-        return static_cast<T *>(p);
-    }
-#else
-    template <class T>
-    T *dev_uncached(size_t count) {
-        return dev<T>(count);
-    }
-#endif
-    template <class T>
-    T *host(size_t count) {
-        void *p = nullptr;
-        HIPCHECK(hipHostMalloc(&p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault));
-        pinned.push_back(p);
-        return static_cast<T *>(p);
-    }
-    void release(void *p) {
-        auto it = std::find(ptrs.begin(), ptrs.end(), p);
-        if (it != ptrs.end()) {
-            (void)hipFree(p);
-            ptrs.erase(it);
-        }
-    }
-    ~Arena() {
-        for (void *p : ptrs) (void)hipFree(p);
-        for (void *p : pinned) (void)hipHostFree(p);
-    }
-};
+namespace {
 
 using pdlp::Ctrl;
 using pdlp::DCsr;
@@ -114,37 +47,34 @@ using pdlp::KktOut;
 using pdlp::kThreads;
 using pdlp::Vecs;
 
-double now_s() {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
-        .count();
-}
-
-int red_grid(int64_t len) {
-    int64_t g = (len + kThreads - 1) / kThreads;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(g, 1024));
-}
 
 // Row blocks of the CSR stream kernels (see DCsr): stream blocks of rows
 // with at most kMedRow nonzeros that fit the LDS stage, wave blocks of up
 // to kWaveRows medium rows, and single long rows.
-std::vector<int32_t> make_blocks(const int32_t *rp, int32_t rows) {
+// `breaks` (sorted, optional) lists rows at which a block must start: the
+// first rows of the instances of a batch.
+std::vector<int32_t> make_blocks(const int32_t *rp, int32_t rows,
+                                 const std::vector<int32_t> *breaks = nullptr) {
     std::vector<int32_t> blk;
     blk.push_back(0);
     int32_t r = 0;
+    size_t bi = 0;
     auto L = [&](int32_t i) { return rp[i + 1] - rp[i]; };
     while (r < rows) {
+        while (breaks && bi < breaks->size() && (*breaks)[bi] <= r) ++bi;
+        const int32_t lim = (breaks && bi < breaks->size()) ? (*breaks)[bi] : rows;
         const int32_t len = L(r);
         if (len > pdlp::kWaveMax) {
             ++r;
         } else if (len > pdlp::kMedRow) {
             const int32_t start = r;
-            while (r < rows && r - start < pdlp::kWaveRows && L(r) > pdlp::kMedRow &&
+            while (r < lim && r - start < pdlp::kWaveRows && L(r) > pdlp::kMedRow &&
                    L(r) <= pdlp::kWaveMax)
                 ++r;
         } else {
             const int32_t start = r;
             int64_t nz = 0;
-            while (r < rows && r - start < pdlp::kMaxBlockRows) {
+            while (r < lim && r - start < pdlp::kMaxBlockRows) {
                 const int32_t l = L(r);
                 if (l > pdlp::kMedRow || nz + l > pdlp::kStage) break;
                 nz += l;
@@ -177,28 +107,6 @@ std::vector<int32_t> order_by_count(const std::vector<int32_t> &cnt, bool reorde
 
 // ===================================================================== problem
 
-struct pdlp_problem {
-    int32_t m = 0, n = 0;
-    int64_t nnz = 0;
-    hipStream_t stream = nullptr;
-    Arena arena;
-    DCsr A, AT;
-    double *d1 = nullptr, *d2 = nullptr;                                // scaling
-    double *c = nullptr, *lc = nullptr, *uc = nullptr, *lv = nullptr, *uv = nullptr;  // original
-    double *cs = nullptr, *lcs = nullptr, *ucs = nullptr, *lvs = nullptr, *uvs = nullptr;
-    double *zero_n = nullptr;                                            // c = 0 (primal polish)
-    double *lc0 = nullptr, *uc0 = nullptr, *lv0 = nullptr, *uv0 = nullptr;  // finite bounds -> 0
-    double obj_offset = 0.0;
-    double *red_part = nullptr;  // partials of generic reductions
-    int red_cap = 0;
-    // internal row/column labels: row_order[new] = caller's row, col_order likewise;
-    // orig_pos[new entry] = caller's entry index
-    int32_t *row_order = nullptr, *col_order = nullptr, *orig_pos = nullptr;
-    double *res_d = nullptr, *res_h = nullptr;  // small reduction results
-    pdlp_params scale_params;
-
-    Vecs scaled() const { return Vecs{cs, lcs, ucs, lvs, uvs}; }
-};
 
 namespace {
 
@@ -236,14 +144,16 @@ void validate(int32_t m, int32_t n, int64_t nnz, const int32_t *rp, const int32_
     }
 }
 
-void upload_blocks(pdlp_problem *P, DCsr &M, const int32_t *rp_host) {
-    std::vector<int32_t> blk = make_blocks(rp_host, M.rows);
+std::vector<int32_t> upload_blocks(pdlp_problem *P, DCsr &M, const int32_t *rp_host,
+                                   const std::vector<int32_t> *breaks = nullptr) {
+    std::vector<int32_t> blk = make_blocks(rp_host, M.rows, breaks);
     M.nblk = (int32_t)blk.size() - 1;
     M.blk = P->arena.dev<int32_t>(blk.size());
     HIPCHECK(hipMemcpyAsync(M.blk, blk.data(), blk.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, P->stream));
     M.grid = std::min<int32_t>(M.nblk, PDLP_STREAM_GRID_CAP);
     HIPCHECK(hipStreamSynchronize(P->stream));
+    return blk;
 }
 
 // A^T from the caller-order entries: a stable radix sort by new column label
@@ -581,19 +491,6 @@ int effective_rc_mode(const pdlp_params &prm) {
     return prm.polish ? 0 : 1;
 }
 
-// Smallest k' > k with (double)(t + k' - k) >= beta * (double)k' (condition (iii)).
-long long next_art(long long k, long long t, double beta, long long cap) {
-    if (!(beta < 1.0)) {
-        if (beta == 1.0 && t == k) return k + 1;
-        return cap;
-    }
-    double est = (beta * (double)k - (double)t) / (1.0 - beta);
-    long long d = (long long)std::ceil(est);
-    if (d < 1) d = 1;
-    d = std::max<long long>(1, d - 2);
-    while ((double)(t + d) < beta * (double)(k + d)) ++d;
-    return std::min(cap, k + d);
-}
 
 // Buffers of feasibility polishing, created on first use and kept.
 struct PolishBufs {
@@ -802,6 +699,19 @@ int run_loop(Ctx &X, Engine &E, long long max_k, int term_mode, bool allow_polis
 
 }  // namespace
 
+long long pdlp::host::next_art(long long k, long long t, double beta, long long cap) {
+    if (!(beta < 1.0)) {
+        if (beta == 1.0 && t == k) return k + 1;
+        return cap;
+    }
+    double est = (beta * (double)k - (double)t) / (1.0 - beta);
+    long long d = (long long)std::ceil(est);
+    if (d < 1) d = 1;
+    d = std::max<long long>(1, d - 2);
+    while ((double)(t + d) < beta * (double)(k + d)) ++d;
+    return std::min(cap, k + d);
+}
+
 struct pdlp_state {
     pdlp_problem *P = nullptr;
     pdlp_params prm{};
@@ -814,32 +724,6 @@ struct pdlp_state {
 
 namespace {
 
-template <class F>
-int guarded(F &&f) {
-    try {
-        g_last_error.clear();
-        f();
-        return PDLP_OK;
-    } catch (const LibError &e) {
-        g_last_error = e.what();
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        g_last_error = "host allocation failed";
-        return PDLP_ERR_OUT_OF_MEMORY;
-    } catch (const std::exception &e) {
-        g_last_error = e.what();
-        return PDLP_ERR_HIP;
-    }
-}
-
-void check_params(const pdlp_params &p) {
-    if (!(p.check_every >= 1)) invalid("check_every must be >= 1");
-    if (p.ruiz_iters < 0) invalid("ruiz_iters must be >= 0");
-    if (!(p.eps_feas >= 0.0) || !(p.eps_gap >= 0.0)) invalid("tolerances must be >= 0");
-    if (p.max_iters < 0) invalid("max_iters must be >= 0");
-    if (!(p.theta >= 0.0 && p.theta <= 1.0)) invalid("theta must lie in [0, 1]");
-    if (!(p.beta_art > 0.0)) invalid("beta_art must be > 0");
-}
 
 void engine_initialize(pdlp_state *S, const double *x0_host, const double *y0_host) {
     pdlp_problem *P = S->P;
@@ -901,19 +785,21 @@ void pdlp_params_default(pdlp_params *p) {
     p->reorder = 1;
 }
 
-int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
-                        const int32_t *col, const double *val, const double *c, const double *lc,
-                        const double *uc, const double *lv, const double *uv, double obj_offset,
-                        const pdlp_params *params, void *hip_stream, pdlp_problem **out) {
-    return guarded([&] {
-        if (!out) invalid("out is NULL");
-        *out = nullptr;
+}  // extern "C"
+
+pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col, const double *val, const double *c,
+                             const double *lc, const double *uc, const double *lv,
+                             const double *uv, double obj_offset, const pdlp_params *params,
+                             void *hip_stream, const std::vector<int32_t> *row_breaks,
+                             const std::vector<int32_t> *col_breaks) {
         validate(m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv);
         if (!std::isfinite(obj_offset)) invalid("objective offset must be finite");
         pdlp_params prm;
         pdlp_params_default(&prm);
         if (params) prm = *params;
         check_params(prm);
+        if (row_breaks || col_breaks) prm.reorder = 0;
         auto *P = new pdlp_problem();
         try {
             P->m = m;
@@ -1000,19 +886,32 @@ int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
             P->red_part = a.dev<double>(P->red_cap);
             P->res_d = a.dev<double>(8);
             P->res_h = a.host<double>(8);
-            upload_blocks(P, A, new_rp.data());
+            P->blkA = upload_blocks(P, A, new_rp.data(), row_breaks);
             {
                 std::vector<int32_t> trp((size_t)n + 1);
                 HIPCHECK(hipMemcpy(trp.data(), P->AT.row_ptr, sizeof(int32_t) * ((size_t)n + 1),
                                    hipMemcpyDeviceToHost));
-                upload_blocks(P, P->AT, trp.data());
+                P->blkT = upload_blocks(P, P->AT, trp.data(), col_breaks);
             }
             precondition(P, prm);
         } catch (...) {
             delete P;
             throw;
         }
-        *out = P;
+        return P;
+}
+
+extern "C" {
+
+int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                        const int32_t *col, const double *val, const double *c, const double *lc,
+                        const double *uc, const double *lv, const double *uv, double obj_offset,
+                        const pdlp_params *params, void *hip_stream, pdlp_problem **out) {
+    return guarded([&] {
+        if (!out) invalid("out is NULL");
+        *out = nullptr;
+        *out = create_problem(m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, obj_offset, params,
+                              hip_stream, nullptr, nullptr);
     });
 }
 

@@ -97,6 +97,18 @@ struct KktOut {
     double pad;
 };
 
+// Block maps of a batch of LPs packed block-diagonally: rows (columns) of
+// instance i are [roff[i], roff[i+1]) ([coff[i], coff[i+1])); row blocks of
+// A and of A^T never straddle two instances.
+struct BatchMaps {
+    int32_t B = 0;                       // instances
+    int32_t nA = 0, nT = 0;              // blocks of A and of A^T
+    const int32_t *ablk_inst = nullptr;  // instance of each A block [nA]
+    const int32_t *tblk_inst = nullptr;  // instance of each A^T block [nT]
+    const int32_t *ablk_off = nullptr;   // first A block of each instance [B+1]
+    const int32_t *tblk_off = nullptr;   // first A^T block of each instance [B+1]
+};
+
 // ------------------------------------------------------------ launchers
 // All launchers enqueue on `s` and return hipGetLastError().
 
@@ -187,5 +199,36 @@ hipError_t launch_rate_copy(hipStream_t s, int64_t len, const double *a, double 
 hipError_t launch_rate_idx(hipStream_t s, int64_t n, uint32_t domain, uint32_t *idx);
 hipError_t launch_rate_gather(hipStream_t s, int64_t n, const uint32_t *idx, const double *x,
                               double *out, int grid);
+
+// batched solver (one control block per instance; per-block partial sums)
+hipError_t launch_b_attempt(hipStream_t s, const DCsr &A, const DCsr &AT, Vecs v, Iter it,
+                            Ctrl *ctrl, const BatchMaps &bm, double *pd, double *pps,
+                            double *ppf);
+hipError_t launch_b_settle(hipStream_t s, const DCsr &A, const DCsr &AT, Iter it, Ctrl *ctrl,
+                           const BatchMaps &bm);
+// masked per-instance elementwise ops: op 0 out = a / sv[i], 1 out = a, 2 out = sv[i]
+hipError_t launch_b_elementwise(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                                const int32_t *mask, int op, const double *sv, const double *xa,
+                                double *xo, const double *ya, double *yo);
+hipError_t launch_b_spmv_plain(hipStream_t s, const DCsr &M, const int32_t *blk_inst,
+                               const int32_t *mask, const double *x, double *out);
+// per-instance pairs out[2i], out[2i+1]: op 0 ||xa-xb||^2, ||ya-yb||^2;
+// op 2 ||c||^2, ||Combine(lc, uc)||^2; op 3 max |A^T value| (maxmask 1)
+hipError_t launch_b_norms(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                          const int32_t *mask, int op, const double *xa, const double *xb,
+                          const double *ya, const double *yb, Vecs v, double *part,
+                          unsigned maxmask, double *out);
+// termination sums per instance, out[7i + k]: 0 primal res abs, 1 rel, 2 dual res abs, 3 rel
+// (max), 4 c^T x, 5 dual objective terms, 6 non-finite count; p0/p1 = {x, y, ax, aty}
+// chosen per instance by sel
+hipError_t launch_b_kkt(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                        const int32_t *mask, const int32_t *sel, const double *const *p0,
+                        const double *const *p1, const double *d1, const double *d2, Vecs orig,
+                        int mode, double *part, double *out, double *r_out, double *x_out,
+                        double *y_out);
+hipError_t launch_b_gap(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                        const int32_t *mask, Vecs v, const double *x, const double *y,
+                        const double *ax, const double *aty, const double *xr, const double *yr,
+                        const double *omega, double *part, GapState *gs, int steps);
 
 }  // namespace pdlp

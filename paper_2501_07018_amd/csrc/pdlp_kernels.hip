@@ -12,7 +12,7 @@
 // Reductions are deterministic: fixed grids, per-thread accumulation in a
 // fixed order, wave butterfly + LDS in a fixed order, and a one-workgroup
 // final pass in a fixed order.  No floating-point atomics anywhere.
-#include "pdlp_internal.h"
+#include "pdlp_device.h"
 
 #include <hip/hip_ext.h>
 
@@ -20,166 +20,8 @@
 
 namespace pdlp {
 
-// ------------------------------------------------------------ reductions
-
-__device__ __forceinline__ double nan_max(double a, double b) {
-    if (a != a) return a;
-    if (b != b) return b;
-    return b > a ? b : a;
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = nan_max(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-// Reduce NV per-thread values over the workgroup; bit i of MAXMASK selects a
-// max instead of a sum for value i.  The result is valid in thread 0.
-// lds must hold (kThreads/64)*NV doubles.
-template <int NV, unsigned MAXMASK = 0u>
-__device__ __forceinline__ void block_reduce(double (&v)[NV], double *lds) {
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = ((MAXMASK >> i) & 1u) ? wave_max(v[i]) : wave_sum(v[i]);
-    __syncthreads();
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) lds[wid * NV + i] = v[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            double a = lds[i];
-            for (int w = 1; w < kThreads / 64; ++w)
-                a = ((MAXMASK >> i) & 1u) ? nan_max(a, lds[w * NV + i]) : a + lds[w * NV + i];
-            v[i] = a;
-        }
-    }
-    __syncthreads();
-}
-
-template <int NV, unsigned MAXMASK = 0u>
-__device__ __forceinline__ void write_partials(double (&v)[NV], double *lds, double *part) {
-    block_reduce<NV, MAXMASK>(v, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) part[blockIdx.x * NV + i] = v[i];
-    }
-}
-
-__device__ __forceinline__ double clampd(double v, double lo, double hi) {
-    return v < lo ? lo : (v > hi ? hi : v);
-}
-
-// Dual update in case form (Section 2): with yhat = y - sigma A(2x' - x),
-// y' = yhat + sigma uc if yhat < -sigma uc; yhat + sigma lc if yhat > -sigma lc; else 0.
-__device__ __forceinline__ double dual_case(double yhat, double sigma, double lc, double uc) {
-    if (isfinite(uc)) {
-        const double su = sigma * uc;
-        if (yhat < -su) return yhat + su;
-    }
-    if (isfinite(lc)) {
-        const double sl = sigma * lc;
-        if (yhat > -sl) return yhat + sl;
-    }
-    return 0.0;
-}
-
 // [hot-path kernels begin]
-// Matrix streams (values, column indices) are read once per product: load
-// them with the non-temporal hint so they do not displace the gathered
-// vector from the caches.
-#ifndef PDLP_NT_STREAM
-#define PDLP_NT_STREAM 1
-#endif
-template <class T>
-__device__ __forceinline__ T stream_load(const T *p) {
-#if PDLP_NT_STREAM
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
-}
-
-// ------------------------------------------------------- CSR stream SpMV
-//
-// Workgroup-per-row-block CSR product.  A short-row block stages its
-// products in LDS with fully coalesced loads of val/col (one gather of x per
-// nonzero), then one lane per row sums its slice in stored order -- the
-// same order as a sequential row loop.  Medium rows get one wave each
-// (lane-strided partial sums, butterfly reduction); a long row is reduced
-// across the workgroup.  The grid is persistent: workgroup g handles blocks
-// g, g + grid, ...
-
-template <int NACC, class Epi>
-__device__ __forceinline__ void stream_spmv(const DCsr &A, const double *__restrict__ x,
-                                            const Epi &epi, double (&acc)[NACC], double *prod,
-                                            double *red) {
-    constexpr int kPer = kStage / kThreads;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int b = blockIdx.x; b < A.nblk; b += gridDim.x) {
-        const int r0 = A.blk[b], r1 = A.blk[b + 1];
-        const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
-        const int len = e1 - e0;
-        const int len0 = A.row_ptr[r0 + 1] - e0;
-        if (len0 > kMedRow && len0 <= kWaveMax) {
-            // wave block: row r0 + wid
-            const int r = r0 + wid;
-            if (r < r1) {
-                const int a = A.row_ptr[r], z = A.row_ptr[r + 1];
-                double s = 0.0;
-                for (int e = a + lane; e < z; e += 64)
-                    s += stream_load(A.val + e) * x[stream_load(A.col + e)];
-                s = wave_sum(s);
-                if (lane == 0) epi(r, s, acc);
-            }
-        } else if (len <= kStage && len0 <= kMedRow) {
-            int ci[kPer];
-            double vv[kPer];
-#pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int q = i * kThreads + threadIdx.x;
-                if (q < len) {
-                    ci[i] = stream_load(A.col + e0 + q);
-                    vv[i] = stream_load(A.val + e0 + q);
-                } else {
-                    ci[i] = 0;
-                    vv[i] = 0.0;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int q = i * kThreads + threadIdx.x;
-                if (q < len) prod[q] = vv[i] * x[ci[i]];
-            }
-            __syncthreads();
-            for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
-                const int a = A.row_ptr[r] - e0, z = A.row_ptr[r + 1] - e0;
-                double s = 0.0;
-                for (int q = a; q < z; ++q) s += prod[q];
-                epi(r, s, acc);
-            }
-            __syncthreads();
-        } else {
-            double s = 0.0;
-            for (int e = e0 + threadIdx.x; e < e1; e += kThreads)
-                s += stream_load(A.val + e) * x[stream_load(A.col + e)];
-            double t[1] = {s};
-            block_reduce<1>(t, red);
-            if (threadIdx.x == 0) epi(r0, t[0], acc);
-        }
-    }
-}
-
-struct PlainEpi {
+struct PlainEpi : SingleEpi {
     double *out;
     template <int N>
     __device__ __forceinline__ void operator()(int r, double s, double (&)[N]) const { out[r] = s; }
@@ -190,27 +32,16 @@ __global__ __launch_bounds__(kThreads) void k_spmv_plain(DCsr A, const double *_
     __shared__ double prod[kStage];
     __shared__ double red[kThreads / 64];
     double acc[1] = {0.0};
-    PlainEpi epi{out};
-    stream_spmv<1>(A, x, epi, acc, prod, red);
+    PlainEpi epi;
+    epi.gsrc = x;
+    epi.out = out;
+    stream_spmv<1>(A, epi, acc, prod, red);
 }
 
-// A x' + dual step.  acc[0] = ||y'-y||^2, acc[1] = (y'-y)^T (A x' - A x).
-struct DualEpi {
-    const double *y, *ax, *lc, *uc;
-    double *ax_new, *y_new, *sy;
-    double sigma, eta_avg;
-    int pend;
+struct DualEpi : SingleEpi {
+    DualRow row;
     __device__ __forceinline__ void operator()(int r, double s, double (&acc)[2]) const {
-        ax_new[r] = s;
-        const double yr = y[r];
-        if (pend) sy[r] += eta_avg * yr;
-        const double axr = ax[r];
-        const double yhat = yr - sigma * (2.0 * s - axr);
-        const double yn = dual_case(yhat, sigma, lc[r], uc[r]);
-        y_new[r] = yn;
-        const double dy = yn - yr;
-        acc[0] += dy * dy;
-        acc[1] += dy * (s - axr);
+        row(r, s, acc);
     }
 };
 
@@ -220,30 +51,19 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dual(DCsr A, Vecs v, Iter it,
     __shared__ double prod[kStage];
     __shared__ double red[2 * (kThreads / 64)];
     const int cur = ctrl->cur;
-    DualEpi epi{it.Y[cur], it.AX[cur], v.lc, v.uc, it.AX[cur ^ 1], it.Y[cur ^ 1], it.sy,
-                ctrl->eta * ctrl->omega, ctrl->eta_avg_y, ctrl->pending_sy};
+    DualEpi epi;
+    epi.gsrc = it.X[cur ^ 1];
+    epi.row = DualRow{it.Y[cur], it.AX[cur], v.lc, v.uc, it.AX[cur ^ 1], it.Y[cur ^ 1], it.sy,
+                      ctrl->eta * ctrl->omega, ctrl->eta_avg_y, ctrl->pending_sy};
     double acc[2] = {0.0, 0.0};
-    stream_spmv<2>(A, it.X[cur ^ 1], epi, acc, prod, red);
+    stream_spmv<2>(A, epi, acc, prod, red);
     write_partials<2>(acc, red, part);
 }
 
-// A^T y' + primal average + next candidate x'.  acc[0] = ||x'-x||^2.
-struct PrimalEpi {
-    const double *x, *c, *lv, *uv;
-    double *aty, *x_new, *sx;
-    double eta_used, tau;
-    int next;
+struct PrimalEpi : SingleEpi {
+    PrimalRow row;
     __device__ __forceinline__ void operator()(int j, double s, double (&acc)[1]) const {
-        aty[j] = s;
-        const double xj = x[j];
-        sx[j] += eta_used * xj;
-        if (next) {
-            const double g = c[j] - s;
-            const double xn = clampd(xj - tau * g, lv[j], uv[j]);
-            x_new[j] = xn;
-            const double d = xn - xj;
-            acc[0] += d * d;
-        }
+        row(j, s, acc);
     }
 };
 
@@ -254,10 +74,12 @@ __global__ __launch_bounds__(kThreads) void k_spmv_primal(DCsr AT, Vecs v, Iter 
     __shared__ double red[kThreads / 64];
     const int cur = ctrl->cur;
     const int next = !ctrl->stop;
-    PrimalEpi epi{it.X[cur], v.c, v.lv, v.uv, it.ATY[cur], it.X[cur ^ 1], it.sx,
-                  ctrl->eta_used, ctrl->eta / ctrl->omega, next};
+    PrimalEpi epi;
+    epi.gsrc = it.Y[cur];
+    epi.row = PrimalRow{it.X[cur], v.c, v.lv, v.uv, it.ATY[cur], it.X[cur ^ 1], it.sx,
+                        ctrl->eta_used, ctrl->eta / ctrl->omega, next};
     double acc[1] = {0.0};
-    stream_spmv<1>(AT, it.Y[cur], epi, acc, prod, red);
+    stream_spmv<1>(AT, epi, acc, prod, red);
     if (next) write_partials<1>(acc, red, part);
 }
 
@@ -725,72 +547,6 @@ __global__ void k_kkt_final(const double *part, int grid, double obj_offset, Kkt
 // whose difference between neighbouring abscissae counts the breakpoints in
 // between.  Once the bracket holding r^2 has none, D = A s^2 + B and
 // f = F1 s + F0 there, so s* = sqrt((r^2 - B)/A) and mu = (F1 s* + F0)/r.
-
-struct Seg {
-    double b1, b2, a1, c, a3, f1, f0, f3, f3b;
-};
-
-__device__ __forceinline__ Seg seg_x(double x, double g, double lv, double uv, double omega) {
-    Seg q;
-    q.b2 = INFINITY;
-    q.a3 = 0.0;
-    q.f3 = 0.0;
-    q.f3b = 0.0;
-    if (g == 0.0) {
-        q.b1 = INFINITY;
-        q.a1 = q.c = q.f1 = q.f0 = 0.0;
-        return q;
-    }
-    const double dist = g > 0.0 ? x - lv : uv - x;  // may be +inf
-    q.a1 = g * g / omega;
-    q.f1 = q.a1;
-    q.b1 = omega * dist / fabs(g);
-    q.c = isfinite(dist) ? omega * dist * dist : INFINITY;
-    q.f0 = isfinite(dist) ? fabs(g) * dist : INFINITY;
-    return q;
-}
-
-// y in Y; af/bf: lc/uc finite; a/b: slopes for positive/negative y^.
-__device__ __forceinline__ Seg seg_y(double y, bool af, double a, bool bf, double b, double omega) {
-    Seg q;
-    q.b1 = q.b2 = INFINITY;
-    q.a1 = q.c = q.a3 = q.f1 = q.f0 = q.f3 = q.f3b = 0.0;
-    if (y > 0.0) {
-        if (af && a > 0.0) {          // moves up without end
-            q.a1 = q.f1 = omega * a * a;
-        } else if (af && a == 0.0) {  // static
-        } else {
-            q.a1 = q.f1 = af ? omega * a * a : 0.0;
-            q.b1 = af ? y / (omega * (-a)) : 0.0;  // reaches 0
-            q.c = y * y / omega;
-            q.f0 = af ? -a * y : 0.0;
-            if (bf && b < 0.0) {                   // leaves 0 downwards
-                q.b2 = y / (omega * (-b));
-                q.a3 = q.f3 = omega * b * b;
-                q.f3b = (b - (af ? a : 0.0)) * y;
-            }
-        }
-    } else if (y < 0.0) {
-        if (bf && b < 0.0) {
-            q.a1 = q.f1 = omega * b * b;
-        } else if (bf && b == 0.0) {
-        } else {
-            q.a1 = q.f1 = bf ? omega * b * b : 0.0;
-            q.b1 = bf ? -y / (omega * b) : 0.0;
-            q.c = y * y / omega;
-            q.f0 = bf ? -b * y : 0.0;
-            if (af && a > 0.0) {
-                q.b2 = -y / (omega * a);
-                q.a3 = q.f3 = omega * a * a;
-                q.f3b = (a - (bf ? b : 0.0)) * y;
-            }
-        }
-    } else {
-        if (af && a > 0.0) q.a1 = q.f1 = omega * a * a;
-        else if (bf && b < 0.0) q.a1 = q.f1 = omega * b * b;
-    }
-    return q;
-}
 
 __device__ __forceinline__ Seg coord_seg(int idx, int n, Vecs v, const double *x, const double *y,
                                          const double *ax, const double *aty, double omega) {
