@@ -218,6 +218,58 @@ typedef struct pdlp_device_rates {
 } pdlp_device_rates;
 int pdlp_measure_device_rates(int64_t copy_bytes, int64_t gather_len, pdlp_device_rates *out);
 
+/*
+ * Batches: many independent LPs solved together in the same kernel launches.
+ *
+ * The instances are packed block-diagonally on the device; each keeps its
+ * own step size, primal weight, restart state and termination (Algorithm 1
+ * per instance, with the same readings as pdlp_solve), so a batch result
+ * equals that of solving each instance alone up to the rounding order of
+ * the reductions.  Scaling (Ruiz + Pock-Chambolle) is per row and column and
+ * hence per instance.  Feasibility polishing and warm starts are not
+ * offered for batches.
+ */
+typedef struct pdlp_batch pdlp_batch;     /* opaque: packed instances on the device */
+
+/*
+ * Create a batch of `count` >= 1 instances from host arrays.  Instance i has
+ * m[i] >= 0 rows, n[i] >= 1 columns and nnz[i] nonzeros.  Arrays are the
+ * instances' own arrays concatenated in instance order:
+ *   row_ptr: sum(m[i] + 1) entries, each instance's CSR row pointers starting at 0;
+ *   col, val: sum(nnz[i]) entries, column indices local to the instance;
+ *   c, lv, uv: sum(n[i]);  lc, uc: sum(m[i]);
+ *   obj_offset: count entries, or NULL for zeros.
+ * Each instance obeys the conventions above; the batch totals of rows,
+ * columns and nonzeros must stay below 2^31.  params: scaling parameters
+ * (ruiz_iters, pock_chambolle), NULL = defaults.  Errors as
+ * pdlp_problem_create, with the instance named in the message.
+ */
+int pdlp_batch_create(int32_t count, const int32_t *m, const int32_t *n, const int64_t *nnz,
+                      const int32_t *row_ptr_host, const int32_t *col_host,
+                      const double *val_host, const double *c_host, const double *lc_host,
+                      const double *uc_host, const double *lv_host, const double *uv_host,
+                      const double *obj_offset_host, const pdlp_params *params,
+                      void *hip_stream, pdlp_batch **out);
+
+void pdlp_batch_destroy(pdlp_batch *b);
+
+/* Instance count and batch totals. */
+int pdlp_batch_dims(const pdlp_batch *b, int32_t *count, int64_t *m_total, int64_t *n_total,
+                    int64_t *nnz_total);
+
+/*
+ * Solve every instance from (proj_X(0), 0) with the same params (NULL =
+ * defaults; params->polish must be 0, else INVALID_ARGUMENT; max_iters and
+ * time_limit apply to each instance, the time limit measured from the start
+ * of the call).  results: `count` entries, filled as by pdlp_solve (their
+ * x, y, r pointers are ignored and set to NULL; seconds is the wall time of
+ * the whole batch).  x, r (sum(n[i])) and y (sum(m[i])) receive the unscaled
+ * outputs concatenated in instance order, or may be NULL.  Repeated calls
+ * solve again from the start and reuse the device work buffers.
+ */
+int pdlp_batch_solve(pdlp_batch *b, const pdlp_params *params, pdlp_result *results, double *x,
+                     double *y, double *r);
+
 /* Message for the last error on this thread ("" if none). */
 const char *pdlp_last_error(void);
 

@@ -95,7 +95,8 @@ EXPORTS = ("pdlp_problem_create", "pdlp_problem_destroy", "pdlp_problem_dims",
            "pdlp_problem_get_scaled", "pdlp_spmv", "pdlp_params_default", "pdlp_solve",
            "pdlp_state_create", "pdlp_state_destroy", "pdlp_iterate_k", "pdlp_state_get",
            "pdlp_state_set", "pdlp_norm_gap", "pdlp_last_error", "pdlp_state_solve",
-           "pdlp_state_kernel_stats", "pdlp_measure_device_rates")
+           "pdlp_state_kernel_stats", "pdlp_measure_device_rates", "pdlp_batch_create",
+           "pdlp_batch_destroy", "pdlp_batch_dims", "pdlp_batch_solve")
 
 
 def lib() -> C.CDLL:
@@ -128,6 +129,13 @@ def lib() -> C.CDLL:
     L.pdlp_state_solve.argtypes = [vp, C.c_int64, C.POINTER(Result)]
     L.pdlp_state_kernel_stats.argtypes = [vp, C.POINTER(KernelStats), C.c_int32]
     L.pdlp_measure_device_rates.argtypes = [C.c_int64, C.c_int64, C.POINTER(DeviceRates)]
+    I64 = C.POINTER(C.c_int64)
+    L.pdlp_batch_create.argtypes = [C.c_int32, I32, I32, I64, I32, I32, D, D, D, D, D, D, D,
+                                    C.POINTER(Params), vp, C.POINTER(vp)]
+    L.pdlp_batch_destroy.argtypes = [vp]
+    L.pdlp_batch_destroy.restype = None
+    L.pdlp_batch_dims.argtypes = [vp, I32, I64, I64, I64]
+    L.pdlp_batch_solve.argtypes = [vp, C.POINTER(Params), C.POINTER(Result), D, D, D]
     L.pdlp_last_error.argtypes = []
     L.pdlp_last_error.restype = C.c_char_p
     _lib = L
@@ -286,6 +294,90 @@ def pdlp_measure_device_rates(copy_bytes=2 << 30, gather_len=25_000_000) -> dict
     r = DeviceRates()
     _check(lib().pdlp_measure_device_rates(int(copy_bytes), int(gather_len), C.byref(r)))
     return {f: getattr(r, f) for f, _ in DeviceRates._fields_}
+
+
+def pdlp_batch_create(lps, params: Params | None = None, stream=None):
+    """Create a batch from a sequence of objects with CSR fields (as Problem)."""
+    count = len(lps)
+    m = np.array([lp.m for lp in lps], dtype=np.int32)
+    n = np.array([lp.n for lp in lps], dtype=np.int32)
+    nnz = np.array([int(lp.row_ptr[-1]) if len(lp.row_ptr) else 0 for lp in lps], dtype=np.int64)
+    rp = np.ascontiguousarray(np.concatenate([np.asarray(lp.row_ptr, dtype=np.int32)
+                                              for lp in lps]), dtype=np.int32)
+    cl = np.ascontiguousarray(np.concatenate([np.asarray(lp.col, dtype=np.int32) for lp in lps]),
+                              dtype=np.int32)
+    cat = {k: _f64(np.concatenate([np.asarray(getattr(lp, k), dtype=np.float64) for lp in lps]))
+           for k in ("val", "c", "lc", "uc", "lv", "uv")}
+    off = _f64([getattr(lp, "obj_offset", 0.0) for lp in lps])
+    h = C.c_void_p()
+    rc = lib().pdlp_batch_create(int(count), m.ctypes.data_as(I32), n.ctypes.data_as(I32),
+                                 nnz.ctypes.data_as(C.POINTER(C.c_int64)), rp.ctypes.data_as(I32),
+                                 cl.ctypes.data_as(I32),
+                                 *[_d(cat[k]) for k in ("val", "c", "lc", "uc", "lv", "uv")],
+                                 _d(off), C.byref(params) if params is not None else None,
+                                 stream, C.byref(h))
+    _check(rc)
+    return h
+
+
+def pdlp_batch_destroy(h):
+    lib().pdlp_batch_destroy(h)
+
+
+def pdlp_batch_dims(h):
+    cnt, m, n, nnz = C.c_int32(), C.c_int64(), C.c_int64(), C.c_int64()
+    _check(lib().pdlp_batch_dims(h, C.byref(cnt), C.byref(m), C.byref(n), C.byref(nnz)))
+    return cnt.value, m.value, n.value, nnz.value
+
+
+def pdlp_batch_solve(h, params: Params | None = None, want_solution=True):
+    """Solve every instance; returns (results, x, y, r) with x, y, r concatenated
+    in instance order (None unless want_solution)."""
+    cnt, m, n, _ = pdlp_batch_dims(h)
+    res = (Result * cnt)()
+    x = y = r = None
+    if want_solution:
+        x, y, r = np.empty(n), np.empty(m), np.empty(n)
+    _check(lib().pdlp_batch_solve(h, C.byref(params) if params is not None else None, res,
+                                  _d(x), _d(y), _d(r)))
+    out = []
+    for i in range(cnt):
+        d = {f: getattr(res[i], f) for f, _ in Result._fields_ if f not in ("x", "y", "r")}
+        d["status_name"] = STATUS.get(d["status"], str(d["status"]))
+        out.append(d)
+    return out, x, y, r
+
+
+class Batch:
+    """Owner of a batch handle; solve() returns per-instance result dicts with
+    the instance's x, y, r split out of the concatenated outputs."""
+
+    def __init__(self, lps, params: Params | None = None, stream=None):
+        self.m = [int(lp.m) for lp in lps]
+        self.n = [int(lp.n) for lp in lps]
+        self.h = pdlp_batch_create(lps, params, stream)
+
+    def solve(self, params: Params | None = None, want_solution=True) -> list:
+        res, x, y, r = pdlp_batch_solve(self.h, params, want_solution)
+        if want_solution:
+            co = np.concatenate([[0], np.cumsum(self.n)])
+            ro = np.concatenate([[0], np.cumsum(self.m)])
+            for i, d in enumerate(res):
+                d["x"] = x[co[i]:co[i + 1]]
+                d["r"] = r[co[i]:co[i + 1]]
+                d["y"] = y[ro[i]:ro[i + 1]]
+        return res
+
+    def close(self):
+        if self.h:
+            pdlp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def pdlp_last_error() -> str:

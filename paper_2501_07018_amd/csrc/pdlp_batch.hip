@@ -1,0 +1,702 @@
+// Batched PDLP: many independent LPs solved together on one device.
+//
+// The instances are packed block-diagonally into one problem (rows and
+// columns in instance order, caller labels kept), so Ruiz and Pock-Chambolle
+// scaling, which act per row and per column, are exactly those of each
+// instance alone.  Each instance has its own device control block: step
+// size, primal weight, counters and the accept/reject flags of Algorithm 2.
+// One launch of each step kernel serves every instance; a row block belongs
+// to one instance, reads that instance's control block and skips itself when
+// the instance is idle, finished or has reached its block target.
+//
+// The host runs Algorithm 1 per instance at the boundaries of iteration
+// blocks.  In one round every unfinished instance runs to its own next
+// boundary (next multiple of the check cadence, the first count where
+// restart condition (iii) holds, or the iteration cap); the round ends when
+// all have arrived.  The checks of the round (average, normalized duality
+// gaps, termination, restart with the primal-weight update) then run for all
+// instances at once with per-instance masks.  Decisions, counters and
+// readings are those of the single-LP driver; feasibility polishing and warm
+// starts are not offered for batches.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "pdlp_host.h"
+
+using namespace pdlp::host;
+using pdlp::BatchMaps;
+using pdlp::Ctrl;
+using pdlp::DCsr;
+using pdlp::GapState;
+using pdlp::Iter;
+using pdlp::Vecs;
+
+namespace {
+
+// Active-set steps per normalized-duality-gap evaluation.
+constexpr int kBatchGapSteps = 32;
+
+// Device buffers of a batch solve, sized by the packed problem.
+struct BatchWork {
+    Arena arena;
+    Iter it{};
+    double *x0, *y0, *xb, *yb, *axb, *atyb, *xp, *yp, *xo, *yo, *ro;
+    Ctrl *ctrl_d, *ctrl_h;
+    double *part_dual, *part_ps, *part_pf, *part_chk;
+    GapState *gs_d, *gs_h;
+    double *out_d, *out_h;
+    int32_t *mask_d, *mask_h;  // kMasks arrays of B
+    int32_t *sel_d, *sel_h;
+    double *sv_d, *sv_h, *om_d, *om_h, *zero_d;
+};
+
+enum { MASK_CHK = 0, MASK_KKT, MASK_RST, MASK_RST_AVG, kMasks };
+
+}  // namespace
+
+struct pdlp_batch {
+    int32_t B = 0;
+    std::vector<int32_t> m, n, roff, coff;
+    std::vector<double> obj_offset;
+    pdlp_problem *P = nullptr;
+    Arena arena;
+    BatchMaps bm;
+    BatchWork *W = nullptr;
+    ~pdlp_batch() {
+        delete W;
+        delete P;
+    }
+};
+
+namespace {
+
+BatchWork *make_work(pdlp_batch *b) {
+    pdlp_problem *P = b->P;
+    const int64_t M = P->m, N = P->n;
+    const int B = b->B;
+    const int ncb = b->bm.nA + b->bm.nT;
+    auto *W = new BatchWork();
+    try {
+        Arena &a = W->arena;
+        for (int k = 0; k < 2; ++k) {
+            W->it.X[k] = a.dev<double>(N);
+            W->it.ATY[k] = a.dev<double>(N);
+            W->it.Y[k] = a.dev<double>(M);
+            W->it.AX[k] = a.dev<double>(M);
+        }
+        W->it.sx = a.dev<double>(N);
+        W->it.sy = a.dev<double>(M);
+        double **vn[] = {&W->x0, &W->xb, &W->atyb, &W->xp, &W->xo, &W->ro};
+        for (auto p : vn) *p = a.dev<double>(N);
+        double **vm[] = {&W->y0, &W->yb, &W->axb, &W->yp, &W->yo};
+        for (auto p : vm) *p = a.dev<double>(M);
+        W->ctrl_d = a.dev<Ctrl>(B);
+        W->ctrl_h = a.host<Ctrl>(B);
+        W->part_dual = a.dev<double>(2 * (size_t)std::max(b->bm.nA, 1));
+        W->part_ps = a.dev<double>(std::max(b->bm.nT, 1));
+        W->part_pf = a.dev<double>(std::max(b->bm.nT, 1));
+        W->part_chk = a.dev<double>(7 * (size_t)std::max(ncb, 1));
+        W->gs_d = a.dev<GapState>(3 * (size_t)B);
+        W->gs_h = a.host<GapState>(3 * (size_t)B);
+        W->out_d = a.dev<double>(7 * (size_t)B);
+        W->out_h = a.host<double>(7 * (size_t)B);
+        W->mask_d = a.dev<int32_t>(kMasks * (size_t)B);
+        W->mask_h = a.host<int32_t>(kMasks * (size_t)B);
+        W->sel_d = a.dev<int32_t>(B);
+        W->sel_h = a.host<int32_t>(B);
+        W->sv_d = a.dev<double>(B);
+        W->sv_h = a.host<double>(B);
+        W->om_d = a.dev<double>(B);
+        W->om_h = a.host<double>(B);
+        W->zero_d = a.dev<double>(B);
+        HIPCHECK(pdlp::launch_fill(P->stream, B, W->zero_d, 0.0));
+        HIPCHECK(hipStreamSynchronize(P->stream));
+    } catch (...) {
+        delete W;
+        throw;
+    }
+    return W;
+}
+
+// Per-instance solver state kept on the host.
+struct Inst {
+    int status = -1;  // -1 while running, else a PDLP_STATUS_* value
+    long long n_outer = 0, kkt_passes = 1, r_i = 0, r_ii = 0, r_iii = 0;
+    double mu_ref = INFINITY, mu_c_prev = INFINITY;
+    bool have = false;  // a candidate has been evaluated for termination
+    int out_sel = 0;    // its buffers: 0 current iterate, 1 average
+    // flags of the current round
+    bool full = false, art = false, capchk = false, chk = false, use_cur = false;
+    double mu_c = 0.0;
+};
+
+struct KktHost {
+    double pres_abs, pres_rel, dres_abs, dres_rel, pobj, dobj, gap;
+};
+
+KktHost kkt_from(const double *v, double off) {
+    KktHost k;
+    k.pres_abs = v[0];
+    k.pres_rel = v[1];
+    k.dres_abs = v[2];
+    k.dres_rel = v[3];
+    k.pobj = v[4] + off;
+    k.dobj = v[5] + off;
+    const double den = std::fabs(k.pobj) + std::fabs(k.dobj);
+    k.gap = den > 0.0 ? std::fabs(k.pobj - k.dobj) / den : 0.0;
+    if (v[6] > 0.0) k.gap = NAN;
+    return k;
+}
+
+bool met(const pdlp_params &prm, const KktHost &k) {
+    return k.pres_rel <= prm.eps_feas && k.dres_rel <= prm.eps_feas && k.gap <= prm.eps_gap;
+}
+
+class BatchSolver {
+  public:
+    BatchSolver(pdlp_batch *b, const pdlp_params &prm) : b_(b), P_(b->P), W_(*b->W), prm_(prm) {}
+
+    void run(pdlp_result *res, double *x_host, double *y_host, double *r_host) {
+        const double t0 = now_s();
+        rc_mode_ = prm_.reduced_cost_mode >= 0 ? prm_.reduced_cost_mode : 1;
+        init();
+        const double t_setup = now_s() - t0;
+        const long long max_k = prm_.max_iters;
+        // termination check at k = 0
+        for (int i = 0; i < B(); ++i) mask(MASK_KKT)[i] = 1, W_.sel_h[i] = 0;
+        eval_kkt();
+        for (int i = 0; i < B(); ++i) {
+            inst_[i].have = true;
+            inst_[i].out_sel = 0;
+            if (met(prm_, kkt_[i])) inst_[i].status = PDLP_STATUS_OPTIMAL;
+            else if (max_k == 0) inst_[i].status = PDLP_STATUS_ITERATION_LIMIT;
+        }
+        while (any_running()) {
+            if (now_s() - t0 >= prm_.time_limit) {
+                for (auto &s : inst_)
+                    if (s.status < 0) s.status = PDLP_STATUS_TIME_LIMIT;
+                break;
+            }
+            run_round(max_k);
+            check_round(max_k);
+        }
+        finish(res, x_host, y_host, r_host, now_s() - t0, t_setup);
+    }
+
+  private:
+    pdlp_batch *b_;
+    pdlp_problem *P_;
+    BatchWork &W_;
+    pdlp_params prm_;
+    int rc_mode_ = 1;
+    std::vector<Inst> inst_;
+    std::vector<KktHost> kkt_;
+
+    int B() const { return b_->B; }
+    hipStream_t s() const { return P_->stream; }
+    int32_t *mask(int k) const { return W_.mask_h + (size_t)k * b_->B; }
+    const int32_t *mask_dev(int k) const { return W_.mask_d + (size_t)k * b_->B; }
+    bool any_running() const {
+        for (const auto &s : inst_)
+            if (s.status < 0) return true;
+        return false;
+    }
+    const double *X() const { return W_.it.X[0]; }
+    const double *Y() const { return W_.it.Y[0]; }
+
+    void sync() { HIPCHECK(hipStreamSynchronize(s())); }
+    void push_ctrl() {
+        HIPCHECK(hipMemcpyAsync(W_.ctrl_d, W_.ctrl_h, sizeof(Ctrl) * B(), hipMemcpyHostToDevice,
+                                s()));
+        sync();
+    }
+    void pull_ctrl() {
+        HIPCHECK(hipMemcpyAsync(W_.ctrl_h, W_.ctrl_d, sizeof(Ctrl) * B(), hipMemcpyDeviceToHost,
+                                s()));
+        sync();
+    }
+    void push_masks() {
+        HIPCHECK(hipMemcpyAsync(W_.mask_d, W_.mask_h, sizeof(int32_t) * kMasks * B(),
+                                hipMemcpyHostToDevice, s()));
+        HIPCHECK(hipMemcpyAsync(W_.sel_d, W_.sel_h, sizeof(int32_t) * B(), hipMemcpyHostToDevice,
+                                s()));
+        sync();
+    }
+    void push_doubles(double *d, const double *h) {
+        HIPCHECK(hipMemcpyAsync(d, h, sizeof(double) * B(), hipMemcpyHostToDevice, s()));
+        sync();
+    }
+    void pull_out(int nv) {
+        HIPCHECK(hipMemcpyAsync(W_.out_h, W_.out_d, sizeof(double) * nv * B(),
+                                hipMemcpyDeviceToHost, s()));
+        sync();
+    }
+    void pull_gaps(int slots) {
+        HIPCHECK(hipMemcpyAsync(W_.gs_h, W_.gs_d, sizeof(GapState) * slots * B(),
+                                hipMemcpyDeviceToHost, s()));
+        sync();
+    }
+
+    // Algorithm 1 initialization per instance (the single-LP readings:
+    // eta_hat = 1 / max |scaled A entry|, omega = ||c|| / ||Combine(lc, uc)||,
+    // x = proj_X(0), y = 0).
+    void init() {
+        const BatchMaps &bm = b_->bm;
+        const Vecs v = P_->scaled();
+        inst_.assign(B(), Inst());
+        kkt_.assign(B(), KktHost{});
+        HIPCHECK(pdlp::launch_b_norms(s(), P_->A, P_->AT, bm, nullptr, 3, nullptr, nullptr, nullptr,
+                                      nullptr, v, W_.part_chk, 1u, W_.out_d));
+        pull_out(2);
+        std::vector<double> amax(B());
+        for (int i = 0; i < B(); ++i) amax[i] = W_.out_h[2 * i];
+        HIPCHECK(pdlp::launch_b_norms(s(), P_->A, P_->AT, bm, nullptr, 2, nullptr, nullptr, nullptr,
+                                      nullptr, v, W_.part_chk, 0u, W_.out_d));
+        pull_out(2);
+        std::memset(W_.ctrl_h, 0, sizeof(Ctrl) * B());
+        for (int i = 0; i < B(); ++i) {
+            const double nc = std::sqrt(W_.out_h[2 * i]), nb = std::sqrt(W_.out_h[2 * i + 1]);
+            Ctrl &c = W_.ctrl_h[i];
+            c.omega = (nc > 0.0 && nb > 0.0) ? nc / nb : 1.0;
+            c.eta = c.eta_hat = amax[i] > 0.0 ? 1.0 / amax[i] : 1.0;
+            c.red_exp = prm_.red_exp;
+            c.grow_exp = prm_.grow_exp;
+            c.need_primal = 1;
+        }
+        const int64_t M = P_->m, N = P_->n;
+        HIPCHECK(pdlp::launch_clamp0(s(), (int)N, P_->lvs, P_->uvs, W_.it.X[0]));
+        HIPCHECK(pdlp::launch_fill(s(), M, W_.it.Y[0], 0.0));
+        HIPCHECK(pdlp::launch_spmv_plain(s(), P_->A, W_.it.X[0], W_.it.AX[0]));
+        HIPCHECK(pdlp::launch_spmv_plain(s(), P_->AT, W_.it.Y[0], W_.it.ATY[0]));
+        HIPCHECK(pdlp::launch_copy(s(), N, W_.it.X[0], W_.x0));
+        HIPCHECK(pdlp::launch_copy(s(), M, W_.it.Y[0], W_.y0));
+        HIPCHECK(pdlp::launch_fill(s(), N, W_.it.sx, 0.0));
+        HIPCHECK(pdlp::launch_fill(s(), M, W_.it.sy, 0.0));
+        sync();
+    }
+
+    // Termination sums for the instances of MASK_KKT at the points chosen by sel.
+    void eval_kkt() {
+        push_masks();
+        const double *p0[4] = {W_.it.X[0], W_.it.Y[0], W_.it.AX[0], W_.it.ATY[0]};
+        const double *p1[4] = {W_.xb, W_.yb, W_.axb, W_.atyb};
+        const Vecs orig{P_->c, P_->lc, P_->uc, P_->lv, P_->uv};
+        HIPCHECK(pdlp::launch_b_kkt(s(), P_->A, P_->AT, b_->bm, mask_dev(MASK_KKT), W_.sel_d, p0, p1,
+                                    P_->d1, P_->d2, orig, rc_mode_, W_.part_chk, W_.out_d, nullptr,
+                                    nullptr, nullptr));
+        pull_out(7);
+        for (int i = 0; i < B(); ++i)
+            if (mask(MASK_KKT)[i]) kkt_[i] = kkt_from(W_.out_h + 7 * i, b_->obj_offset[i]);
+    }
+
+    // Every running instance advances to its next block boundary.
+    void run_round(long long max_k) {
+        const long long ce = prm_.check_every;
+        long long rem = 0;
+        for (int i = 0; i < B(); ++i) {
+            Ctrl &c = W_.ctrl_h[i];
+            c.block_acc = 0;
+            c.run_at = 0;
+            c.cur = 0;
+            c.pending_sy = 0;
+            if (inst_[i].status >= 0) {
+                c.block_target = 0;
+                c.stop = 1;
+                c.need_primal = 0;
+                continue;
+            }
+            long long kb = (c.k / ce + 1) * ce;
+            kb = std::min(kb, next_art(c.k, c.t, prm_.beta_art, max_k));
+            kb = std::min(kb, max_k);
+            c.block_target = kb - c.k;
+            c.stop = 0;
+            c.need_primal = 1;
+            rem = std::max(rem, c.block_target);
+        }
+        push_ctrl();
+        const BatchMaps &bm = b_->bm;
+        const Vecs v = P_->scaled();
+        while (rem > 0) {
+            long long n_att = rem + rem / 8 + 1;
+            if (n_att > 4096) n_att = 4096;
+            for (long long a = 0; a < n_att; ++a)
+                HIPCHECK(pdlp::launch_b_attempt(s(), P_->A, P_->AT, v, W_.it, W_.ctrl_d, bm,
+                                                W_.part_dual, W_.part_ps, W_.part_pf));
+            pull_ctrl();
+            rem = 0;
+            for (int i = 0; i < B(); ++i) {
+                const Ctrl &c = W_.ctrl_h[i];
+                if (inst_[i].status < 0 && !c.stop) rem = std::max(rem, c.block_target - c.block_acc);
+            }
+            if (rem == 0) {
+                // instances still running with nothing left cannot exist: stop is set
+                // exactly when block_acc reaches the target
+                break;
+            }
+        }
+        HIPCHECK(pdlp::launch_b_settle(s(), P_->A, P_->AT, W_.it, W_.ctrl_d, bm));
+        sync();
+        for (int i = 0; i < B(); ++i) {
+            Ctrl &c = W_.ctrl_h[i];
+            c.cur = 0;
+            c.pending_sy = 0;
+            if (inst_[i].status >= 0) continue;
+            inst_[i].kkt_passes += c.block_acc;
+            if (c.numerr) inst_[i].status = PDLP_STATUS_NUMERICAL_ERROR;
+        }
+    }
+
+    // Periodic checks of Section 3 for the instances at a boundary.
+    void check_round(long long max_k) {
+        const BatchMaps &bm = b_->bm;
+        const Vecs v = P_->scaled();
+        bool any = false;
+        for (int i = 0; i < B(); ++i) {
+            Inst &st = inst_[i];
+            const Ctrl &c = W_.ctrl_h[i];
+            st.chk = false;
+            for (int k = 0; k < kMasks; ++k) mask(k)[i] = 0;
+            if (st.status >= 0) continue;
+            st.full = (c.k % prm_.check_every) == 0;
+            st.art = (double)c.t >= prm_.beta_art * (double)c.k;
+            st.capchk = c.k == max_k;
+            st.chk = st.full || st.art || st.capchk;
+            mask(MASK_CHK)[i] = st.chk;
+            W_.sv_h[i] = c.seta > 0.0 ? c.seta : 1.0;
+            W_.om_h[i] = c.omega;
+            any = any || st.chk;
+        }
+        if (!any) return;
+        push_masks();
+        push_doubles(W_.sv_d, W_.sv_h);
+        push_doubles(W_.om_d, W_.om_h);
+        const DCsr &A = P_->A, &AT = P_->AT;
+        const int32_t *mchk = mask_dev(MASK_CHK);
+        // average and its products
+        HIPCHECK(pdlp::launch_b_elementwise(s(), A, AT, bm, mchk, 0, W_.sv_d, W_.it.sx, W_.xb,
+                                            W_.it.sy, W_.yb));
+        HIPCHECK(pdlp::launch_b_spmv_plain(s(), A, bm.ablk_inst, mchk, W_.xb, W_.axb));
+        HIPCHECK(pdlp::launch_b_spmv_plain(s(), AT, bm.tblk_inst, mchk, W_.yb, W_.atyb));
+        // mu(z, z0) and mu(z_bar, z0)
+        HIPCHECK(pdlp::launch_b_gap(s(), A, AT, bm, mchk, v, W_.it.X[0], W_.it.Y[0], W_.it.AX[0],
+                                    W_.it.ATY[0], W_.x0, W_.y0, W_.om_d, W_.part_chk, W_.gs_d,
+                                    kBatchGapSteps));
+        HIPCHECK(pdlp::launch_b_gap(s(), A, AT, bm, mchk, v, W_.xb, W_.yb, W_.axb, W_.atyb, W_.x0,
+                                    W_.y0, W_.om_d, W_.part_chk, W_.gs_d + B(), kBatchGapSteps));
+        pull_gaps(2);
+        bool any_kkt = false;
+        for (int i = 0; i < B(); ++i) {
+            Inst &st = inst_[i];
+            if (!st.chk) continue;
+            st.kkt_passes += 1;
+            const double mu_cur = W_.gs_h[i].mu, mu_avg = W_.gs_h[B() + i].mu;
+            if (!std::isfinite(mu_cur) || !std::isfinite(mu_avg)) {
+                st.status = PDLP_STATUS_NUMERICAL_ERROR;
+                st.chk = false;
+                continue;
+            }
+            st.use_cur = mu_cur < mu_avg;  // a tie goes to the average
+            st.mu_c = st.use_cur ? mu_cur : mu_avg;
+            W_.sel_h[i] = st.use_cur ? 0 : 1;
+            if (st.full || st.capchk) {
+                mask(MASK_KKT)[i] = 1;
+                any_kkt = true;
+            }
+        }
+        if (any_kkt) {
+            eval_kkt();
+            for (int i = 0; i < B(); ++i) {
+                Inst &st = inst_[i];
+                if (!mask(MASK_KKT)[i]) continue;
+                st.have = true;
+                st.out_sel = W_.sel_h[i];
+                if (prm_.verbose)
+                    std::fprintf(stderr, "[pdlp batch %d] k=%lld gap=%.2e pres=%.2e dres=%.2e\n", i,
+                                 W_.ctrl_h[i].k, kkt_[i].gap, kkt_[i].pres_rel, kkt_[i].dres_rel);
+                if (!std::isfinite(kkt_[i].gap)) {
+                    st.status = PDLP_STATUS_NUMERICAL_ERROR;
+                } else if (met(prm_, kkt_[i])) {
+                    st.status = PDLP_STATUS_OPTIMAL;
+                } else if (st.capchk) {
+                    st.status = PDLP_STATUS_ITERATION_LIMIT;
+                }
+                if (st.status >= 0) st.chk = false;
+            }
+        }
+        // restart decisions (criteria (i)-(iii))
+        bool any_rst = false;
+        for (int i = 0; i < B(); ++i) {
+            Inst &st = inst_[i];
+            if (!st.chk) continue;
+            int why = 0;
+            if (!prm_.adaptive_restarts || st.n_outer == 0) {
+                if (st.art) why = 3;
+            } else {
+                if (st.full && st.mu_c <= prm_.beta_suff * st.mu_ref) why = 1;
+                else if (st.full && st.mu_c <= prm_.beta_nec * st.mu_ref && st.mu_c > st.mu_c_prev)
+                    why = 2;
+                else if (st.art) why = 3;
+            }
+            if (!why) {
+                if (st.full) st.mu_c_prev = st.mu_c;
+                continue;
+            }
+            st.r_i += why == 1;
+            st.r_ii += why == 2;
+            st.r_iii += why == 3;
+            mask(MASK_RST)[i] = 1;
+            mask(MASK_RST_AVG)[i] = !st.use_cur;
+            any_rst = true;
+        }
+        if (!any_rst) return;
+        push_masks();
+        const int32_t *mr = mask_dev(MASK_RST), *ma = mask_dev(MASK_RST_AVG);
+        Iter &it = W_.it;
+        // z_prev0 = z0; z = z0 = candidate (with its products)
+        HIPCHECK(pdlp::launch_b_elementwise(s(), A, AT, bm, mr, 1, nullptr, W_.x0, W_.xp, W_.y0,
+                                            W_.yp));
+        HIPCHECK(pdlp::launch_b_elementwise(s(), A, AT, bm, ma, 1, nullptr, W_.xb, it.X[0], W_.yb,
+                                            it.Y[0]));
+        HIPCHECK(pdlp::launch_b_elementwise(s(), A, AT, bm, ma, 1, nullptr, W_.atyb, it.ATY[0],
+                                            W_.axb, it.AX[0]));
+        HIPCHECK(pdlp::launch_b_elementwise(s(), A, AT, bm, mr, 1, nullptr, it.X[0], W_.x0,
+                                            it.Y[0], W_.y0));
+        // primal weight update (Algorithm 3)
+        HIPCHECK(pdlp::launch_b_norms(s(), A, AT, bm, mr, 0, W_.x0, W_.xp, W_.y0, W_.yp, v,
+                                      W_.part_chk, 0u, W_.out_d));
+        pull_out(2);
+        const double ez = prm_.eps_zero;
+        for (int i = 0; i < B(); ++i) {
+            if (!mask(MASK_RST)[i]) continue;
+            Inst &st = inst_[i];
+            Ctrl &c = W_.ctrl_h[i];
+            const double dx = std::sqrt(W_.out_h[2 * i]), dy = std::sqrt(W_.out_h[2 * i + 1]);
+            if (dx > ez && dx < 1.0 / ez && dy > ez && dy < 1.0 / ez)
+                c.omega = std::exp(prm_.theta * std::log(dy / dx) +
+                                   (1.0 - prm_.theta) * std::log(c.omega));
+            st.n_outer += 1;
+            c.t = 0;
+            c.seta = 0.0;
+            W_.om_h[i] = c.omega;
+        }
+        push_doubles(W_.om_d, W_.om_h);
+        HIPCHECK(pdlp::launch_b_elementwise(s(), A, AT, bm, mr, 2, W_.zero_d, nullptr, it.sx,
+                                            nullptr, it.sy));
+        // mu_ref = mu(z0, z_prev0) under the new primal weight
+        HIPCHECK(pdlp::launch_b_gap(s(), A, AT, bm, mr, v, W_.x0, W_.y0, it.AX[0], it.ATY[0], W_.xp,
+                                    W_.yp, W_.om_d, W_.part_chk, W_.gs_d + 2 * (size_t)B(),
+                                    kBatchGapSteps));
+        pull_gaps(3);
+        for (int i = 0; i < B(); ++i) {
+            if (!mask(MASK_RST)[i]) continue;
+            inst_[i].mu_ref = W_.gs_h[2 * (size_t)B() + i].mu;
+            inst_[i].mu_c_prev = INFINITY;
+        }
+    }
+
+    // Final evaluation on each instance's output point, unscaled outputs.
+    void finish(pdlp_result *res, double *x_host, double *y_host, double *r_host, double secs,
+                double setup) {
+        for (int i = 0; i < B(); ++i) {
+            const Inst &st = inst_[i];
+            mask(MASK_KKT)[i] = 1;
+            const bool cand = st.have && st.status != PDLP_STATUS_NUMERICAL_ERROR;
+            W_.sel_h[i] = cand ? st.out_sel : 0;
+        }
+        push_masks();
+        const double *p0[4] = {W_.it.X[0], W_.it.Y[0], W_.it.AX[0], W_.it.ATY[0]};
+        const double *p1[4] = {W_.xb, W_.yb, W_.axb, W_.atyb};
+        const Vecs orig{P_->c, P_->lc, P_->uc, P_->lv, P_->uv};
+        HIPCHECK(pdlp::launch_b_kkt(s(), P_->A, P_->AT, b_->bm, mask_dev(MASK_KKT), W_.sel_d, p0,
+                                    p1, P_->d1, P_->d2, orig, rc_mode_, W_.part_chk, W_.out_d,
+                                    W_.ro, W_.xo, W_.yo));
+        pull_out(7);
+        const int64_t M = P_->m, N = P_->n;
+        if (x_host && N > 0)
+            HIPCHECK(hipMemcpyAsync(x_host, W_.xo, sizeof(double) * N, hipMemcpyDeviceToHost, s()));
+        if (y_host && M > 0)
+            HIPCHECK(hipMemcpyAsync(y_host, W_.yo, sizeof(double) * M, hipMemcpyDeviceToHost, s()));
+        if (r_host && N > 0)
+            HIPCHECK(hipMemcpyAsync(r_host, W_.ro, sizeof(double) * N, hipMemcpyDeviceToHost, s()));
+        sync();
+        for (int i = 0; i < B(); ++i) {
+            const Inst &st = inst_[i];
+            const Ctrl &c = W_.ctrl_h[i];
+            const KktHost k = kkt_from(W_.out_h + 7 * i, b_->obj_offset[i]);
+            pdlp_result &r = res[i];
+            std::memset(&r, 0, sizeof r);
+            r.status = st.status >= 0 ? st.status : PDLP_STATUS_ITERATION_LIMIT;
+            r.iterations = c.k;
+            r.attempts = c.attempts;
+            r.kkt_passes = st.kkt_passes;
+            r.restarts_i = st.r_i;
+            r.restarts_ii = st.r_ii;
+            r.restarts_iii = st.r_iii;
+            r.restarts = st.r_i + st.r_ii + st.r_iii;
+            r.primal_obj = k.pobj;
+            r.dual_obj = k.dobj;
+            r.rel_gap = k.gap;
+            r.primal_res_abs = k.pres_abs;
+            r.primal_res_rel = k.pres_rel;
+            r.dual_res_abs = k.dres_abs;
+            r.dual_res_rel = k.dres_rel;
+            r.omega = c.omega;
+            r.eta = c.eta_hat;
+            r.seconds = secs;
+            r.seconds_setup = setup;
+        }
+    }
+};
+
+void build_maps(pdlp_batch *b) {
+    pdlp_problem *P = b->P;
+    const int B = b->B;
+    const std::vector<int32_t> &ba = P->blkA, &bt = P->blkT;
+    const int nA = (int)ba.size() - 1, nT = (int)bt.size() - 1;
+    std::vector<int32_t> ainst(std::max(nA, 1)), tinst(std::max(nT, 1)), aoff(B + 1), toff(B + 1);
+    auto inst_of = [](const std::vector<int32_t> &off, int32_t r) {
+        return (int32_t)(std::upper_bound(off.begin(), off.end(), r) - off.begin()) - 1;
+    };
+    for (int k = 0; k < nA; ++k) ainst[k] = inst_of(b->roff, ba[k]);
+    for (int k = 0; k < nT; ++k) tinst[k] = inst_of(b->coff, bt[k]);
+    for (int i = 0; i <= B; ++i) {
+        aoff[i] = (int32_t)(std::lower_bound(ba.begin(), ba.end() - 1, b->roff[i]) - ba.begin());
+        toff[i] = (int32_t)(std::lower_bound(bt.begin(), bt.end() - 1, b->coff[i]) - bt.begin());
+    }
+    aoff[B] = nA;
+    toff[B] = nT;
+    // every block lies inside its instance
+    for (int k = 0; k < nA; ++k)
+        if (ba[k + 1] > b->roff[ainst[k] + 1] || k < aoff[ainst[k]] || k >= aoff[ainst[k] + 1])
+            throw LibError(PDLP_ERR_HIP, "internal: row block crosses an instance boundary");
+    for (int k = 0; k < nT; ++k)
+        if (bt[k + 1] > b->coff[tinst[k] + 1] || k < toff[tinst[k]] || k >= toff[tinst[k] + 1])
+            throw LibError(PDLP_ERR_HIP, "internal: column block crosses an instance boundary");
+    Arena &a = b->arena;
+    int32_t *d_ai = a.dev<int32_t>(ainst.size()), *d_ti = a.dev<int32_t>(tinst.size());
+    int32_t *d_ao = a.dev<int32_t>(B + 1), *d_to = a.dev<int32_t>(B + 1);
+    hipStream_t s = P->stream;
+    HIPCHECK(hipMemcpyAsync(d_ai, ainst.data(), sizeof(int32_t) * ainst.size(), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(d_ti, tinst.data(), sizeof(int32_t) * tinst.size(), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(d_ao, aoff.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(d_to, toff.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    b->bm.B = B;
+    b->bm.nA = nA;
+    b->bm.nT = nT;
+    b->bm.ablk_inst = d_ai;
+    b->bm.tblk_inst = d_ti;
+    b->bm.ablk_off = d_ao;
+    b->bm.tblk_off = d_to;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdlp_batch_create(int32_t count, const int32_t *m, const int32_t *n, const int64_t *nnz,
+                      const int32_t *row_ptr, const int32_t *col, const double *val,
+                      const double *c, const double *lc, const double *uc, const double *lv,
+                      const double *uv, const double *obj_offset, const pdlp_params *params,
+                      void *hip_stream, pdlp_batch **out) {
+    return guarded([&] {
+        if (!out) invalid("out is NULL");
+        *out = nullptr;
+        if (count < 1) invalid("count must be >= 1");
+        if (!m || !n || !nnz || !row_ptr) invalid("NULL size array");
+        int64_t M = 0, N = 0, NZ = 0;
+        for (int32_t i = 0; i < count; ++i) {
+            if (m[i] < 0 || n[i] < 1 || nnz[i] < 0)
+                invalid("instance " + std::to_string(i) + ": need m >= 0, n >= 1, nnz >= 0");
+            M += m[i];
+            N += n[i];
+            NZ += nnz[i];
+        }
+        const int64_t lim = std::numeric_limits<int32_t>::max();
+        if (M >= lim || N >= lim || NZ >= lim) invalid("batch totals must stay below 2^31");
+        if ((NZ > 0 && (!col || !val)) || !c || (M > 0 && (!lc || !uc)) || !lv || !uv)
+            invalid("NULL input array");
+        // per-instance checks, then pack: global row pointers and column labels
+        std::vector<int32_t> rp((size_t)M + 1), cg((size_t)NZ);
+        std::vector<int32_t> roff(count + 1), coff(count + 1);
+        std::vector<int32_t> row_breaks, col_breaks;
+        int64_t r0 = 0, c0 = 0, e0 = 0, p0 = 0;
+        rp[0] = 0;
+        for (int32_t i = 0; i < count; ++i) {
+            const int32_t *rpi = row_ptr + p0;
+            try {
+                validate(m[i], n[i], nnz[i], rpi, NZ > 0 ? col + e0 : nullptr,
+                         NZ > 0 ? val + e0 : nullptr, c + c0, M > 0 ? lc + r0 : nullptr,
+                         M > 0 ? uc + r0 : nullptr, lv + c0, uv + c0);
+            } catch (const LibError &e) {
+                throw LibError(e.code, "instance " + std::to_string(i) + ": " + e.what());
+            }
+            for (int64_t e = 0; e < nnz[i]; ++e) cg[e0 + e] = (int32_t)(col[e0 + e] + c0);
+            for (int32_t r = 0; r < m[i]; ++r) rp[r0 + r + 1] = (int32_t)(e0 + rpi[r + 1]);
+            roff[i] = (int32_t)r0;
+            coff[i] = (int32_t)c0;
+            row_breaks.push_back((int32_t)r0);
+            col_breaks.push_back((int32_t)c0);
+            r0 += m[i];
+            c0 += n[i];
+            e0 += nnz[i];
+            p0 += (int64_t)m[i] + 1;
+        }
+        roff[count] = (int32_t)M;
+        coff[count] = (int32_t)N;
+        auto *b = new pdlp_batch();
+        try {
+            b->B = count;
+            b->m.assign(m, m + count);
+            b->n.assign(n, n + count);
+            b->roff = roff;
+            b->coff = coff;
+            b->obj_offset.assign(count, 0.0);
+            if (obj_offset)
+                for (int32_t i = 0; i < count; ++i) {
+                    if (!std::isfinite(obj_offset[i])) invalid("objective offset must be finite");
+                    b->obj_offset[i] = obj_offset[i];
+                }
+            b->P = create_problem((int32_t)M, (int32_t)N, NZ, rp.data(), cg.data(), val, c, lc, uc,
+                                  lv, uv, 0.0, params, hip_stream, &row_breaks, &col_breaks, true);
+            build_maps(b);
+        } catch (...) {
+            delete b;
+            throw;
+        }
+        *out = b;
+    });
+}
+
+void pdlp_batch_destroy(pdlp_batch *b) { delete b; }
+
+int pdlp_batch_dims(const pdlp_batch *b, int32_t *count, int64_t *m_total, int64_t *n_total,
+                    int64_t *nnz_total) {
+    return guarded([&] {
+        if (!b) invalid("batch is NULL");
+        if (count) *count = b->B;
+        if (m_total) *m_total = b->P->m;
+        if (n_total) *n_total = b->P->n;
+        if (nnz_total) *nnz_total = b->P->nnz;
+    });
+}
+
+int pdlp_batch_solve(pdlp_batch *b, const pdlp_params *params, pdlp_result *results, double *x,
+                     double *y, double *r) {
+    return guarded([&] {
+        if (!b || !results) invalid("NULL argument");
+        pdlp_params prm;
+        pdlp_params_default(&prm);
+        if (params) prm = *params;
+        check_params(prm);
+        if (prm.polish) invalid("feasibility polishing is not available for batches");
+        if (!b->W) b->W = make_work(b);
+        BatchSolver solver(b, prm);
+        solver.run(results, x, y, r);
+    });
+}
+
+}  // extern "C"

@@ -130,6 +130,12 @@ inline void check_params(const pdlp_params &p) {
     if (!(p.beta_art > 0.0)) invalid("beta_art must be > 0");
 }
 
+// Input checks of a problem (conventions of the C ABI); throws
+// INVALID_ARGUMENT with a message naming the offending row or column.
+void validate(int32_t m, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
+              const double *val, const double *c, const double *lc, const double *uc,
+              const double *lv, const double *uv);
+
 // Smallest k' > k with (double)(t + k' - k) >= beta * (double)k' (restart
 // condition (iii) of Section 3), capped at cap.
 long long next_art(long long k, long long t, double beta, long long cap);
@@ -170,4 +176,4 @@ pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *r
                              const double *lc, const double *uc, const double *lv,
                              const double *uv, double obj_offset, const pdlp_params *params,
                              void *hip_stream, const std::vector<int32_t> *row_breaks,
-                             const std::vector<int32_t> *col_breaks);
+                             const std::vector<int32_t> *col_breaks, bool validated = false);

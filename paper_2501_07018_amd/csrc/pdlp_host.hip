@@ -107,12 +107,10 @@ std::vector<int32_t> order_by_count(const std::vector<int32_t> &cnt, bool reorde
 
 // ===================================================================== problem
 
-
-namespace {
-
-void validate(int32_t m, int32_t n, int64_t nnz, const int32_t *rp, const int32_t *col,
-              const double *val, const double *c, const double *lc, const double *uc,
-              const double *lv, const double *uv) {
+void pdlp::host::validate(int32_t m, int32_t n, int64_t nnz, const int32_t *rp,
+                          const int32_t *col, const double *val, const double *c,
+                          const double *lc, const double *uc, const double *lv,
+                          const double *uv) {
     if (m < 0 || n < 1) invalid("need m >= 0 and n >= 1");
     if (nnz < 0 || nnz > (int64_t)std::numeric_limits<int32_t>::max())
         invalid("nnz must lie in [0, 2^31)");
@@ -143,6 +141,8 @@ void validate(int32_t m, int32_t n, int64_t nnz, const int32_t *rp, const int32_
         if (lc[i] > uc[i]) invalid("lc > uc for row " + std::to_string(i));
     }
 }
+
+namespace {
 
 std::vector<int32_t> upload_blocks(pdlp_problem *P, DCsr &M, const int32_t *rp_host,
                                    const std::vector<int32_t> *breaks = nullptr) {
@@ -792,8 +792,8 @@ pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *r
                              const double *lc, const double *uc, const double *lv,
                              const double *uv, double obj_offset, const pdlp_params *params,
                              void *hip_stream, const std::vector<int32_t> *row_breaks,
-                             const std::vector<int32_t> *col_breaks) {
-        validate(m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv);
+                             const std::vector<int32_t> *col_breaks, bool validated) {
+        if (!validated) validate(m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv);
         if (!std::isfinite(obj_offset)) invalid("objective offset must be finite");
         pdlp_params prm;
         pdlp_params_default(&prm);

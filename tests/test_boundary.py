@@ -89,3 +89,32 @@ def test_params_defaults_are_the_papers_constants():
     assert (p.beta_suff, p.beta_nec, p.beta_art) == (0.1, 0.9, 0.5)
     assert (p.theta, p.eps_zero, p.red_exp, p.grow_exp) == (0.5, 1e-10, 0.3, 0.6)
     assert p.polish_first == 100
+
+
+class _Obj:
+    def __init__(self, d):
+        self.__dict__.update(d)
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda d: d.update(col=np.array([0, 3, 1], np.int32)), "out of range"),
+    (lambda d: d.update(col=np.array([2, 0, 1], np.int32)), "increasing"),
+    (lambda d: d.update(val=np.array([1.0, np.nan, 3.0])), "non-finite"),
+    (lambda d: d.update(lc=np.array([2.0, -np.inf])), "lc > uc"),
+    (lambda d: d.update(row_ptr=np.array([0, 3, 2], np.int32)), "nondecreasing"),
+    (lambda d: d.update(row_ptr=np.array([1, 2, 3], np.int32)), "row_ptr[0]"),
+])
+def test_invalid_batches_name_the_instance_before_gpu_work(mutate, msg):
+    good, bad = _tiny(), _tiny()
+    mutate(bad)
+    with pytest.raises(pd.PdlpError) as ei:
+        pd.pdlp_batch_create([_Obj(good), _Obj(bad), _Obj(_tiny())])
+    assert ei.value.code == pd.PDLP_ERR_INVALID_ARGUMENT
+    assert "instance 1: " in str(ei.value) and msg in str(ei.value)
+
+
+def test_empty_batch_is_rejected():
+    h = C.c_void_p()
+    rc = pd.lib().pdlp_batch_create(0, None, None, None, None, None, None, None, None, None,
+                                    None, None, None, None, None, C.byref(h))
+    assert rc == pd.PDLP_ERR_INVALID_ARGUMENT and not h.value
