@@ -270,6 +270,18 @@ int pdlp_batch_dims(const pdlp_batch *b, int32_t *count, int64_t *m_total, int64
 int pdlp_batch_solve(pdlp_batch *b, const pdlp_params *params, pdlp_result *results, double *x,
                      double *y, double *r);
 
+/* Where the time of the last pdlp_batch_solve went.  A round advances every
+ * unfinished instance to its next iteration-block boundary (step seconds),
+ * then runs the checks of the instances at a boundary (check seconds). */
+typedef struct pdlp_batch_stats {
+    int64_t rounds;            /* iteration blocks run */
+    int64_t attempt_launches;  /* step attempts enqueued (each serves every instance) */
+    int64_t max_iterations;    /* accepted steps of the slowest instance */
+    int64_t total_iterations;  /* accepted steps summed over instances */
+    double seconds, setup_seconds, step_seconds, check_seconds;
+} pdlp_batch_stats;
+int pdlp_batch_get_stats(const pdlp_batch *b, pdlp_batch_stats *stats);
+
 /* Message for the last error on this thread ("" if none). */
 const char *pdlp_last_error(void);
 

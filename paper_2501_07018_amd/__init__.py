@@ -81,6 +81,13 @@ class DeviceRates(C.Structure):
                 ("gather_l2_gps", C.c_double)]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("rounds", C.c_int64), ("attempt_launches", C.c_int64),
+                ("max_iterations", C.c_int64), ("total_iterations", C.c_int64),
+                ("seconds", C.c_double), ("setup_seconds", C.c_double),
+                ("step_seconds", C.c_double), ("check_seconds", C.c_double)]
+
+
 class StateBlob(C.Structure):
     _fields_ = [(k, D) for k in ("x", "y", "ax", "aty", "x0", "y0", "sx", "sy")] + \
                [(k, C.c_double) for k in ("seta", "omega", "eta_hat", "mu_ref", "mu_c_prev",
@@ -96,7 +103,7 @@ EXPORTS = ("pdlp_problem_create", "pdlp_problem_destroy", "pdlp_problem_dims",
            "pdlp_state_create", "pdlp_state_destroy", "pdlp_iterate_k", "pdlp_state_get",
            "pdlp_state_set", "pdlp_norm_gap", "pdlp_last_error", "pdlp_state_solve",
            "pdlp_state_kernel_stats", "pdlp_measure_device_rates", "pdlp_batch_create",
-           "pdlp_batch_destroy", "pdlp_batch_dims", "pdlp_batch_solve")
+           "pdlp_batch_destroy", "pdlp_batch_dims", "pdlp_batch_solve", "pdlp_batch_get_stats")
 
 
 def lib() -> C.CDLL:
@@ -136,6 +143,7 @@ def lib() -> C.CDLL:
     L.pdlp_batch_destroy.restype = None
     L.pdlp_batch_dims.argtypes = [vp, I32, I64, I64, I64]
     L.pdlp_batch_solve.argtypes = [vp, C.POINTER(Params), C.POINTER(Result), D, D, D]
+    L.pdlp_batch_get_stats.argtypes = [vp, C.POINTER(BatchStats)]
     L.pdlp_last_error.argtypes = []
     L.pdlp_last_error.restype = C.c_char_p
     _lib = L
@@ -348,6 +356,12 @@ def pdlp_batch_solve(h, params: Params | None = None, want_solution=True):
     return out, x, y, r
 
 
+def pdlp_batch_get_stats(h) -> dict:
+    st = BatchStats()
+    _check(lib().pdlp_batch_get_stats(h, C.byref(st)))
+    return {f: getattr(st, f) for f, _ in BatchStats._fields_}
+
+
 class Batch:
     """Owner of a batch handle; solve() returns per-instance result dicts with
     the instance's x, y, r split out of the concatenated outputs."""
@@ -367,6 +381,9 @@ class Batch:
                 d["r"] = r[co[i]:co[i + 1]]
                 d["y"] = y[ro[i]:ro[i + 1]]
         return res
+
+    def stats(self) -> dict:
+        return pdlp_batch_get_stats(self.h)
 
     def close(self):
         if self.h:

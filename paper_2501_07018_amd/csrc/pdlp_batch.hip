@@ -36,8 +36,10 @@ using pdlp::Vecs;
 
 namespace {
 
-// Active-set steps per normalized-duality-gap evaluation.
+// Active-set steps per normalized-duality-gap evaluation (at most), enqueued
+// in chunks; the host stops once every evaluation of the launch has converged.
 constexpr int kBatchGapSteps = 32;
+constexpr int kBatchGapChunk = 6;
 
 // Device buffers of a batch solve, sized by the packed problem.
 struct BatchWork {
@@ -51,6 +53,7 @@ struct BatchWork {
     int32_t *mask_d, *mask_h;  // kMasks arrays of B
     int32_t *sel_d, *sel_h;
     double *sv_d, *sv_h, *om_d, *om_h, *zero_d;
+    int32_t *list_d, *list_h;  // ilist | alist | tlist | clist of the running instances
 };
 
 enum { MASK_CHK = 0, MASK_KKT, MASK_RST, MASK_RST_AVG, kMasks };
@@ -64,7 +67,9 @@ struct pdlp_batch {
     pdlp_problem *P = nullptr;
     Arena arena;
     BatchMaps bm;
+    std::vector<int32_t> aoff, toff;  // host copies of the block ranges per instance
     BatchWork *W = nullptr;
+    pdlp_batch_stats stats{};  // of the last solve
     ~pdlp_batch() {
         delete W;
         delete P;
@@ -112,6 +117,9 @@ BatchWork *make_work(pdlp_batch *b) {
         W->om_d = a.dev<double>(B);
         W->om_h = a.host<double>(B);
         W->zero_d = a.dev<double>(B);
+        const size_t nl = (size_t)B + 2 * ((size_t)b->bm.nA + b->bm.nT);
+        W->list_d = a.dev<int32_t>(nl);
+        W->list_h = a.host<int32_t>(nl);
         HIPCHECK(pdlp::launch_fill(P->stream, B, W->zero_d, 0.0));
         HIPCHECK(hipStreamSynchronize(P->stream));
     } catch (...) {
@@ -174,16 +182,30 @@ class BatchSolver {
             if (met(prm_, kkt_[i])) inst_[i].status = PDLP_STATUS_OPTIMAL;
             else if (max_k == 0) inst_[i].status = PDLP_STATUS_ITERATION_LIMIT;
         }
+        pdlp_batch_stats &st = b_->stats;
+        std::memset(&st, 0, sizeof st);
+        st.setup_seconds = t_setup;
         while (any_running()) {
             if (now_s() - t0 >= prm_.time_limit) {
                 for (auto &s : inst_)
                     if (s.status < 0) s.status = PDLP_STATUS_TIME_LIMIT;
                 break;
             }
+            set_active(false);
+            const double ta = now_s();
             run_round(max_k);
+            const double tb = now_s();
             check_round(max_k);
+            st.rounds += 1;
+            st.step_seconds += tb - ta;
+            st.check_seconds += now_s() - tb;
         }
         finish(res, x_host, y_host, r_host, now_s() - t0, t_setup);
+        for (int i = 0; i < B(); ++i) {
+            st.max_iterations = std::max<int64_t>(st.max_iterations, res[i].iterations);
+            st.total_iterations += res[i].iterations;
+        }
+        st.seconds = now_s() - t0;
     }
 
   private:
@@ -194,6 +216,81 @@ class BatchSolver {
     int rc_mode_ = 1;
     std::vector<Inst> inst_;
     std::vector<KktHost> kkt_;
+    BatchMaps bm_;       // maps with the lists of the instances launches serve
+    int listed_ = -1;    // running instances when the lists were built (-1: all)
+
+    // Lists of the instances the launches serve and of their blocks: every
+    // instance (all = true) or the running ones.  Rebuilt when that set changes.
+    void set_active(bool all) {
+        int running = 0;
+        for (const auto &st : inst_) running += st.status < 0;
+        const int want = all ? -1 : running;
+        if (want == listed_ && bm_.ilist) return;
+        const BatchMaps &base = b_->bm;
+        const int B = b_->B, nA = base.nA, nT = base.nT;
+        std::vector<int32_t> il, al, tl;
+        for (int i = 0; i < B; ++i) {
+            if (!all && inst_[i].status >= 0) continue;
+            il.push_back(i);
+            for (int k = b_->aoff[i]; k < b_->aoff[i + 1]; ++k) al.push_back(k);
+            for (int k = b_->toff[i]; k < b_->toff[i + 1]; ++k) tl.push_back(k);
+        }
+        int32_t *h = W_.list_h;
+        size_t o = 0;
+        std::copy(il.begin(), il.end(), h + o);
+        const size_t oi = o;
+        o += B;
+        std::copy(al.begin(), al.end(), h + o);
+        const size_t oa = o;
+        o += nA;
+        std::copy(tl.begin(), tl.end(), h + o);
+        const size_t ot = o;
+        o += nT;
+        const size_t oc = o;
+        std::copy(tl.begin(), tl.end(), h + o);
+        for (size_t k = 0; k < al.size(); ++k) h[o + tl.size() + k] = nT + al[k];
+        HIPCHECK(hipMemcpyAsync(W_.list_d, W_.list_h, sizeof(int32_t) * (oc + tl.size() + al.size()),
+                                hipMemcpyHostToDevice, s()));
+        sync();
+        bm_ = base;
+        bm_.ni = (int32_t)il.size();
+        bm_.na = (int32_t)al.size();
+        bm_.nt = (int32_t)tl.size();
+        bm_.nc = (int32_t)(al.size() + tl.size());
+        bm_.ilist = W_.list_d + oi;
+        bm_.alist = W_.list_d + oa;
+        bm_.tlist = W_.list_d + ot;
+        bm_.clist = W_.list_d + oc;
+        listed_ = want;
+    }
+
+    // Normalized duality gaps of up to three evaluations (slots of gs) for the
+    // instances of mask; the active-set steps run in chunks until all converged.
+    struct GapArgs {
+        const double *x, *y, *ax, *aty, *xr, *yr;
+        int slot;
+    };
+    void gaps(const GapArgs *g, int ng, int mask_k) {
+        const Vecs v = P_->scaled();
+        const int32_t *md = mask_dev(mask_k);
+        for (int q = 0; q < ng; ++q)
+            HIPCHECK(pdlp::launch_b_gap_begin(s(), P_->A, P_->AT, bm_, md, v, g[q].x, g[q].y,
+                                              g[q].ax, g[q].aty, g[q].xr, g[q].yr, W_.om_d,
+                                              W_.part_chk, W_.gs_d + (size_t)g[q].slot * B()));
+        for (int first = 0; first < kBatchGapSteps; first += kBatchGapChunk) {
+            for (int q = 0; q < ng; ++q)
+                HIPCHECK(pdlp::launch_b_gap_steps(s(), P_->A, P_->AT, bm_, md, v, g[q].x, g[q].y,
+                                                  g[q].ax, g[q].aty, W_.part_chk,
+                                                  W_.gs_d + (size_t)g[q].slot * B(), first,
+                                                  kBatchGapChunk, kBatchGapSteps));
+            pull_gaps(g[0].slot, g[ng - 1].slot - g[0].slot + 1);
+            bool open = false;
+            for (int q = 0; q < ng && !open; ++q)
+                for (int i = 0; i < B() && !open; ++i)
+                    open = mask(mask_k)[i] && W_.gs_h[(size_t)g[q].slot * B() + i].done == 0;
+            if (!open) break;
+        }
+    }
 
     int B() const { return b_->B; }
     hipStream_t s() const { return P_->stream; }
@@ -234,8 +331,9 @@ class BatchSolver {
                                 hipMemcpyDeviceToHost, s()));
         sync();
     }
-    void pull_gaps(int slots) {
-        HIPCHECK(hipMemcpyAsync(W_.gs_h, W_.gs_d, sizeof(GapState) * slots * B(),
+    void pull_gaps(int first_slot, int slots) {
+        const size_t o = (size_t)first_slot * B();
+        HIPCHECK(hipMemcpyAsync(W_.gs_h + o, W_.gs_d + o, sizeof(GapState) * slots * B(),
                                 hipMemcpyDeviceToHost, s()));
         sync();
     }
@@ -244,10 +342,12 @@ class BatchSolver {
     // eta_hat = 1 / max |scaled A entry|, omega = ||c|| / ||Combine(lc, uc)||,
     // x = proj_X(0), y = 0).
     void init() {
-        const BatchMaps &bm = b_->bm;
         const Vecs v = P_->scaled();
         inst_.assign(B(), Inst());
         kkt_.assign(B(), KktHost{});
+        listed_ = -2;
+        set_active(true);
+        const BatchMaps &bm = bm_;
         HIPCHECK(pdlp::launch_b_norms(s(), P_->A, P_->AT, bm, nullptr, 3, nullptr, nullptr, nullptr,
                                       nullptr, v, W_.part_chk, 1u, W_.out_d));
         pull_out(2);
@@ -284,7 +384,7 @@ class BatchSolver {
         const double *p0[4] = {W_.it.X[0], W_.it.Y[0], W_.it.AX[0], W_.it.ATY[0]};
         const double *p1[4] = {W_.xb, W_.yb, W_.axb, W_.atyb};
         const Vecs orig{P_->c, P_->lc, P_->uc, P_->lv, P_->uv};
-        HIPCHECK(pdlp::launch_b_kkt(s(), P_->A, P_->AT, b_->bm, mask_dev(MASK_KKT), W_.sel_d, p0, p1,
+        HIPCHECK(pdlp::launch_b_kkt(s(), P_->A, P_->AT, bm_, mask_dev(MASK_KKT), W_.sel_d, p0, p1,
                                     P_->d1, P_->d2, orig, rc_mode_, W_.part_chk, W_.out_d, nullptr,
                                     nullptr, nullptr));
         pull_out(7);
@@ -317,11 +417,12 @@ class BatchSolver {
             rem = std::max(rem, c.block_target);
         }
         push_ctrl();
-        const BatchMaps &bm = b_->bm;
+        const BatchMaps &bm = bm_;
         const Vecs v = P_->scaled();
         while (rem > 0) {
             long long n_att = rem + rem / 8 + 1;
             if (n_att > 4096) n_att = 4096;
+            b_->stats.attempt_launches += n_att;
             for (long long a = 0; a < n_att; ++a)
                 HIPCHECK(pdlp::launch_b_attempt(s(), P_->A, P_->AT, v, W_.it, W_.ctrl_d, bm,
                                                 W_.part_dual, W_.part_ps, W_.part_pf));
@@ -351,7 +452,7 @@ class BatchSolver {
 
     // Periodic checks of Section 3 for the instances at a boundary.
     void check_round(long long max_k) {
-        const BatchMaps &bm = b_->bm;
+        const BatchMaps &bm = bm_;
         const Vecs v = P_->scaled();
         bool any = false;
         for (int i = 0; i < B(); ++i) {
@@ -378,15 +479,15 @@ class BatchSolver {
         // average and its products
         HIPCHECK(pdlp::launch_b_elementwise(s(), A, AT, bm, mchk, 0, W_.sv_d, W_.it.sx, W_.xb,
                                             W_.it.sy, W_.yb));
-        HIPCHECK(pdlp::launch_b_spmv_plain(s(), A, bm.ablk_inst, mchk, W_.xb, W_.axb));
-        HIPCHECK(pdlp::launch_b_spmv_plain(s(), AT, bm.tblk_inst, mchk, W_.yb, W_.atyb));
+        HIPCHECK(pdlp::launch_b_spmv_plain(s(), A, bm.ablk_inst, bm.alist, bm.na, mchk, W_.xb,
+                                           W_.axb));
+        HIPCHECK(pdlp::launch_b_spmv_plain(s(), AT, bm.tblk_inst, bm.tlist, bm.nt, mchk, W_.yb,
+                                           W_.atyb));
         // mu(z, z0) and mu(z_bar, z0)
-        HIPCHECK(pdlp::launch_b_gap(s(), A, AT, bm, mchk, v, W_.it.X[0], W_.it.Y[0], W_.it.AX[0],
-                                    W_.it.ATY[0], W_.x0, W_.y0, W_.om_d, W_.part_chk, W_.gs_d,
-                                    kBatchGapSteps));
-        HIPCHECK(pdlp::launch_b_gap(s(), A, AT, bm, mchk, v, W_.xb, W_.yb, W_.axb, W_.atyb, W_.x0,
-                                    W_.y0, W_.om_d, W_.part_chk, W_.gs_d + B(), kBatchGapSteps));
-        pull_gaps(2);
+        const GapArgs g2[2] = {
+            {W_.it.X[0], W_.it.Y[0], W_.it.AX[0], W_.it.ATY[0], W_.x0, W_.y0, 0},
+            {W_.xb, W_.yb, W_.axb, W_.atyb, W_.x0, W_.y0, 1}};
+        gaps(g2, 2, MASK_CHK);
         bool any_kkt = false;
         for (int i = 0; i < B(); ++i) {
             Inst &st = inst_[i];
@@ -486,10 +587,8 @@ class BatchSolver {
         HIPCHECK(pdlp::launch_b_elementwise(s(), A, AT, bm, mr, 2, W_.zero_d, nullptr, it.sx,
                                             nullptr, it.sy));
         // mu_ref = mu(z0, z_prev0) under the new primal weight
-        HIPCHECK(pdlp::launch_b_gap(s(), A, AT, bm, mr, v, W_.x0, W_.y0, it.AX[0], it.ATY[0], W_.xp,
-                                    W_.yp, W_.om_d, W_.part_chk, W_.gs_d + 2 * (size_t)B(),
-                                    kBatchGapSteps));
-        pull_gaps(3);
+        const GapArgs g1[1] = {{W_.x0, W_.y0, it.AX[0], it.ATY[0], W_.xp, W_.yp, 2}};
+        gaps(g1, 1, MASK_RST);
         for (int i = 0; i < B(); ++i) {
             if (!mask(MASK_RST)[i]) continue;
             inst_[i].mu_ref = W_.gs_h[2 * (size_t)B() + i].mu;
@@ -500,6 +599,7 @@ class BatchSolver {
     // Final evaluation on each instance's output point, unscaled outputs.
     void finish(pdlp_result *res, double *x_host, double *y_host, double *r_host, double secs,
                 double setup) {
+        set_active(true);
         for (int i = 0; i < B(); ++i) {
             const Inst &st = inst_[i];
             mask(MASK_KKT)[i] = 1;
@@ -510,7 +610,7 @@ class BatchSolver {
         const double *p0[4] = {W_.it.X[0], W_.it.Y[0], W_.it.AX[0], W_.it.ATY[0]};
         const double *p1[4] = {W_.xb, W_.yb, W_.axb, W_.atyb};
         const Vecs orig{P_->c, P_->lc, P_->uc, P_->lv, P_->uv};
-        HIPCHECK(pdlp::launch_b_kkt(s(), P_->A, P_->AT, b_->bm, mask_dev(MASK_KKT), W_.sel_d, p0,
+        HIPCHECK(pdlp::launch_b_kkt(s(), P_->A, P_->AT, bm_, mask_dev(MASK_KKT), W_.sel_d, p0,
                                     p1, P_->d1, P_->d2, orig, rc_mode_, W_.part_chk, W_.out_d,
                                     W_.ro, W_.xo, W_.yo));
         pull_out(7);
@@ -584,6 +684,8 @@ void build_maps(pdlp_batch *b) {
     HIPCHECK(hipMemcpyAsync(d_ao, aoff.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
     HIPCHECK(hipMemcpyAsync(d_to, toff.data(), sizeof(int32_t) * (B + 1), hipMemcpyHostToDevice, s));
     HIPCHECK(hipStreamSynchronize(s));
+    b->aoff = aoff;
+    b->toff = toff;
     b->bm.B = B;
     b->bm.nA = nA;
     b->bm.nT = nT;
@@ -681,6 +783,13 @@ int pdlp_batch_dims(const pdlp_batch *b, int32_t *count, int64_t *m_total, int64
         if (m_total) *m_total = b->P->m;
         if (n_total) *n_total = b->P->n;
         if (nnz_total) *nnz_total = b->P->nnz;
+    });
+}
+
+int pdlp_batch_get_stats(const pdlp_batch *b, pdlp_batch_stats *stats) {
+    return guarded([&] {
+        if (!b || !stats) invalid("NULL argument");
+        *stats = b->stats;
     });
 }
 

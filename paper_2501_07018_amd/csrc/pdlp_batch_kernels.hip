@@ -7,6 +7,8 @@
 // "Check blocks" index both partitions: cb < nT are blocks of A^T (columns of
 // an instance), cb >= nT are blocks of A (rows), so segmented reductions over
 // the primal and dual coordinates of an instance share one partial array.
+// Every launch walks the host-set lists of running instances and their
+// blocks (BatchMaps), so finished instances cost nothing.
 #include "pdlp_device.h"
 
 #include <cmath>
@@ -22,7 +24,8 @@ __device__ __forceinline__ int cb_inst(const BatchMaps &bm, int cb) {
 __global__ __launch_bounds__(kThreads) void kb_primal(DCsr AT, Vecs v, Iter it, const Ctrl *ctrl,
                                                       BatchMaps bm, double *part) {
     __shared__ double red[kThreads / 64];
-    for (int b = blockIdx.x; b < AT.nblk; b += gridDim.x) {
+    for (int bi = blockIdx.x; bi < bm.nt; bi += gridDim.x) {
+        const int b = bm.tlist[bi];
         const Ctrl &c = ctrl[bm.tblk_inst[b]];
         if (c.stop || !c.need_primal) continue;
         const int cur = c.cur;
@@ -50,6 +53,8 @@ struct BatchDualEpi {
     double *part;
     const double *gsrc;
     DualRow row;
+    __device__ __forceinline__ int count(const DCsr &) const { return bm.na; }
+    __device__ __forceinline__ int block(int bi) const { return bm.alist[bi]; }
     __device__ __forceinline__ bool begin(int b) {
         const Ctrl &c = ctrl[bm.ablk_inst[b]];
         if (c.stop) return false;
@@ -95,6 +100,8 @@ struct BatchPrimalEpi {
     double *part;
     const double *gsrc;
     PrimalRow row;
+    __device__ __forceinline__ int count(const DCsr &) const { return bm.nt; }
+    __device__ __forceinline__ int block(int bi) const { return bm.tlist[bi]; }
     __device__ __forceinline__ bool begin(int b) {
         const Ctrl &c = ctrl[bm.tblk_inst[b]];
         if (!c.run_at) return false;
@@ -136,8 +143,9 @@ __global__ __launch_bounds__(kThreads) void kb_spmv_primal(DCsr AT, Vecs v, Iter
 __global__ __launch_bounds__(kThreads) void kb_decide(Ctrl *ctrl, BatchMaps bm, const double *pd,
                                                       const double *pps, const double *ppf) {
     const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-    if (i >= bm.B) return;
+    const int ii = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (ii >= bm.ni) return;
+    const int i = bm.ilist[ii];
     const Ctrl c0 = ctrl[i];
     if (c0.stop) {
         if (lane == 0) ctrl[i].run_at = 0;
@@ -199,8 +207,8 @@ __global__ __launch_bounds__(kThreads) void kb_decide(Ctrl *ctrl, BatchMaps bm, 
 // moved to buffer 0 so the checks see every instance in the same buffers.
 __global__ __launch_bounds__(kThreads) void kb_settle(DCsr A, DCsr AT, Iter it, const Ctrl *ctrl,
                                                       BatchMaps bm) {
-    const int ncb = bm.nT + bm.nA;
-    for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
+    for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
+        const int cb = bm.clist[ci];
         const Ctrl &c = ctrl[cb_inst(bm, cb)];
         if (cb < bm.nT) {
             if (c.cur != 1) continue;
@@ -236,8 +244,8 @@ __global__ __launch_bounds__(kThreads) void kb_elementwise(DCsr A, DCsr AT, Batc
                                                            const double *sv, const double *xa,
                                                            double *xo, const double *ya,
                                                            double *yo) {
-    const int ncb = bm.nT + bm.nA;
-    for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
+    for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
+        const int cb = bm.clist[ci];
         const int inst = cb_inst(bm, cb);
         if (!mask[inst]) continue;
         const double s = sv ? sv[inst] : 0.0;
@@ -253,9 +261,12 @@ __global__ __launch_bounds__(kThreads) void kb_elementwise(DCsr A, DCsr AT, Batc
 }
 
 struct BatchPlainEpi {
-    const int32_t *inst, *mask;
+    const int32_t *inst, *mask, *list;
+    int nlist;
     const double *gsrc;
     double *out;
+    __device__ __forceinline__ int count(const DCsr &) const { return nlist; }
+    __device__ __forceinline__ int block(int bi) const { return list[bi]; }
     __device__ __forceinline__ bool begin(int b) const { return mask[inst[b]] != 0; }
     __device__ __forceinline__ const double *src() const { return gsrc; }
     template <int N>
@@ -265,11 +276,12 @@ struct BatchPlainEpi {
 };
 
 __global__ __launch_bounds__(kThreads) void kb_spmv_plain(DCsr M, const int32_t *blk_inst,
+                                                          const int32_t *list, int nlist,
                                                           const int32_t *mask, const double *x,
                                                           double *out) {
     __shared__ double prod[kStage];
     __shared__ double red[kThreads / 64];
-    BatchPlainEpi epi{blk_inst, mask, x, out};
+    BatchPlainEpi epi{blk_inst, mask, list, nlist, x, out};
     double acc[1] = {0.0};
     stream_spmv<1>(M, epi, acc, prod, red);
 }
@@ -280,8 +292,10 @@ __global__ __launch_bounds__(kThreads) void kb_inst_reduce(const double *part, i
                                                            unsigned maxmask, BatchMaps bm,
                                                            const int32_t *mask, double *out) {
     const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-    if (i >= bm.B || (mask && !mask[i])) return;
+    const int ii = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (ii >= bm.ni) return;
+    const int i = bm.ilist[ii];
+    if (mask && !mask[i]) return;
     for (int k = 0; k < nv; ++k) {
         const bool mx = (maxmask >> k) & 1u;
         double a = 0.0;
@@ -306,8 +320,8 @@ __global__ __launch_bounds__(kThreads) void kb_norms(DCsr A, DCsr AT, BatchMaps 
                                                      const double *xb, const double *ya,
                                                      const double *yb, Vecs v, double *part) {
     __shared__ double red[2 * (kThreads / 64)];
-    const int ncb = bm.nT + bm.nA;
-    for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
+    for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
+        const int cb = bm.clist[ci];
         const int inst = cb_inst(bm, cb);
         if (mask && !mask[inst]) continue;
         double acc[2] = {0.0, 0.0};
@@ -362,8 +376,8 @@ __global__ __launch_bounds__(kThreads) void kb_kkt(DCsr A, DCsr AT, BatchMaps bm
                                                    Vecs orig, int mode, double *part,
                                                    double *r_out, double *x_out, double *y_out) {
     __shared__ double red[7 * (kThreads / 64)];
-    const int ncb = bm.nT + bm.nA;
-    for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
+    for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
+        const int cb = bm.clist[ci];
         const int inst = cb_inst(bm, cb);
         if (mask && !mask[inst]) continue;
         const int s = sel ? sel[inst] : 0;
@@ -452,8 +466,8 @@ __global__ __launch_bounds__(kThreads) void kb_gap_setup(DCsr A, DCsr AT, BatchM
                                                          const double *xr, const double *yr,
                                                          const double *omega, double *part) {
     __shared__ double red[4 * (kThreads / 64)];
-    const int ncb = bm.nT + bm.nA;
-    for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
+    for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
+        const int cb = bm.clist[ci];
         const int inst = cb_inst(bm, cb);
         if (!mask[inst]) continue;
         const double w = omega[inst];
@@ -489,8 +503,10 @@ __global__ __launch_bounds__(kThreads) void kb_gap_init(const double *part, Batc
                                                         const int32_t *mask, const double *omega,
                                                         GapState *gs) {
     const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-    if (i >= bm.B || !mask[i]) return;
+    const int ii = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (ii >= bm.ni) return;
+    const int i = bm.ilist[ii];
+    if (!mask[i]) return;
     double v[4];
     for (int k = 0; k < 4; ++k) {
         double a = 0.0;
@@ -539,8 +555,8 @@ __global__ __launch_bounds__(kThreads) void kb_gap_step(DCsr A, DCsr AT, BatchMa
                                                         const double *ax, const double *aty,
                                                         const GapState *gs, double *part) {
     __shared__ double red[6 * (kThreads / 64)];
-    const int ncb = bm.nT + bm.nA;
-    for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
+    for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
+        const int cb = bm.clist[ci];
         const int inst = cb_inst(bm, cb);
         if (!mask[inst]) continue;
         const GapState &g = gs[inst];
@@ -585,8 +601,10 @@ __global__ __launch_bounds__(kThreads) void kb_gap_update(const double *part, Ba
                                                           const int32_t *mask, GapState *gs,
                                                           int last) {
     const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-    if (i >= bm.B || !mask[i]) return;
+    const int ii = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    if (ii >= bm.ni) return;
+    const int i = bm.ilist[ii];
+    if (!mask[i]) return;
     if (gs[i].done || !gs[i].newton) return;
     double v[6];
     for (int k = 0; k < 6; ++k) {
@@ -640,54 +658,57 @@ __global__ __launch_bounds__(kThreads) void kb_gap_update(const double *part, Ba
     gs[i] = s;
 }
 
-__global__ void kb_clear_pending(Ctrl *ctrl, int B) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
-        ctrl[i].pending_sy = 0;
-}
-
 // --------------------------------------------------------------- launchers
 
-static inline int wave_grid(int B) { return (B + kThreads / 64 - 1) / (kThreads / 64); }
-static inline int cb_grid(const BatchMaps &bm) {
-    const int n = bm.nT + bm.nA;
-    return n < 4096 ? (n > 0 ? n : 1) : 4096;
+static inline int wave_grid(int ni) {
+    const int g = (ni + kThreads / 64 - 1) / (kThreads / 64);
+    return g > 0 ? g : 1;
 }
+static inline int list_grid(int n, int cap) { return n < cap ? (n > 0 ? n : 1) : cap; }
+constexpr int kBatchGridCap = 4096;   // elementwise / check kernels
+constexpr int kBatchSpmvCap = 2048;   // persistent CSR stream kernels
 
 hipError_t launch_b_attempt(hipStream_t s, const DCsr &A, const DCsr &AT, Vecs v, Iter it,
                             Ctrl *ctrl, const BatchMaps &bm, double *pd, double *pps,
                             double *ppf) {
-    const int gT = AT.nblk < 4096 ? (AT.nblk > 0 ? AT.nblk : 1) : 4096;
-    hipLaunchKernelGGL(kb_primal, dim3(gT), dim3(kThreads), 0, s, AT, v, it, ctrl, bm, pps);
-    if (A.grid > 0)
-        hipLaunchKernelGGL(kb_spmv_dual, dim3(A.grid), dim3(kThreads), 0, s, A, v, it, ctrl, bm, pd);
-    hipLaunchKernelGGL(kb_decide, dim3(wave_grid(bm.B)), dim3(kThreads), 0, s, ctrl, bm, pd, pps,
+    if (bm.ni == 0) return hipSuccess;
+    if (bm.nt > 0)
+        hipLaunchKernelGGL(kb_primal, dim3(list_grid(bm.nt, kBatchGridCap)), dim3(kThreads), 0, s,
+                           AT, v, it, ctrl, bm, pps);
+    if (bm.na > 0)
+        hipLaunchKernelGGL(kb_spmv_dual, dim3(list_grid(bm.na, kBatchSpmvCap)), dim3(kThreads), 0,
+                           s, A, v, it, ctrl, bm, pd);
+    hipLaunchKernelGGL(kb_decide, dim3(wave_grid(bm.ni)), dim3(kThreads), 0, s, ctrl, bm, pd, pps,
                        ppf);
-    if (AT.grid > 0)
-        hipLaunchKernelGGL(kb_spmv_primal, dim3(AT.grid), dim3(kThreads), 0, s, AT, v, it, ctrl, bm,
-                           ppf);
+    if (bm.nt > 0)
+        hipLaunchKernelGGL(kb_spmv_primal, dim3(list_grid(bm.nt, kBatchSpmvCap)), dim3(kThreads), 0,
+                           s, AT, v, it, ctrl, bm, ppf);
     return hipGetLastError();
 }
 
 hipError_t launch_b_settle(hipStream_t s, const DCsr &A, const DCsr &AT, Iter it, Ctrl *ctrl,
                            const BatchMaps &bm) {
-    hipLaunchKernelGGL(kb_settle, dim3(cb_grid(bm)), dim3(kThreads), 0, s, A, AT, it, ctrl, bm);
-    hipLaunchKernelGGL(kb_clear_pending, dim3((bm.B + 255) / 256), dim3(256), 0, s, ctrl, bm.B);
+    if (bm.nc > 0)
+        hipLaunchKernelGGL(kb_settle, dim3(list_grid(bm.nc, kBatchGridCap)), dim3(kThreads), 0, s,
+                           A, AT, it, ctrl, bm);
     return hipGetLastError();
 }
 
 hipError_t launch_b_elementwise(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
                                 const int32_t *mask, int op, const double *sv, const double *xa,
                                 double *xo, const double *ya, double *yo) {
-    hipLaunchKernelGGL(kb_elementwise, dim3(cb_grid(bm)), dim3(kThreads), 0, s, A, AT, bm, mask,
-                       op, sv, xa, xo, ya, yo);
+    if (bm.nc > 0)
+        hipLaunchKernelGGL(kb_elementwise, dim3(list_grid(bm.nc, kBatchGridCap)), dim3(kThreads), 0,
+                           s, A, AT, bm, mask, op, sv, xa, xo, ya, yo);
     return hipGetLastError();
 }
 
 hipError_t launch_b_spmv_plain(hipStream_t s, const DCsr &M, const int32_t *blk_inst,
-                               const int32_t *mask, const double *x, double *out) {
-    if (M.grid > 0)
-        hipLaunchKernelGGL(kb_spmv_plain, dim3(M.grid), dim3(kThreads), 0, s, M, blk_inst, mask, x,
-                           out);
+                               const int32_t *list, int nlist, const int32_t *mask,
+                               const double *x, double *out) {
+    if (nlist > 0)
+        hipLaunchKernelGGL(kb_spmv_plain, dim3(list_grid(nlist, kBatchSpmvCap)), dim3(kThreads), 0,
+                           s, M, blk_inst, list, nlist, mask, x, out);
     return hipGetLastError();
 }
 
@@ -695,9 +716,10 @@ hipError_t launch_b_norms(hipStream_t s, const DCsr &A, const DCsr &AT, const Ba
                           const int32_t *mask, int op, const double *xa, const double *xb,
                           const double *ya, const double *yb, Vecs v, double *part,
                           unsigned maxmask, double *out) {
-    hipLaunchKernelGGL(kb_norms, dim3(cb_grid(bm)), dim3(kThreads), 0, s, A, AT, bm, mask, op, xa,
-                       xb, ya, yb, v, part);
-    hipLaunchKernelGGL(kb_inst_reduce, dim3(wave_grid(bm.B)), dim3(kThreads), 0, s, part, 2,
+    if (bm.ni == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_norms, dim3(list_grid(bm.nc, kBatchGridCap)), dim3(kThreads), 0, s, A,
+                       AT, bm, mask, op, xa, xb, ya, yb, v, part);
+    hipLaunchKernelGGL(kb_inst_reduce, dim3(wave_grid(bm.ni)), dim3(kThreads), 0, s, part, 2,
                        maxmask, bm, mask, out);
     return hipGetLastError();
 }
@@ -707,28 +729,37 @@ hipError_t launch_b_kkt(hipStream_t s, const DCsr &A, const DCsr &AT, const Batc
                         const double *const *p1, const double *d1, const double *d2, Vecs orig,
                         int mode, double *part, double *out, double *r_out, double *x_out,
                         double *y_out) {
-    hipLaunchKernelGGL(kb_kkt, dim3(cb_grid(bm)), dim3(kThreads), 0, s, A, AT, bm, mask, sel,
-                       p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3], d1, d2, orig, mode,
-                       part, r_out, x_out, y_out);
-    hipLaunchKernelGGL(kb_inst_reduce, dim3(wave_grid(bm.B)), dim3(kThreads), 0, s, part, 7, 0x0Fu,
+    if (bm.ni == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_kkt, dim3(list_grid(bm.nc, kBatchGridCap)), dim3(kThreads), 0, s, A, AT,
+                       bm, mask, sel, p0[0], p0[1], p0[2], p0[3], p1[0], p1[1], p1[2], p1[3], d1,
+                       d2, orig, mode, part, r_out, x_out, y_out);
+    hipLaunchKernelGGL(kb_inst_reduce, dim3(wave_grid(bm.ni)), dim3(kThreads), 0, s, part, 7, 0x0Fu,
                        bm, mask, out);
     return hipGetLastError();
 }
 
-hipError_t launch_b_gap(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
-                        const int32_t *mask, Vecs v, const double *x, const double *y,
-                        const double *ax, const double *aty, const double *xr, const double *yr,
-                        const double *omega, double *part, GapState *gs, int steps) {
-    const int g = cb_grid(bm);
-    hipLaunchKernelGGL(kb_gap_setup, dim3(g), dim3(kThreads), 0, s, A, AT, bm, mask, v, x, y, ax,
-                       aty, xr, yr, omega, part);
-    hipLaunchKernelGGL(kb_gap_init, dim3(wave_grid(bm.B)), dim3(kThreads), 0, s, part, bm, mask,
+hipError_t launch_b_gap_begin(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                              const int32_t *mask, Vecs v, const double *x, const double *y,
+                              const double *ax, const double *aty, const double *xr,
+                              const double *yr, const double *omega, double *part, GapState *gs) {
+    if (bm.ni == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_gap_setup, dim3(list_grid(bm.nc, kBatchGridCap)), dim3(kThreads), 0, s,
+                       A, AT, bm, mask, v, x, y, ax, aty, xr, yr, omega, part);
+    hipLaunchKernelGGL(kb_gap_init, dim3(wave_grid(bm.ni)), dim3(kThreads), 0, s, part, bm, mask,
                        omega, gs);
-    for (int k = 0; k < steps; ++k) {
-        hipLaunchKernelGGL(kb_gap_step, dim3(g), dim3(kThreads), 0, s, A, AT, bm, mask, v, x, y, ax,
-                           aty, gs, part);
-        hipLaunchKernelGGL(kb_gap_update, dim3(wave_grid(bm.B)), dim3(kThreads), 0, s, part, bm,
-                           mask, gs, k == steps - 1 ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_gap_steps(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                              const int32_t *mask, Vecs v, const double *x, const double *y,
+                              const double *ax, const double *aty, double *part, GapState *gs,
+                              int first, int count, int total) {
+    if (bm.ni == 0) return hipSuccess;
+    for (int k = first; k < first + count && k < total; ++k) {
+        hipLaunchKernelGGL(kb_gap_step, dim3(list_grid(bm.nc, kBatchGridCap)), dim3(kThreads), 0,
+                           s, A, AT, bm, mask, v, x, y, ax, aty, gs, part);
+        hipLaunchKernelGGL(kb_gap_update, dim3(wave_grid(bm.ni)), dim3(kThreads), 0, s, part, bm,
+                           mask, gs, k == total - 1 ? 1 : 0);
     }
     return hipGetLastError();
 }

@@ -104,7 +104,9 @@ __device__ __forceinline__ T stream_load(const T *p) {
 // across the workgroup.  The grid is persistent: workgroup g handles blocks
 // g, g + grid, ...
 
-// Hooks of the epilogue: begin(b) says whether block b runs (and may load
+// Hooks of the epilogue: count(A) blocks are visited, the bi-th being
+// block(bi) (all blocks in order for one LP, a list of the blocks of running
+// instances in a batch); begin(b) says whether block b runs (and may load
 // per-block parameters), src() is the gathered vector, end(b, acc, red) is
 // called after the block (per-block partial sums in the batched solver).
 template <int NACC, class Epi>
@@ -112,7 +114,9 @@ __device__ __forceinline__ void stream_spmv(const DCsr &A, Epi &epi, double (&ac
                                             double *prod, double *red) {
     constexpr int kPer = kStage / kThreads;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int b = blockIdx.x; b < A.nblk; b += gridDim.x) {
+    const int nb = epi.count(A);
+    for (int bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+        const int b = epi.block(bi);
         if (!epi.begin(b)) continue;
         const double *__restrict__ x = epi.src();
         const int r0 = A.blk[b], r1 = A.blk[b + 1];
@@ -218,6 +222,8 @@ struct PrimalRow {
 // partial sums accumulate per thread across blocks.
 struct SingleEpi {
     const double *gsrc;
+    __device__ __forceinline__ int count(const DCsr &A) const { return A.nblk; }
+    __device__ __forceinline__ int block(int bi) const { return bi; }
     __device__ __forceinline__ bool begin(int) { return true; }
     __device__ __forceinline__ const double *src() const { return gsrc; }
     template <int N>

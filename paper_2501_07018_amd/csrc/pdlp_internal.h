@@ -107,6 +107,11 @@ struct BatchMaps {
     const int32_t *tblk_inst = nullptr;  // instance of each A^T block [nT]
     const int32_t *ablk_off = nullptr;   // first A block of each instance [B+1]
     const int32_t *tblk_off = nullptr;   // first A^T block of each instance [B+1]
+    // The instances a launch serves and their blocks, set by the host: ilist
+    // (ni instances), alist (na A blocks), tlist (nt A^T blocks) and clist
+    // (nc check blocks: c < nT is A^T block c, c >= nT is A block c - nT).
+    int32_t ni = 0, na = 0, nt = 0, nc = 0;
+    const int32_t *ilist = nullptr, *alist = nullptr, *tlist = nullptr, *clist = nullptr;
 };
 
 // ------------------------------------------------------------ launchers
@@ -210,8 +215,10 @@ hipError_t launch_b_settle(hipStream_t s, const DCsr &A, const DCsr &AT, Iter it
 hipError_t launch_b_elementwise(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
                                 const int32_t *mask, int op, const double *sv, const double *xa,
                                 double *xo, const double *ya, double *yo);
+// product over the listed blocks of M whose instance is masked in
 hipError_t launch_b_spmv_plain(hipStream_t s, const DCsr &M, const int32_t *blk_inst,
-                               const int32_t *mask, const double *x, double *out);
+                               const int32_t *list, int nlist, const int32_t *mask,
+                               const double *x, double *out);
 // per-instance pairs out[2i], out[2i+1]: op 0 ||xa-xb||^2, ||ya-yb||^2;
 // op 2 ||c||^2, ||Combine(lc, uc)||^2; op 3 max |A^T value| (maxmask 1)
 hipError_t launch_b_norms(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
@@ -226,9 +233,15 @@ hipError_t launch_b_kkt(hipStream_t s, const DCsr &A, const DCsr &AT, const Batc
                         const double *const *p1, const double *d1, const double *d2, Vecs orig,
                         int mode, double *part, double *out, double *r_out, double *x_out,
                         double *y_out);
-hipError_t launch_b_gap(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
-                        const int32_t *mask, Vecs v, const double *x, const double *y,
-                        const double *ax, const double *aty, const double *xr, const double *yr,
-                        const double *omega, double *part, GapState *gs, int steps);
+// normalized duality gap per instance: begin = radius, slopes and the first
+// abscissa; then active-set steps first .. first+count-1 of at most `total`
+hipError_t launch_b_gap_begin(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                              const int32_t *mask, Vecs v, const double *x, const double *y,
+                              const double *ax, const double *aty, const double *xr,
+                              const double *yr, const double *omega, double *part, GapState *gs);
+hipError_t launch_b_gap_steps(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                              const int32_t *mask, Vecs v, const double *x, const double *y,
+                              const double *ax, const double *aty, double *part, GapState *gs,
+                              int first, int count, int total);
 
 }  // namespace pdlp
