@@ -91,6 +91,55 @@ def cpu_baseline(lp, steps):
                        f"{dt:.1f} s")}
 
 
+def batch_section(pd, count, loop_n):
+    """Batched solver on the planted batch workload: `count` LPs with m ~ U{200..20000},
+    n = 1.5 m, 8 distinct rows per column, relative KKT tolerance 1e-6, against
+    pdlp_solve looped over a seeded sample of the same instances."""
+    import numpy as np
+    import lpgen
+    t0 = time.perf_counter()
+    sizes = lpgen.batch_sizes()[:count]
+    lps = [lpgen.batch_lp(i, m, n) for i, (m, n) in enumerate(sizes)]
+    nnz = sum(lp.nnz for lp in lps)
+    log(f"batch: generated {count} LPs ({nnz} nonzeros) in {time.perf_counter() - t0:.1f}s")
+    prm = pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6, max_iters=200000)
+    b = pd.Batch(lps)
+    t0 = time.perf_counter()
+    res = b.solve(prm, want_solution=False)
+    tb = time.perf_counter() - t0
+    st = b.stats()
+    status = {}
+    for r in res:
+        status[r["status_name"]] = status.get(r["status_name"], 0) + 1
+    log(f"batch: solved in {tb:.2f}s {status} {st}")
+    b.close()
+    rng = np.random.default_rng(2025)
+    idx = rng.choice(count, size=min(loop_n, count), replace=False)
+    t0 = time.perf_counter()
+    loop_it = 0
+    for i in idx:
+        p = pd.Problem(lps[i])
+        loop_it += p.solve(prm)["iterations"]
+        p.close()
+    tl = time.perf_counter() - t0
+    log(f"batch: loop of {len(idx)} pdlp_solve in {tl:.2f}s")
+    return {
+        "workload": (f"{count} planted LPs, m ~ U{{200..20000}}, n = 1.5 m, 8 rows per column, "
+                     f"{nnz} nonzeros in total; relative KKT 1e-6, iteration cap 200000"),
+        "lps_per_s": count / tb, "seconds": tb, "status": status,
+        "iters_per_s_aggregate": st["total_iterations"] / tb,
+        "max_iterations": st["max_iterations"], "total_iterations": st["total_iterations"],
+        "rounds": st["rounds"], "step_seconds": st["step_seconds"],
+        "check_seconds": st["check_seconds"],
+        "loop_sample": int(len(idx)), "loop_lps_per_s": len(idx) / tl,
+        "loop_iters_per_s": loop_it / tl,
+        "speedup_lps": (count / tb) / (len(idx) / tl),
+        "note": ("lps_per_s = instances / wall time of one pdlp_batch_solve on resident inputs "
+                 "(set by the slowest instance); loop figures time pdlp_solve (creation included) "
+                 "on a seeded random sample"),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +149,10 @@ def main():
     ap.add_argument("--n", type=int, default=25_000_000)
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=1024,
+                    help="instances of the batched-solver measurement (0 skips it)")
+    ap.add_argument("--batch-loop", type=int, default=16,
+                    help="instances solved one by one for the loop comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -213,6 +266,8 @@ def main():
         "setup_s": setup_s,
         "check_ms_per_step": ks["check_ms"] / max(steps_done, 1),
     }
+    if args.batch_count > 0:
+        out["batched"] = batch_section(pd, args.batch_count, args.batch_loop)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(lp, args.cpu_steps)

@@ -278,6 +278,9 @@ typedef struct pdlp_batch_stats {
     int64_t attempt_launches;  /* step attempts enqueued (each serves every instance) */
     int64_t max_iterations;    /* accepted steps of the slowest instance */
     int64_t total_iterations;  /* accepted steps summed over instances */
+    int64_t gap_evals;         /* normalized-duality-gap evaluations */
+    int64_t gap_steps;         /* active-set steps they took */
+    int64_t gap_capped;        /* evaluations that ended without an exact root (step cap) */
     double seconds, setup_seconds, step_seconds, check_seconds;
 } pdlp_batch_stats;
 int pdlp_batch_get_stats(const pdlp_batch *b, pdlp_batch_stats *stats);

@@ -84,6 +84,7 @@ class DeviceRates(C.Structure):
 class BatchStats(C.Structure):
     _fields_ = [("rounds", C.c_int64), ("attempt_launches", C.c_int64),
                 ("max_iterations", C.c_int64), ("total_iterations", C.c_int64),
+                ("gap_evals", C.c_int64), ("gap_steps", C.c_int64), ("gap_capped", C.c_int64),
                 ("seconds", C.c_double), ("setup_seconds", C.c_double),
                 ("step_seconds", C.c_double), ("check_seconds", C.c_double)]
 

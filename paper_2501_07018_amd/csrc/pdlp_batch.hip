@@ -40,6 +40,8 @@ namespace {
 // in chunks; the host stops once every evaluation of the launch has converged.
 constexpr int kBatchGapSteps = 32;
 constexpr int kBatchGapChunk = 6;
+// XCDs of the device: workgroup w of a launch runs on XCD w mod kXcds.
+constexpr int kXcds = 8;
 
 // Device buffers of a batch solve, sized by the packed problem.
 struct BatchWork {
@@ -117,7 +119,8 @@ BatchWork *make_work(pdlp_batch *b) {
         W->om_d = a.dev<double>(B);
         W->om_h = a.host<double>(B);
         W->zero_d = a.dev<double>(B);
-        const size_t nl = (size_t)B + 2 * ((size_t)b->bm.nA + b->bm.nT);
+        // instance list + per-XCD interleaved block lists (padding at most kXcds-fold)
+        const size_t nl = (size_t)B + 2 * (size_t)kXcds * ((size_t)b->bm.nA + b->bm.nT);
         W->list_d = a.dev<int32_t>(nl);
         W->list_h = a.host<int32_t>(nl);
         HIPCHECK(pdlp::launch_fill(P->stream, B, W->zero_d, 0.0));
@@ -220,43 +223,68 @@ class BatchSolver {
     int listed_ = -1;    // running instances when the lists were built (-1: all)
 
     // Lists of the instances the launches serve and of their blocks: every
-    // instance (all = true) or the running ones.  Rebuilt when that set changes.
+    // instance (all = true) or the running ones.  Rebuilt when that set
+    // changes.  With at least kXcds instances, each is assigned to one XCD
+    // (greedy by block count) and the block lists are interleaved so that
+    // position p of a list serves an instance of XCD p mod kXcds (padding -1).
     void set_active(bool all) {
         int running = 0;
         for (const auto &st : inst_) running += st.status < 0;
         const int want = all ? -1 : running;
         if (want == listed_ && bm_.ilist) return;
         const BatchMaps &base = b_->bm;
-        const int B = b_->B, nA = base.nA, nT = base.nT;
-        std::vector<int32_t> il, al, tl;
-        for (int i = 0; i < B; ++i) {
-            if (!all && inst_[i].status >= 0) continue;
-            il.push_back(i);
-            for (int k = b_->aoff[i]; k < b_->aoff[i + 1]; ++k) al.push_back(k);
-            for (int k = b_->toff[i]; k < b_->toff[i + 1]; ++k) tl.push_back(k);
+        const int B = b_->B, nT = base.nT;
+        const std::vector<int32_t> &ao = b_->aoff, &to = b_->toff;
+        std::vector<int32_t> il;
+        for (int i = 0; i < B; ++i)
+            if (all || inst_[i].status < 0) il.push_back(i);
+        const int nx = (int)il.size() >= kXcds ? kXcds : 1;
+        // instance -> XCD, heaviest first onto the least loaded XCD
+        std::vector<int32_t> order(il);
+        auto nblk = [&](int i) { return (ao[i + 1] - ao[i]) + (to[i + 1] - to[i]); };
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return nblk(a) > nblk(b); });
+        std::vector<std::vector<int32_t>> sub_a(nx), sub_t(nx), sub_c(nx);
+        std::vector<long long> load(nx, 0);
+        for (int i : order) {
+            const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            load[k] += nblk(i);
+            for (int q = ao[i]; q < ao[i + 1]; ++q) sub_a[k].push_back(q);
+            for (int q = to[i]; q < to[i + 1]; ++q) sub_t[k].push_back(q);
+            for (int q = to[i]; q < to[i + 1]; ++q) sub_c[k].push_back(q);
+            for (int q = ao[i]; q < ao[i + 1]; ++q) sub_c[k].push_back(nT + q);
         }
+        auto interleave = [&](const std::vector<std::vector<int32_t>> &sub, int32_t *dst) {
+            size_t mx = 0;
+            for (const auto &v : sub) mx = std::max(mx, v.size());
+            size_t len = 0;
+            for (size_t t = 0; t < mx; ++t)
+                for (int k = 0; k < nx; ++k) {
+                    const int32_t e = t < sub[k].size() ? sub[k][t] : -1;
+                    dst[t * nx + k] = e;
+                    if (e >= 0) len = t * nx + k + 1;
+                }
+            return (int32_t)len;
+        };
         int32_t *h = W_.list_h;
-        size_t o = 0;
-        std::copy(il.begin(), il.end(), h + o);
-        const size_t oi = o;
-        o += B;
-        std::copy(al.begin(), al.end(), h + o);
-        const size_t oa = o;
-        o += nA;
-        std::copy(tl.begin(), tl.end(), h + o);
-        const size_t ot = o;
-        o += nT;
-        const size_t oc = o;
-        std::copy(tl.begin(), tl.end(), h + o);
-        for (size_t k = 0; k < al.size(); ++k) h[o + tl.size() + k] = nT + al[k];
-        HIPCHECK(hipMemcpyAsync(W_.list_d, W_.list_h, sizeof(int32_t) * (oc + tl.size() + al.size()),
-                                hipMemcpyHostToDevice, s()));
+        const size_t oi = 0, oa = (size_t)B, ot = oa + (size_t)kXcds * base.nA,
+                     oc = ot + (size_t)kXcds * nT;
+        std::copy(il.begin(), il.end(), h + oi);
+        const int32_t na = interleave(sub_a, h + oa);
+        const int32_t nt = interleave(sub_t, h + ot);
+        const int32_t nc = interleave(sub_c, h + oc);
+        const size_t off[4] = {oi, oa, ot, oc};
+        const size_t len[4] = {il.size(), (size_t)na, (size_t)nt, (size_t)nc};
+        for (int q = 0; q < 4; ++q)
+            if (len[q] > 0)
+                HIPCHECK(hipMemcpyAsync(W_.list_d + off[q], W_.list_h + off[q],
+                                        sizeof(int32_t) * len[q], hipMemcpyHostToDevice, s()));
         sync();
         bm_ = base;
         bm_.ni = (int32_t)il.size();
-        bm_.na = (int32_t)al.size();
-        bm_.nt = (int32_t)tl.size();
-        bm_.nc = (int32_t)(al.size() + tl.size());
+        bm_.na = na;
+        bm_.nt = nt;
+        bm_.nc = nc;
         bm_.ilist = W_.list_d + oi;
         bm_.alist = W_.list_d + oa;
         bm_.tlist = W_.list_d + ot;
@@ -290,6 +318,15 @@ class BatchSolver {
                     open = mask(mask_k)[i] && W_.gs_h[(size_t)g[q].slot * B() + i].done == 0;
             if (!open) break;
         }
+        pdlp_batch_stats &st = b_->stats;
+        for (int q = 0; q < ng; ++q)
+            for (int i = 0; i < B(); ++i) {
+                if (!mask(mask_k)[i]) continue;
+                const GapState &gsi = W_.gs_h[(size_t)g[q].slot * B() + i];
+                st.gap_evals += 1;
+                st.gap_steps += gsi.nsteps;
+                st.gap_capped += gsi.nsteps > 0 && !gsi.exact;
+            }
     }
 
     int B() const { return b_->B; }

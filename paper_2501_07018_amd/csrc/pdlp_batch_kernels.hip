@@ -8,7 +8,11 @@
 // an instance), cb >= nT are blocks of A (rows), so segmented reductions over
 // the primal and dual coordinates of an instance share one partial array.
 // Every launch walks the host-set lists of running instances and their
-// blocks (BatchMaps), so finished instances cost nothing.
+// blocks (BatchMaps), so finished instances cost nothing.  The lists are
+// interleaved by XCD: list position p goes to workgroup p mod grid, which the
+// dispatcher places on XCD p mod 8 (grids are multiples of 8 or cover the
+// list), and each instance's blocks sit at positions of one residue, so an
+// instance's vectors stay in one XCD's L2.  Padding entries are -1.
 #include "pdlp_device.h"
 
 #include <cmath>
@@ -26,6 +30,7 @@ __global__ __launch_bounds__(kThreads) void kb_primal(DCsr AT, Vecs v, Iter it, 
     __shared__ double red[kThreads / 64];
     for (int bi = blockIdx.x; bi < bm.nt; bi += gridDim.x) {
         const int b = bm.tlist[bi];
+        if (b < 0) continue;  // padding of the per-XCD interleave
         const Ctrl &c = ctrl[bm.tblk_inst[b]];
         if (c.stop || !c.need_primal) continue;
         const int cur = c.cur;
@@ -56,6 +61,7 @@ struct BatchDualEpi {
     __device__ __forceinline__ int count(const DCsr &) const { return bm.na; }
     __device__ __forceinline__ int block(int bi) const { return bm.alist[bi]; }
     __device__ __forceinline__ bool begin(int b) {
+        if (b < 0) return false;
         const Ctrl &c = ctrl[bm.ablk_inst[b]];
         if (c.stop) return false;
         const int cur = c.cur;
@@ -103,6 +109,7 @@ struct BatchPrimalEpi {
     __device__ __forceinline__ int count(const DCsr &) const { return bm.nt; }
     __device__ __forceinline__ int block(int bi) const { return bm.tlist[bi]; }
     __device__ __forceinline__ bool begin(int b) {
+        if (b < 0) return false;
         const Ctrl &c = ctrl[bm.tblk_inst[b]];
         if (!c.run_at) return false;
         const int cur = c.cur;
@@ -209,6 +216,7 @@ __global__ __launch_bounds__(kThreads) void kb_settle(DCsr A, DCsr AT, Iter it, 
                                                       BatchMaps bm) {
     for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
         const int cb = bm.clist[ci];
+        if (cb < 0) continue;
         const Ctrl &c = ctrl[cb_inst(bm, cb)];
         if (cb < bm.nT) {
             if (c.cur != 1) continue;
@@ -246,6 +254,7 @@ __global__ __launch_bounds__(kThreads) void kb_elementwise(DCsr A, DCsr AT, Batc
                                                            double *yo) {
     for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
         const int cb = bm.clist[ci];
+        if (cb < 0) continue;
         const int inst = cb_inst(bm, cb);
         if (!mask[inst]) continue;
         const double s = sv ? sv[inst] : 0.0;
@@ -267,7 +276,7 @@ struct BatchPlainEpi {
     double *out;
     __device__ __forceinline__ int count(const DCsr &) const { return nlist; }
     __device__ __forceinline__ int block(int bi) const { return list[bi]; }
-    __device__ __forceinline__ bool begin(int b) const { return mask[inst[b]] != 0; }
+    __device__ __forceinline__ bool begin(int b) const { return b >= 0 && mask[inst[b]] != 0; }
     __device__ __forceinline__ const double *src() const { return gsrc; }
     template <int N>
     __device__ __forceinline__ void operator()(int r, double s, double (&)[N]) const { out[r] = s; }
@@ -322,6 +331,7 @@ __global__ __launch_bounds__(kThreads) void kb_norms(DCsr A, DCsr AT, BatchMaps 
     __shared__ double red[2 * (kThreads / 64)];
     for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
         const int cb = bm.clist[ci];
+        if (cb < 0) continue;
         const int inst = cb_inst(bm, cb);
         if (mask && !mask[inst]) continue;
         double acc[2] = {0.0, 0.0};
@@ -378,6 +388,7 @@ __global__ __launch_bounds__(kThreads) void kb_kkt(DCsr A, DCsr AT, BatchMaps bm
     __shared__ double red[7 * (kThreads / 64)];
     for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
         const int cb = bm.clist[ci];
+        if (cb < 0) continue;
         const int inst = cb_inst(bm, cb);
         if (mask && !mask[inst]) continue;
         const int s = sel ? sel[inst] : 0;
@@ -468,6 +479,7 @@ __global__ __launch_bounds__(kThreads) void kb_gap_setup(DCsr A, DCsr AT, BatchM
     __shared__ double red[4 * (kThreads / 64)];
     for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
         const int cb = bm.clist[ci];
+        if (cb < 0) continue;
         const int inst = cb_inst(bm, cb);
         if (!mask[inst]) continue;
         const double w = omega[inst];
@@ -545,7 +557,7 @@ __global__ __launch_bounds__(kThreads) void kb_gap_init(const double *part, Batc
     s.D_prev = 0.0;
     s.s_cur = s.done ? 0.0 : (s.pathend ? 1e300 : s.r / sqrt(s.A0));
     s.nsteps = 0;
-    s.pad2 = 0;
+    s.exact = 0;
     gs[i] = s;
 }
 
@@ -557,6 +569,7 @@ __global__ __launch_bounds__(kThreads) void kb_gap_step(DCsr A, DCsr AT, BatchMa
     __shared__ double red[6 * (kThreads / 64)];
     for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
         const int cb = bm.clist[ci];
+        if (cb < 0) continue;
         const int inst = cb_inst(bm, cb);
         if (!mask[inst]) continue;
         const GapState &g = gs[inst];
@@ -625,6 +638,7 @@ __global__ __launch_bounds__(kThreads) void kb_gap_update(const double *part, Ba
         s.mu = F0 / s.r;
         s.done = 3;
         s.newton = 0;
+        s.exact = 1;
         gs[i] = s;
         return;
     }
@@ -639,6 +653,7 @@ __global__ __launch_bounds__(kThreads) void kb_gap_update(const double *part, Ba
         // s_cur, kept inside the bracket
         if (exact) st = at_root ? sc : fmin(fmax(st, a), b);
         else if (!(st >= s.lo && st <= s.hi)) st = isfinite(s.hi) ? 0.5 * (s.lo + s.hi) : s.lo;
+        s.exact = exact ? 1 : 0;
         s.s_star = st;
         s.Acoef = A_;
         s.Bcoef = B_;

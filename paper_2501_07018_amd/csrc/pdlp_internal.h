@@ -87,7 +87,7 @@ struct GapState {
     int newton;           // 1 while the active-set iteration runs
     double s_cur, s_prev, D_prev;
     int nsteps;
-    int pad2;
+    int exact;            // 1 when the root was found on its segment (no cap, no bracket fallback)
 };
 
 // Results of the termination evaluation (Section 6).

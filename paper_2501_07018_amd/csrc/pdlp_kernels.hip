@@ -626,7 +626,7 @@ __global__ void k_gap_init(const double *part, int grid, double omega, GapState 
     s.D_prev = 0.0;
     s.s_cur = s.done ? 0.0 : s.r / sqrt(s.A0);
     s.nsteps = 0;
-    s.pad2 = 0;
+    s.exact = 0;
     *gs = s;
 }
 
@@ -696,6 +696,7 @@ __global__ void k_gap_update(const double *part, int grid, GapState *gs) {
         s.mu = s.f / s.r;
         s.done = 3;
         s.newton = 0;
+        s.exact = 1;
         *gs = s;
         return;
     }
