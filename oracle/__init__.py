@@ -21,6 +21,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle_pdlp.so")
 SRC = os.path.join(HERE, "pdlp_oracle.c")
+SRCS = [SRC, os.path.join(HERE, "pdlp_oracle_unroll.c")]
 
 D = C.POINTER(C.c_double)
 I32 = C.POINTER(C.c_int32)
@@ -28,10 +29,11 @@ I32 = C.POINTER(C.c_int32)
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (-O2 -ffp-contract=off)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+    newest = max(os.path.getmtime(f) for f in SRCS + [os.path.join(HERE, "pdlp_oracle.h")])
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < newest:
         tmp = LIB_PATH + ".tmp"
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall",
-               "-fPIC", "-shared", "-o", tmp, SRC, "-lm"]
+               "-fPIC", "-shared", "-o", tmp, *SRCS, "-lm"]
         subprocess.run(cmd, check=True, cwd=HERE)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -84,6 +86,10 @@ class _Result(C.Structure):
                 ("polished", C.c_int32)]
 
 
+class _Tape(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("eta", D), ("omega", D), ("restart", I32)]
+
+
 class _KKT(C.Structure):
     _fields_ = [("primal_obj", C.c_double), ("dual_obj", C.c_double), ("rel_gap", C.c_double),
                 ("primal_res_abs", C.c_double), ("primal_res_rel", C.c_double),
@@ -123,6 +129,16 @@ def lib():
         L.orc_pdlp.argtypes = [C.POINTER(_LP), C.POINTER(_Unscale), C.POINTER(_Params),
                                C.POINTER(_State), C.POINTER(_Scratch), D, D, C.POINTER(_Result)]
         L.orc_pdlp.restype = C.c_int32
+        L.orc_pdlp_record.argtypes = [C.POINTER(_LP), C.POINTER(_Unscale), C.POINTER(_Params),
+                                      C.POINTER(_State), C.POINTER(_Scratch), D, D,
+                                      C.POINTER(_Result), C.POINTER(_Tape)]
+        L.orc_pdlp_record.restype = C.c_int32
+        L.orc_unroll_replay.argtypes = [C.POINTER(_LP), C.POINTER(_Tape), C.c_int64, D, D, D, D,
+                                        C.POINTER(C.c_int64)]
+        L.orc_unroll_replay.restype = None
+        L.orc_unroll_adjoint.argtypes = [C.POINTER(_LP), C.POINTER(_Tape), C.c_int64, D, D, D, D,
+                                         D]
+        L.orc_unroll_adjoint.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -368,3 +384,93 @@ def primal_weight_update(dx, dy, omega, theta=0.5, eps_zero=1e-10) -> float:
 
 def initial_primal_weight(view: LPView) -> float:
     return lib().orc_initial_primal_weight(view.ref())
+
+
+def scale_by(lp, d1, d2, c=None, lc=None, uc=None, val=None):
+    """Scaled data of `lp` (or of replacement c, lc, uc, val in original units)
+    under fixed diagonals: A~ = D1 A D2 entry by entry as (d1_i a_ij) d2_j,
+    c~ = D2 c, (lc~, uc~) = D1 (lc, uc), (lv~, uv~) = (lv, uv) / D2."""
+    m, n = lp.m, lp.n
+    rp = np.asarray(lp.row_ptr, dtype=np.int64)
+    rows = np.repeat(np.arange(m), np.diff(rp))
+    cols = np.asarray(lp.col, dtype=np.int64)
+    val = np.asarray(lp.val if val is None else val, dtype=np.float64)
+    vs = (d1[rows] * val) * d2[cols]
+    cc = lp.c if c is None else c
+    l = lp.lc if lc is None else lc
+    u = lp.uc if uc is None else uc
+    fake = type("_D", (), {})()
+    fake.m, fake.n, fake.c, fake.lc, fake.uc, fake.lv, fake.uv = m, n, cc, l, u, lp.lv, lp.uv
+    cs, lcs, ucs, lvs, uvs = scale_vectors(fake, d1, d2)
+    return LPView(m, n, lp.row_ptr, lp.col, vs, cs, lcs, ucs, lvs, uvs)
+
+
+class Unroll:
+    """K accepted steps of Algorithm 1 with their decisions recorded, and the
+    map they define with those decisions held fixed (pdlp_oracle_unroll.c).
+
+    Scaling: D1, D2 from the preconditioning of `lp`; every scaled quantity is
+    formed from the original data by scale_by, for the recorded run and for
+    replays of perturbed data alike.  Gradients are returned in original
+    units: dc = D2 dc~, dlc = D1 dlc~ (0 where lc is infinite), likewise uc,
+    dA_ij = D1_i D2_j dA~_ij; the upstream gradient on x = D2 x~ enters as
+    D2 dL/dx.
+    """
+
+    def __init__(self, lp, K: int, params: Params | None = None):
+        self.lp, self.K = lp, int(K)
+        prm = dataclasses.replace(params or Params(), terminate=False, max_iters=int(K),
+                                  polish=False)
+        _, self.d1, self.d2 = precondition(lp, prm.ruiz_iters, prm.pc)
+        self.view = scale_by(lp, self.d1, self.d2)
+        m, n = lp.m, lp.n
+        z = lambda k: np.zeros(k)
+        arr = {k: z(n) for k in ("x", "aty", "x0", "sx")}
+        arr.update({k: z(m) for k in ("y", "ax", "y0", "sy")})
+        st = _State(*[_d(arr[k]) for k in ("x", "y", "ax", "aty", "x0", "y0", "sx", "sy")])
+        scr_arr = [z(max(n, 1)) for _ in range(6)] + [z(max(m, 1)) for _ in range(6)]
+        scr = _Scratch(*[_d(a) for a in scr_arr])
+        lib().orc_init_state(self.view.ref(), C.byref(st))
+        self.eta = np.zeros(max(self.K, 1))
+        self.omega = np.zeros(max(self.K, 1))
+        self.restart = np.zeros(max(self.K, 1), dtype=np.int32)
+        self.tape = _Tape(self.K, _d(self.eta), _d(self.omega), _i(self.restart))
+        orig = LPView.of(lp)
+        uns = _Unscale(orig.s, _d(self.d1), _d(self.d2), 0.0)
+        ox, oy = z(n), z(m)
+        res = _Result()
+        lib().orc_pdlp_record(self.view.ref(), C.byref(uns), C.byref(prm.cstruct()), C.byref(st),
+                              C.byref(scr), _d(ox), _d(oy), C.byref(res), C.byref(self.tape))
+        self.result = {f: getattr(res, f) for f, _ in _Result._fields_}
+        self.x_scaled = arr["x"].copy()
+        self.x = self.d2 * self.x_scaled
+
+    def replay(self, c=None, lc=None, uc=None, val=None):
+        """x_K (original units) and the activity signature for the given data."""
+        view = self.view if all(a is None for a in (c, lc, uc, val)) else \
+            scale_by(self.lp, self.d1, self.d2, c, lc, uc, val)
+        x = np.zeros(self.lp.n)
+        sig = C.c_int64()
+        lib().orc_unroll_replay(view.ref(), C.byref(self.tape), self.K, _d(x), None, None, None,
+                                C.byref(sig))
+        return self.d2 * x, sig.value
+
+    def backward(self, gx) -> dict:
+        """Gradients of <gx, x_K> in original units (dc, dlc, duc, dval)."""
+        lp = self.lp
+        m, n = lp.m, lp.n
+        gxs = _f64(self.d2 * np.asarray(gx, dtype=np.float64))
+        gc, glc, guc = np.zeros(n), np.zeros(m), np.zeros(m)
+        gval = np.zeros(int(np.asarray(lp.row_ptr)[-1]) if m else 0)
+        rc = lib().orc_unroll_adjoint(self.view.ref(), C.byref(self.tape), self.K, _d(gxs),
+                                      _d(gc), _d(glc), _d(guc), _d(gval) if gval.size else None)
+        if rc != 0:
+            raise MemoryError("oracle adjoint out of memory")
+        rp = np.asarray(lp.row_ptr, dtype=np.int64)
+        rows = np.repeat(np.arange(m), np.diff(rp))
+        cols = np.asarray(lp.col, dtype=np.int64)
+        fin_l = np.isfinite(np.asarray(lp.lc, dtype=np.float64))
+        fin_u = np.isfinite(np.asarray(lp.uc, dtype=np.float64))
+        return {"c": self.d2 * gc, "lc": np.where(fin_l, self.d1 * glc, 0.0),
+                "uc": np.where(fin_u, self.d1 * guc, 0.0),
+                "val": self.d1[rows] * self.d2[cols] * gval}

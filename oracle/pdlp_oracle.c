@@ -600,6 +600,7 @@ typedef struct {
     const orc_params *prm;
     orc_state *st;
     orc_scratch *scr;
+    orc_tape *tape;                    /* optional record of the decisions */
     /* extra buffers */
     double *xb, *yb, *axb, *atyb;      /* average and its products */
     double *xp, *yp;                   /* previous restart point */
@@ -781,6 +782,11 @@ static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish
         int rc = orc_adaptive_step(lp, prm, st, L->scr);
         if (rc != ORC_OK) return ORC_NUMERR;
         double eta = st->last_eta;
+        if (L->tape && st->k < L->tape->cap) {
+            L->tape->eta[st->k] = eta;
+            L->tape->omega[st->k] = st->omega;
+            L->tape->restart[st->k] = 0;
+        }
         st->seta += eta;
         for (int32_t j = 0; j < n; ++j) st->sx[j] += eta * st->x[j];
         for (int32_t i = 0; i < m; ++i) st->sy[i] += eta * st->y[i];
@@ -843,6 +849,7 @@ static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish
         if (why == 1) st->restarts_i += 1;
         if (why == 2) st->restarts_ii += 1;
         if (why == 3) st->restarts_iii += 1;
+        if (L->tape && st->k - 1 < L->tape->cap) L->tape->restart[st->k - 1] = use_cur ? 1 : 2;
         /* previous restart point */
         memcpy(L->xp, st->x0, sizeof(double) * n);
         memcpy(L->yp, st->y0, sizeof(double) * m);
@@ -892,13 +899,16 @@ static void free_ctx(loop_ctx *L) {
  * max_iters - st->k further accepted steps with restart checks and no
  * termination test.  out_x/out_y (scaled, caller owned) receive the returned
  * point (the candidate of the last termination evaluation; the current
- * iterate in the no-termination mode).  Returns the status code.
+ * iterate in the no-termination mode).  Returns the status code.  When
+ * `tape` is not NULL the decisions of every accepted step are recorded in it
+ * (see orc_tape).
  */
-int32_t orc_pdlp(const orc_lp *lp, const orc_unscale *u, const orc_params *prm, orc_state *st,
-                 orc_scratch *scr, double *out_x, double *out_y, orc_result *res) {
+int32_t orc_pdlp_record(const orc_lp *lp, const orc_unscale *u, const orc_params *prm,
+                        orc_state *st, orc_scratch *scr, double *out_x, double *out_y,
+                        orc_result *res, orc_tape *tape) {
     loop_ctx L;
     memset(&L, 0, sizeof L);
-    L.lp = lp; L.u = u; L.prm = prm; L.st = st; L.scr = scr;
+    L.lp = lp; L.u = u; L.prm = prm; L.st = st; L.scr = scr; L.tape = tape;
     if (!alloc_ctx(&L, lp->m, lp->n)) { free_ctx(&L); return -3; }
     orc_kkt kk;
     memset(&kk, 0, sizeof kk);
@@ -929,4 +939,10 @@ int32_t orc_pdlp(const orc_lp *lp, const orc_unscale *u, const orc_params *prm, 
     res->eta = st->eta_hat;
     free_ctx(&L);
     return res->status;
+}
+
+/* orc_pdlp_record without a record. */
+int32_t orc_pdlp(const orc_lp *lp, const orc_unscale *u, const orc_params *prm, orc_state *st,
+                 orc_scratch *scr, double *out_x, double *out_y, orc_result *res) {
+    return orc_pdlp_record(lp, u, prm, st, scr, out_x, out_y, res, NULL);
 }

@@ -87,4 +87,21 @@ typedef struct {
     double primal_res_abs, primal_res_rel, dual_res_abs, dual_res_rel;
 } orc_kkt;
 
+/*
+ * Decisions of an Algorithm 1 run, recorded per accepted step k = 0 .. cap-1
+ * (caller-owned arrays): the step size eta and primal weight omega the step
+ * used, and restart[k] = 0 (none), 1 (restart to the current iterate) or 2
+ * (restart to the average) for a restart taken right after that step.
+ */
+typedef struct {
+    int64_t cap;
+    double *eta, *omega;
+    int32_t *restart;
+} orc_tape;
+
+/* Sparse products and the dual case step (pdlp_oracle.c). */
+void orc_spmv(const orc_lp *lp, const double *x, double *out);
+void orc_spmv_t(const orc_lp *lp, const double *y, double *out);
+double orc_dual_case(double yhat, double sigma, double lc, double uc);
+
 #endif

@@ -460,3 +460,86 @@ def test_feasibility_polishing_on_planted_lp():
     assert r["primal_res_rel"] <= 1e-8 and r["dual_res_rel"] <= 1e-8 and r["rel_gap"] <= 1e-2
     x, _ = s.solution()
     assert abs(lp.c @ x - lp.p_star) <= 2e-2 * abs(lp.p_star)
+
+
+# ------------------------------------------------------- unrolled map and adjoint
+#
+# The map of K accepted steps with the recorded decisions held fixed is
+# affine in (c, lc, uc) and polynomial in the matrix values once the
+# projection and dual-case selections are fixed; its adjoint is pinned by
+# central differences of the replay (independent of the adjoint code), by the
+# one-step closed form and by exact affinity in c.
+
+def _unroll_case():
+    lp = lpgen.planted_uniform(60, 100, 5, seed=3)
+    return lp, oracle.Unroll(lp, 120)
+
+
+def test_unroll_records_both_restart_kinds_and_replays_bitwise():
+    lp, U = _unroll_case()
+    kinds = set(np.unique(U.restart).tolist())
+    assert kinds == {0, 1, 2}
+    assert U.result["iterations"] == 120
+    x, _ = U.replay()
+    assert np.array_equal(x, U.x)
+    # the recorded run is the oracle's Algorithm 1 on the same scaled data
+    assert np.all(U.eta[:120] > 0) and np.all(U.omega[:120] > 0)
+
+
+def _direction(rng, base, scale_rel=True):
+    base = np.asarray(base, dtype=np.float64)
+    fin = np.isfinite(base)
+    mag = np.where(fin, np.abs(np.where(fin, base, 0.0)), 0.0).clip(1e-3) if scale_rel else 1.0
+    return np.where(fin, rng.standard_normal(base.size) * mag, 0.0)
+
+
+@pytest.mark.parametrize("name,h", [("c", 1e-5), ("lc", 1e-5), ("uc", 1e-5), ("val", 1e-5)])
+def test_unroll_adjoint_matches_central_differences(name, h):
+    lp, U = _unroll_case()
+    rng = np.random.default_rng(1)
+    gx = rng.standard_normal(lp.n)
+    g = U.backward(gx)
+    _, sig = U.replay()
+    base = np.asarray(getattr(lp, name), dtype=np.float64)
+    for trial in range(3):
+        d = _direction(rng, base)
+        xp, sp = U.replay(**{name: base + h * d})
+        xm, sm = U.replay(**{name: base - h * d})
+        assert sp == sig and sm == sig  # same projection / dual-case selections
+        fd = (gx @ xp - gx @ xm) / (2 * h)
+        an = g[name] @ d
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-12), (name, trial, fd, an)
+
+
+def test_unroll_is_affine_in_c():
+    lp, U = _unroll_case()
+    rng = np.random.default_rng(2)
+    gx = rng.standard_normal(lp.n)
+    g = U.backward(gx)
+    d = _direction(rng, lp.c)
+    _, sig = U.replay()
+    vals = []
+    for h in (2e-6, 1e-5):
+        xp, sp = U.replay(c=lp.c + h * d)
+        xm, sm = U.replay(c=lp.c - h * d)
+        assert sp == sig and sm == sig
+        vals.append((gx @ xp - gx @ xm) / (2 * h))
+    assert vals[0] == pytest.approx(vals[1], rel=1e-7)
+    assert g["c"] @ d == pytest.approx(vals[1], rel=1e-7)
+
+
+def test_unroll_one_step_closed_form():
+    """K = 1 from (proj_X(0), 0): x_1 = proj(x_0 - tau c~), so
+    dL/dc_j = -tau p_j D2_j^2 g_j and every other gradient is 0."""
+    lp = lpgen.planted_uniform(40, 70, 5, seed=9)
+    U = oracle.Unroll(lp, 1)
+    rng = np.random.default_rng(3)
+    gx = rng.standard_normal(lp.n)
+    g = U.backward(gx)
+    tau = U.eta[0] / U.omega[0]
+    x0 = np.clip(0.0, U.view.lv, U.view.uv)
+    v = x0 - tau * U.view.c
+    p = (v > U.view.lv) & (v < U.view.uv)
+    expect = -tau * p * U.d2 ** 2 * gx
+    np.testing.assert_allclose(g["c"], expect, rtol=1e-15, atol=0)
+    assert not g["lc"].any() and not g["uc"].any() and not g["val"].any()
