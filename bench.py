@@ -140,6 +140,46 @@ def batch_section(pd, count, loop_n):
     }
 
 
+def unroll_section(pd, count, K):
+    """Differentiable layer: `count` planted 2,000 x 4,000 LPs (10 rows per column),
+    K unrolled steps with decisions recorded and checkpoints every 25 steps, an
+    N(0,1) upstream gradient on x; backward = gradients for c, lc, uc and the
+    nonzeros of A."""
+    import numpy as np
+    import lpgen
+    t0 = time.perf_counter()
+    lps = [lpgen.layer_lp(i) for i in range(count)]
+    log(f"unroll: generated {count} LPs in {time.perf_counter() - t0:.1f}s")
+    u = pd.Unroll(lps)
+    gx = np.random.default_rng(2501).standard_normal(u.N)
+    u.forward(K, 25)          # warm-up pair (first-touch allocation of the work buffers)
+    u.backward(gx)
+    fw, bw, rp = [], [], []
+    for _ in range(3):
+        u.forward(K, 25)
+        u.backward(gx)
+        u.replay()
+        st = u.stats()
+        fw.append(st["forward_seconds"])
+        bw.append(st["backward_seconds"])
+        rp.append(st["replay_seconds"])
+    log(f"unroll: forward {fw} backward {bw} replay {rp} stats {st}")
+    nnz = sum(lp.nnz for lp in lps)
+    tf, tb = float(np.median(fw)), float(np.median(bw))
+    return {
+        "workload": (f"{count} planted LPs of 2000 x 4000, 10 rows per column ({nnz} nonzeros), "
+                     f"K = {K} unrolled steps, checkpoints every 25, N(0,1) upstream gradient"),
+        "forward_s": tf, "backward_s": tb, "bwd_over_fwd": tb / tf,
+        "replay_s": float(np.median(rp)),
+        "backward_replay_s": st["backward_replay_seconds"],
+        "backward_reverse_s": st["backward_reverse_seconds"],
+        "restarts": st["restarts"],
+        "note": ("forward = Algorithm 1 with decisions recorded (adaptive steps, restart checks); "
+                 "backward = segment replays from checkpoints + reverse steps; median of 3, "
+                 "host transfers excluded"),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +193,9 @@ def main():
                     help="instances of the batched-solver measurement (0 skips it)")
     ap.add_argument("--batch-loop", type=int, default=16,
                     help="instances solved one by one for the loop comparison")
+    ap.add_argument("--unroll-count", type=int, default=256,
+                    help="instances of the differentiable-layer measurement (0 skips it)")
+    ap.add_argument("--unroll-k", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -268,6 +311,8 @@ def main():
     }
     if args.batch_count > 0:
         out["batched"] = batch_section(pd, args.batch_count, args.batch_loop)
+    if args.unroll_count > 0:
+        out["unroll"] = unroll_section(pd, args.unroll_count, args.unroll_k)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(lp, args.cpu_steps)

@@ -285,6 +285,84 @@ typedef struct pdlp_batch_stats {
 } pdlp_batch_stats;
 int pdlp_batch_get_stats(const pdlp_batch *b, pdlp_batch_stats *stats);
 
+/*
+ * Differentiable unrolled PDHG over a batch of LPs.
+ *
+ * The map: K accepted steps of the PDHG update (Section 2, eq.
+ * "specialized-pdhg" with tau = eta/omega, sigma = eta*omega, the case form
+ * of the dual step) with the averages and restarts of Algorithm 1, from
+ * (proj_X(0), 0), with every decision of a recorded Algorithm 1 run held
+ * fixed: the step size eta and primal weight omega of each accepted step
+ * (Algorithm 2, Algorithm 3) and each restart with its candidate (Section 3,
+ * "Adaptive restarts").  Per instance it sends the data (c, lc, uc and the
+ * nonzeros of A) to x_K (original units).  Its derivative treats the
+ * projection onto the variable box and the case of the dual step as fixed
+ * selections (derivative 1 strictly inside the box, 0 on it).  The diagonal
+ * scalings D1, D2 are computed at creation (Ruiz + Pock-Chambolle) and are
+ * constants: every scaled quantity is formed from the data as
+ * A~_ij = (D1_i A_ij) D2_j, c~ = D2 c, (lc~, uc~) = D1 (lc, uc),
+ * (lv~, uv~) = (lv, uv) / D2.
+ */
+typedef struct pdlp_unroll pdlp_unroll;   /* opaque: batch, data, tape, checkpoints */
+
+/* Create from host arrays laid out as for pdlp_batch_create (no objective
+ * offsets).  params: scaling parameters (NULL = defaults).  Errors as
+ * pdlp_batch_create. */
+int pdlp_unroll_create(int32_t count, const int32_t *m, const int32_t *n, const int64_t *nnz,
+                       const int32_t *row_ptr_host, const int32_t *col_host,
+                       const double *val_host, const double *c_host, const double *lc_host,
+                       const double *uc_host, const double *lv_host, const double *uv_host,
+                       const pdlp_params *params, void *hip_stream, pdlp_unroll **out);
+void pdlp_unroll_destroy(pdlp_unroll *u);
+
+/* Replace the data (original units, concatenated as at creation; any
+ * pointer may be NULL to keep that part).  The sparsity pattern, lv, uv and
+ * D1, D2 are unchanged.  Errors: INVALID_ARGUMENT for non-finite c or
+ * values, NaN or inverted constraint bounds, a lower bound of +inf or an
+ * upper bound of -inf. */
+int pdlp_unroll_set_data(pdlp_unroll *u, const double *c, const double *lc, const double *uc,
+                         const double *val);
+
+/* Forward pass: Algorithm 1 with restart checks and no termination test
+ * runs exactly K accepted steps on every instance (params: the algorithm's
+ * constants, NULL = defaults; tolerances and polishing are not used),
+ * recording its decisions and checkpointing the state every ckpt_every
+ * steps.  x (sum n) receives x_K in original units, or may be NULL.
+ * K >= 0, ckpt_every >= 1.  Errors: STATE on a numerical error. */
+int pdlp_unroll_forward(pdlp_unroll *u, const pdlp_params *params, int64_t K, int32_t ckpt_every,
+                        double *x);
+
+/* The map at the current data with the recorded decisions: x (sum n) as in
+ * pdlp_unroll_forward; signature (count entries, nullable) receives per
+ * instance the number of (step, coordinate) pairs with x strictly inside its
+ * box plus those where the dual step moves y, which identifies the fixed
+ * selections (equal signatures for two data sets: same selections, in
+ * practice).  Needs a forward pass. */
+int pdlp_unroll_replay(pdlp_unroll *u, double *x, int64_t *signature);
+
+/* Backward pass: given gx = dL/dx_K (sum n, original units), the gradients
+ * of L with respect to c (sum n), lc and uc (sum m; 0 where the bound is
+ * infinite) and the nonzeros of A (sum nnz, in the caller's CSR order), at
+ * the current data along the recorded decisions.  Segments between
+ * checkpoints are replayed, then reversed.  Outputs may be NULL. */
+int pdlp_unroll_backward(pdlp_unroll *u, const double *gx, double *gc, double *glc,
+                         double *guc, double *gval);
+
+/* Recorded decisions, count x K each (instance-major): eta and omega of
+ * every accepted step; restart[i K + k] = 0, 1 (to the current iterate) or
+ * 2 (to the average) for a restart right after step k. */
+int pdlp_unroll_get_tape(const pdlp_unroll *u, double *eta, double *omega, int32_t *restart);
+
+typedef struct pdlp_unroll_stats {
+    int64_t K, ckpt, restarts;
+    double forward_seconds;          /* pdlp_unroll_forward, before copying x out */
+    double replay_seconds;           /* pdlp_unroll_replay, likewise */
+    double backward_seconds;         /* pdlp_unroll_backward, after copying gx in, before copying out */
+    double backward_replay_seconds;  /* its segment replays */
+    double backward_reverse_seconds; /* its reverse steps */
+} pdlp_unroll_stats;
+int pdlp_unroll_get_stats(const pdlp_unroll *u, pdlp_unroll_stats *stats);
+
 /* Message for the last error on this thread ("" if none). */
 const char *pdlp_last_error(void);
 

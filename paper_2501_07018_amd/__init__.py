@@ -89,6 +89,13 @@ class BatchStats(C.Structure):
                 ("step_seconds", C.c_double), ("check_seconds", C.c_double)]
 
 
+class UnrollStats(C.Structure):
+    _fields_ = [("K", C.c_int64), ("ckpt", C.c_int64), ("restarts", C.c_int64),
+                ("forward_seconds", C.c_double), ("replay_seconds", C.c_double),
+                ("backward_seconds", C.c_double), ("backward_replay_seconds", C.c_double),
+                ("backward_reverse_seconds", C.c_double)]
+
+
 class StateBlob(C.Structure):
     _fields_ = [(k, D) for k in ("x", "y", "ax", "aty", "x0", "y0", "sx", "sy")] + \
                [(k, C.c_double) for k in ("seta", "omega", "eta_hat", "mu_ref", "mu_c_prev",
@@ -104,7 +111,10 @@ EXPORTS = ("pdlp_problem_create", "pdlp_problem_destroy", "pdlp_problem_dims",
            "pdlp_state_create", "pdlp_state_destroy", "pdlp_iterate_k", "pdlp_state_get",
            "pdlp_state_set", "pdlp_norm_gap", "pdlp_last_error", "pdlp_state_solve",
            "pdlp_state_kernel_stats", "pdlp_measure_device_rates", "pdlp_batch_create",
-           "pdlp_batch_destroy", "pdlp_batch_dims", "pdlp_batch_solve", "pdlp_batch_get_stats")
+           "pdlp_batch_destroy", "pdlp_batch_dims", "pdlp_batch_solve", "pdlp_batch_get_stats",
+           "pdlp_unroll_create", "pdlp_unroll_destroy", "pdlp_unroll_set_data",
+           "pdlp_unroll_forward", "pdlp_unroll_replay", "pdlp_unroll_backward",
+           "pdlp_unroll_get_tape", "pdlp_unroll_get_stats")
 
 
 def lib() -> C.CDLL:
@@ -145,6 +155,16 @@ def lib() -> C.CDLL:
     L.pdlp_batch_dims.argtypes = [vp, I32, I64, I64, I64]
     L.pdlp_batch_solve.argtypes = [vp, C.POINTER(Params), C.POINTER(Result), D, D, D]
     L.pdlp_batch_get_stats.argtypes = [vp, C.POINTER(BatchStats)]
+    L.pdlp_unroll_create.argtypes = [C.c_int32, I32, I32, I64, I32, I32, D, D, D, D, D, D,
+                                     C.POINTER(Params), vp, C.POINTER(vp)]
+    L.pdlp_unroll_destroy.argtypes = [vp]
+    L.pdlp_unroll_destroy.restype = None
+    L.pdlp_unroll_set_data.argtypes = [vp, D, D, D, D]
+    L.pdlp_unroll_forward.argtypes = [vp, C.POINTER(Params), C.c_int64, C.c_int32, D]
+    L.pdlp_unroll_replay.argtypes = [vp, D, I64]
+    L.pdlp_unroll_backward.argtypes = [vp, D, D, D, D, D]
+    L.pdlp_unroll_get_tape.argtypes = [vp, D, D, I32]
+    L.pdlp_unroll_get_stats.argtypes = [vp, C.POINTER(UnrollStats)]
     L.pdlp_last_error.argtypes = []
     L.pdlp_last_error.restype = C.c_char_p
     _lib = L
@@ -389,6 +409,91 @@ class Batch:
     def close(self):
         if self.h:
             pdlp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _pack(lps):
+    m = np.array([lp.m for lp in lps], dtype=np.int32)
+    n = np.array([lp.n for lp in lps], dtype=np.int32)
+    nnz = np.array([int(lp.row_ptr[-1]) if len(lp.row_ptr) else 0 for lp in lps], dtype=np.int64)
+    rp = np.ascontiguousarray(np.concatenate([np.asarray(lp.row_ptr, dtype=np.int32)
+                                              for lp in lps]), dtype=np.int32)
+    cl = np.ascontiguousarray(np.concatenate([np.asarray(lp.col, dtype=np.int32) for lp in lps]),
+                              dtype=np.int32)
+    cat = {k: _f64(np.concatenate([np.asarray(getattr(lp, k), dtype=np.float64) for lp in lps]))
+           for k in ("val", "c", "lc", "uc", "lv", "uv")}
+    return m, n, nnz, rp, cl, cat
+
+
+class Unroll:
+    """Owner of a pdlp_unroll handle: the differentiable K-step map over a batch.
+
+    Arrays are concatenated over instances in instance order (x, c: sum n;
+    lc, uc: sum m; val: sum nnz in each instance's CSR order)."""
+
+    def __init__(self, lps, params: Params | None = None, stream=None):
+        self.count = len(lps)
+        m, n, nnz, rp, cl, cat = _pack(lps)
+        self.m, self.n, self.nnz = m, n, nnz
+        self.M, self.N, self.NZ = int(m.sum()), int(n.sum()), int(nnz.sum())
+        self.h = C.c_void_p()
+        _check(lib().pdlp_unroll_create(int(self.count), m.ctypes.data_as(I32),
+                                        n.ctypes.data_as(I32),
+                                        nnz.ctypes.data_as(C.POINTER(C.c_int64)),
+                                        rp.ctypes.data_as(I32), cl.ctypes.data_as(I32),
+                                        *[_d(cat[k]) for k in ("val", "c", "lc", "uc", "lv", "uv")],
+                                        C.byref(params) if params is not None else None, stream,
+                                        C.byref(self.h)))
+        self.K = None
+
+    def set_data(self, c=None, lc=None, uc=None, val=None):
+        arrs = [None if a is None else _f64(a) for a in (c, lc, uc, val)]
+        _check(lib().pdlp_unroll_set_data(self.h, *[_d(a) for a in arrs]))
+
+    def forward(self, K, ckpt=25, params: Params | None = None):
+        x = np.empty(self.N)
+        _check(lib().pdlp_unroll_forward(self.h, C.byref(params) if params is not None else None,
+                                         int(K), int(ckpt), _d(x)))
+        self.K = int(K)
+        return x
+
+    def replay(self):
+        x = np.empty(self.N)
+        sig = np.empty(self.count, dtype=np.int64)
+        _check(lib().pdlp_unroll_replay(self.h, _d(x), sig.ctypes.data_as(C.POINTER(C.c_int64))))
+        return x, sig
+
+    def backward(self, gx) -> dict:
+        gx = _f64(gx)
+        out = {"c": np.empty(self.N), "lc": np.empty(self.M), "uc": np.empty(self.M),
+               "val": np.empty(self.NZ)}
+        _check(lib().pdlp_unroll_backward(self.h, _d(gx), _d(out["c"]), _d(out["lc"]),
+                                          _d(out["uc"]), _d(out["val"])))
+        return out
+
+    def tape(self):
+        K = self.K or 0
+        eta = np.empty(self.count * K)
+        omega = np.empty(self.count * K)
+        rst = np.empty(self.count * K, dtype=np.int32)
+        _check(lib().pdlp_unroll_get_tape(self.h, _d(eta), _d(omega), rst.ctypes.data_as(I32)))
+        return (eta.reshape(self.count, K), omega.reshape(self.count, K),
+                rst.reshape(self.count, K))
+
+    def stats(self) -> dict:
+        st = UnrollStats()
+        _check(lib().pdlp_unroll_get_stats(self.h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in UnrollStats._fields_}
+
+    def close(self):
+        if self.h:
+            lib().pdlp_unroll_destroy(self.h)
             self.h = None
 
     def __del__(self):

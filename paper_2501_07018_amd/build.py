@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libpdlp.so")
 SOURCES = [os.path.join(HERE, "csrc", f) for f in ("pdlp_kernels.hip", "pdlp_batch_kernels.hip",
-                                                      "pdlp_host.hip", "pdlp_batch.hip")]
+                                                      "pdlp_unroll_kernels.hip", "pdlp_host.hip",
+                                                      "pdlp_batch.hip", "pdlp_unroll.hip")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

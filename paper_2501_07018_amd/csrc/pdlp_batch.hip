@@ -24,7 +24,7 @@
 #include <limits>
 #include <vector>
 
-#include "pdlp_host.h"
+#include "pdlp_batch.h"
 
 using namespace pdlp::host;
 using pdlp::BatchMaps;
@@ -43,8 +43,10 @@ constexpr int kBatchGapChunk = 6;
 // XCDs of the device: workgroup w of a launch runs on XCD w mod kXcds.
 constexpr int kXcds = 8;
 
+}  // namespace
+
 // Device buffers of a batch solve, sized by the packed problem.
-struct BatchWork {
+struct pdlp::host::BatchWork {
     Arena arena;
     Iter it{};
     double *x0, *y0, *xb, *yb, *axb, *atyb, *xp, *yp, *xo, *yo, *ro;
@@ -56,29 +58,17 @@ struct BatchWork {
     int32_t *sel_d, *sel_h;
     double *sv_d, *sv_h, *om_d, *om_h, *zero_d;
     int32_t *list_d, *list_h;  // ilist | alist | tlist | clist of the running instances
+    int32_t *slot_d, *slot_h;  // checkpoint slot per instance (-1: none) of a recorded run
 };
 
-enum { MASK_CHK = 0, MASK_KKT, MASK_RST, MASK_RST_AVG, kMasks };
-
-}  // namespace
-
-struct pdlp_batch {
-    int32_t B = 0;
-    std::vector<int32_t> m, n, roff, coff;
-    std::vector<double> obj_offset;
-    pdlp_problem *P = nullptr;
-    Arena arena;
-    BatchMaps bm;
-    std::vector<int32_t> aoff, toff;  // host copies of the block ranges per instance
-    BatchWork *W = nullptr;
-    pdlp_batch_stats stats{};  // of the last solve
-    ~pdlp_batch() {
-        delete W;
-        delete P;
-    }
-};
+pdlp_batch::~pdlp_batch() {
+    delete W;
+    delete P;
+}
 
 namespace {
+
+enum { MASK_CHK = 0, MASK_KKT, MASK_RST, MASK_RST_AVG, kMasks };
 
 BatchWork *make_work(pdlp_batch *b) {
     pdlp_problem *P = b->P;
@@ -123,6 +113,8 @@ BatchWork *make_work(pdlp_batch *b) {
         const size_t nl = (size_t)B + 2 * (size_t)kXcds * ((size_t)b->bm.nA + b->bm.nT);
         W->list_d = a.dev<int32_t>(nl);
         W->list_h = a.host<int32_t>(nl);
+        W->slot_d = a.dev<int32_t>(B);
+        W->slot_h = a.host<int32_t>(B);
         HIPCHECK(pdlp::launch_fill(P->stream, B, W->zero_d, 0.0));
         HIPCHECK(hipStreamSynchronize(P->stream));
     } catch (...) {
@@ -168,7 +160,36 @@ bool met(const pdlp_params &prm, const KktHost &k) {
 
 class BatchSolver {
   public:
-    BatchSolver(pdlp_batch *b, const pdlp_params &prm) : b_(b), P_(b->P), W_(*b->W), prm_(prm) {}
+    BatchSolver(pdlp_batch *b, const pdlp_params &prm, BatchRecord *rec = nullptr)
+        : b_(b), P_(b->P), W_(*b->W), prm_(prm), rec_(rec) {}
+
+    // Exactly K accepted steps per instance with restart checks and no
+    // termination test (the loop of pdlp_iterate_k), recording the decisions.
+    void run_record() {
+        const long long K = rec_->K;
+        init();
+        take_checkpoints(true);
+        for (auto &st : inst_)
+            if (K == 0) st.status = PDLP_STATUS_ITERATION_LIMIT;
+        while (any_running()) {
+            set_active(false);
+            run_round(K);
+            for (int i = 0; i < B(); ++i)
+                if (inst_[i].status == PDLP_STATUS_NUMERICAL_ERROR)
+                    throw LibError(PDLP_ERR_STATE, "numerical error in instance " +
+                                                       std::to_string(i) + " at step " +
+                                                       std::to_string(W_.ctrl_h[i].k));
+            check_round(K);
+            take_checkpoints(false);
+            for (int i = 0; i < B(); ++i) {
+                if (inst_[i].status == PDLP_STATUS_NUMERICAL_ERROR)
+                    throw LibError(PDLP_ERR_STATE,
+                                   "numerical error in instance " + std::to_string(i));
+                if (inst_[i].status < 0 && W_.ctrl_h[i].k >= K)
+                    inst_[i].status = PDLP_STATUS_ITERATION_LIMIT;
+            }
+        }
+    }
 
     void run(pdlp_result *res, double *x_host, double *y_host, double *r_host) {
         const double t0 = now_s();
@@ -216,6 +237,29 @@ class BatchSolver {
     pdlp_problem *P_;
     BatchWork &W_;
     pdlp_params prm_;
+    BatchRecord *rec_ = nullptr;
+
+    // Checkpoints of a recorded run: every running instance whose step count
+    // is a multiple of the cadence (and below K) stores its state, after the
+    // restart of that boundary; at the start (all = true) every instance.
+    void take_checkpoints(bool all) {
+        if (!rec_) return;
+        bool any = false;
+        for (int i = 0; i < B(); ++i) {
+            const long long k = W_.ctrl_h[i].k;
+            const bool due = all || (inst_[i].status < 0 && k > 0 && k < rec_->K &&
+                                     k % rec_->ckpt == 0);
+            W_.slot_h[i] = due ? (int32_t)(k / rec_->ckpt) : -1;
+            any = any || due;
+        }
+        if (!any) return;
+        HIPCHECK(hipMemcpyAsync(W_.slot_d, W_.slot_h, sizeof(int32_t) * B(),
+                                hipMemcpyHostToDevice, s()));
+        HIPCHECK(pdlp::launch_b_checkpoint(s(), P_->A, P_->AT, bm_, W_.slot_d, W_.it.X[0],
+                                           W_.it.Y[0], W_.it.sx, W_.it.sy, rec_->ck, P_->n,
+                                           P_->m));
+        sync();
+    }
     int rc_mode_ = 1;
     std::vector<Inst> inst_;
     std::vector<KktHost> kkt_;
@@ -281,6 +325,11 @@ class BatchSolver {
                                         sizeof(int32_t) * len[q], hipMemcpyHostToDevice, s()));
         sync();
         bm_ = base;
+        if (rec_) {
+            bm_.tape_eta = rec_->eta;
+            bm_.tape_omega = rec_->omega;
+            bm_.tape_K = rec_->K;
+        }
         bm_.ni = (int32_t)il.size();
         bm_.na = na;
         bm_.nt = nt;
@@ -446,6 +495,7 @@ class BatchSolver {
                 continue;
             }
             long long kb = (c.k / ce + 1) * ce;
+            if (rec_) kb = std::min<long long>(kb, (c.k / rec_->ckpt + 1) * rec_->ckpt);
             kb = std::min(kb, next_art(c.k, c.t, prm_.beta_art, max_k));
             kb = std::min(kb, max_k);
             c.block_target = kb - c.k;
@@ -500,7 +550,7 @@ class BatchSolver {
             if (st.status >= 0) continue;
             st.full = (c.k % prm_.check_every) == 0;
             st.art = (double)c.t >= prm_.beta_art * (double)c.k;
-            st.capchk = c.k == max_k;
+            st.capchk = !rec_ && c.k == max_k;
             st.chk = st.full || st.art || st.capchk;
             mask(MASK_CHK)[i] = st.chk;
             W_.sv_h[i] = c.seta > 0.0 ? c.seta : 1.0;
@@ -539,7 +589,7 @@ class BatchSolver {
             st.use_cur = mu_cur < mu_avg;  // a tie goes to the average
             st.mu_c = st.use_cur ? mu_cur : mu_avg;
             W_.sel_h[i] = st.use_cur ? 0 : 1;
-            if (st.full || st.capchk) {
+            if (!rec_ && (st.full || st.capchk)) {
                 mask(MASK_KKT)[i] = 1;
                 any_kkt = true;
             }
@@ -585,6 +635,10 @@ class BatchSolver {
             st.r_i += why == 1;
             st.r_ii += why == 2;
             st.r_iii += why == 3;
+            if (rec_) {
+                const long long k = W_.ctrl_h[i].k;
+                if (k >= 1 && k <= rec_->K) rec_->rtype[(size_t)i * rec_->K + (k - 1)] = st.use_cur ? 1 : 2;
+            }
             mask(MASK_RST)[i] = 1;
             mask(MASK_RST_AVG)[i] = !st.use_cur;
             any_rst = true;
@@ -734,6 +788,87 @@ void build_maps(pdlp_batch *b) {
 
 }  // namespace
 
+pdlp_batch *pdlp::host::make_batch(int32_t count, const int32_t *m, const int32_t *n,
+                                   const int64_t *nnz, const int32_t *row_ptr,
+                                   const int32_t *col, const double *val, const double *c,
+                                   const double *lc, const double *uc, const double *lv,
+                                   const double *uv, const double *obj_offset,
+                                   const pdlp_params *params, void *hip_stream) {
+    if (count < 1) invalid("count must be >= 1");
+    if (!m || !n || !nnz || !row_ptr) invalid("NULL size array");
+    int64_t M = 0, N = 0, NZ = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        if (m[i] < 0 || n[i] < 1 || nnz[i] < 0)
+            invalid("instance " + std::to_string(i) + ": need m >= 0, n >= 1, nnz >= 0");
+        M += m[i];
+        N += n[i];
+        NZ += nnz[i];
+    }
+    const int64_t lim = std::numeric_limits<int32_t>::max();
+    if (M >= lim || N >= lim || NZ >= lim) invalid("batch totals must stay below 2^31");
+    if ((NZ > 0 && (!col || !val)) || !c || (M > 0 && (!lc || !uc)) || !lv || !uv)
+        invalid("NULL input array");
+    // per-instance checks, then pack: global row pointers and column labels
+    std::vector<int32_t> rp((size_t)M + 1), cg((size_t)NZ);
+    std::vector<int32_t> roff(count + 1), coff(count + 1);
+    std::vector<int32_t> row_breaks, col_breaks;
+    int64_t r0 = 0, c0 = 0, e0 = 0, p0 = 0;
+    rp[0] = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const int32_t *rpi = row_ptr + p0;
+        try {
+            validate(m[i], n[i], nnz[i], rpi, NZ > 0 ? col + e0 : nullptr,
+                     NZ > 0 ? val + e0 : nullptr, c + c0, M > 0 ? lc + r0 : nullptr,
+                     M > 0 ? uc + r0 : nullptr, lv + c0, uv + c0);
+        } catch (const LibError &e) {
+            throw LibError(e.code, "instance " + std::to_string(i) + ": " + e.what());
+        }
+        for (int64_t e = 0; e < nnz[i]; ++e) cg[e0 + e] = (int32_t)(col[e0 + e] + c0);
+        for (int32_t r = 0; r < m[i]; ++r) rp[r0 + r + 1] = (int32_t)(e0 + rpi[r + 1]);
+        roff[i] = (int32_t)r0;
+        coff[i] = (int32_t)c0;
+        row_breaks.push_back((int32_t)r0);
+        col_breaks.push_back((int32_t)c0);
+        r0 += m[i];
+        c0 += n[i];
+        e0 += nnz[i];
+        p0 += (int64_t)m[i] + 1;
+    }
+    roff[count] = (int32_t)M;
+    coff[count] = (int32_t)N;
+    auto *b = new pdlp_batch();
+    try {
+        b->B = count;
+        b->m.assign(m, m + count);
+        b->n.assign(n, n + count);
+        b->roff = roff;
+        b->coff = coff;
+        b->obj_offset.assign(count, 0.0);
+        if (obj_offset)
+            for (int32_t i = 0; i < count; ++i) {
+                if (!std::isfinite(obj_offset[i])) invalid("objective offset must be finite");
+                b->obj_offset[i] = obj_offset[i];
+            }
+        b->P = create_problem((int32_t)M, (int32_t)N, NZ, rp.data(), cg.data(), val, c, lc, uc,
+                              lv, uv, 0.0, params, hip_stream, &row_breaks, &col_breaks, true);
+        build_maps(b);
+    } catch (...) {
+        delete b;
+        throw;
+    }
+    return b;
+}
+
+void pdlp::host::batch_record(pdlp_batch *b, const pdlp_params &prm, BatchRecord &rec) {
+    if (!b->W) b->W = make_work(b);
+    BatchSolver solver(b, prm, &rec);
+    solver.run_record();
+}
+
+const double *pdlp::host::batch_current_x(const pdlp_batch *b) {
+    return b->W ? b->W->it.X[0] : nullptr;
+}
+
 extern "C" {
 
 int pdlp_batch_create(int32_t count, const int32_t *m, const int32_t *n, const int64_t *nnz,
@@ -744,69 +879,8 @@ int pdlp_batch_create(int32_t count, const int32_t *m, const int32_t *n, const i
     return guarded([&] {
         if (!out) invalid("out is NULL");
         *out = nullptr;
-        if (count < 1) invalid("count must be >= 1");
-        if (!m || !n || !nnz || !row_ptr) invalid("NULL size array");
-        int64_t M = 0, N = 0, NZ = 0;
-        for (int32_t i = 0; i < count; ++i) {
-            if (m[i] < 0 || n[i] < 1 || nnz[i] < 0)
-                invalid("instance " + std::to_string(i) + ": need m >= 0, n >= 1, nnz >= 0");
-            M += m[i];
-            N += n[i];
-            NZ += nnz[i];
-        }
-        const int64_t lim = std::numeric_limits<int32_t>::max();
-        if (M >= lim || N >= lim || NZ >= lim) invalid("batch totals must stay below 2^31");
-        if ((NZ > 0 && (!col || !val)) || !c || (M > 0 && (!lc || !uc)) || !lv || !uv)
-            invalid("NULL input array");
-        // per-instance checks, then pack: global row pointers and column labels
-        std::vector<int32_t> rp((size_t)M + 1), cg((size_t)NZ);
-        std::vector<int32_t> roff(count + 1), coff(count + 1);
-        std::vector<int32_t> row_breaks, col_breaks;
-        int64_t r0 = 0, c0 = 0, e0 = 0, p0 = 0;
-        rp[0] = 0;
-        for (int32_t i = 0; i < count; ++i) {
-            const int32_t *rpi = row_ptr + p0;
-            try {
-                validate(m[i], n[i], nnz[i], rpi, NZ > 0 ? col + e0 : nullptr,
-                         NZ > 0 ? val + e0 : nullptr, c + c0, M > 0 ? lc + r0 : nullptr,
-                         M > 0 ? uc + r0 : nullptr, lv + c0, uv + c0);
-            } catch (const LibError &e) {
-                throw LibError(e.code, "instance " + std::to_string(i) + ": " + e.what());
-            }
-            for (int64_t e = 0; e < nnz[i]; ++e) cg[e0 + e] = (int32_t)(col[e0 + e] + c0);
-            for (int32_t r = 0; r < m[i]; ++r) rp[r0 + r + 1] = (int32_t)(e0 + rpi[r + 1]);
-            roff[i] = (int32_t)r0;
-            coff[i] = (int32_t)c0;
-            row_breaks.push_back((int32_t)r0);
-            col_breaks.push_back((int32_t)c0);
-            r0 += m[i];
-            c0 += n[i];
-            e0 += nnz[i];
-            p0 += (int64_t)m[i] + 1;
-        }
-        roff[count] = (int32_t)M;
-        coff[count] = (int32_t)N;
-        auto *b = new pdlp_batch();
-        try {
-            b->B = count;
-            b->m.assign(m, m + count);
-            b->n.assign(n, n + count);
-            b->roff = roff;
-            b->coff = coff;
-            b->obj_offset.assign(count, 0.0);
-            if (obj_offset)
-                for (int32_t i = 0; i < count; ++i) {
-                    if (!std::isfinite(obj_offset[i])) invalid("objective offset must be finite");
-                    b->obj_offset[i] = obj_offset[i];
-                }
-            b->P = create_problem((int32_t)M, (int32_t)N, NZ, rp.data(), cg.data(), val, c, lc, uc,
-                                  lv, uv, 0.0, params, hip_stream, &row_breaks, &col_breaks, true);
-            build_maps(b);
-        } catch (...) {
-            delete b;
-            throw;
-        }
-        *out = b;
+        *out = make_batch(count, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, obj_offset,
+                          params, hip_stream);
     });
 }
 

@@ -188,6 +188,10 @@ __global__ __launch_bounds__(kThreads) void kb_decide(Ctrl *ctrl, BatchMaps bm, 
     const double eta_next = e1 < e2 ? e1 : e2;
     c.last_eta_bar = eta_bar;
     if (c.fixed_step || eta <= eta_bar) {
+        if (bm.tape_eta && c.k < bm.tape_K) {
+            bm.tape_eta[(size_t)i * bm.tape_K + c.k] = eta;
+            bm.tape_omega[(size_t)i * bm.tape_K + c.k] = omega;
+        }
         c.cur ^= 1;
         c.k += 1;
         c.t += 1;
@@ -673,6 +677,33 @@ __global__ __launch_bounds__(kThreads) void kb_gap_update(const double *part, Ba
     gs[i] = s;
 }
 
+// Checkpoint copy of a recorded run (see launch_b_checkpoint).
+__global__ __launch_bounds__(kThreads) void kb_checkpoint(DCsr A, DCsr AT, BatchMaps bm,
+                                                          const int32_t *slot, const double *x,
+                                                          const double *y, const double *sx,
+                                                          const double *sy, double *ck,
+                                                          int64_t N, int64_t M) {
+    for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
+        const int cb = bm.clist[ci];
+        if (cb < 0) continue;
+        const int sl = slot[cb_inst(bm, cb)];
+        if (sl < 0) continue;
+        double *base = ck + (size_t)sl * 2 * (size_t)(N + M);
+        if (cb < bm.nT) {
+            for (int j = AT.blk[cb] + threadIdx.x; j < AT.blk[cb + 1]; j += kThreads) {
+                base[j] = x[j];
+                base[N + M + j] = sx[j];
+            }
+        } else {
+            const int b = cb - bm.nT;
+            for (int r = A.blk[b] + threadIdx.x; r < A.blk[b + 1]; r += kThreads) {
+                base[N + r] = y[r];
+                base[2 * N + M + r] = sy[r];
+            }
+        }
+    }
+}
+
 // --------------------------------------------------------------- launchers
 
 static inline int wave_grid(int ni) {
@@ -776,6 +807,16 @@ hipError_t launch_b_gap_steps(hipStream_t s, const DCsr &A, const DCsr &AT, cons
         hipLaunchKernelGGL(kb_gap_update, dim3(wave_grid(bm.ni)), dim3(kThreads), 0, s, part, bm,
                            mask, gs, k == total - 1 ? 1 : 0);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_b_checkpoint(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                               const int32_t *slot, const double *x, const double *y,
+                               const double *sx, const double *sy, double *ck, int64_t N,
+                               int64_t M) {
+    if (bm.nc > 0)
+        hipLaunchKernelGGL(kb_checkpoint, dim3(list_grid(bm.nc, kBatchGridCap)), dim3(kThreads), 0,
+                           s, A, AT, bm, slot, x, y, sx, sy, ck, N, M);
     return hipGetLastError();
 }
 

@@ -112,6 +112,10 @@ struct BatchMaps {
     // (nc check blocks: c < nT is A^T block c, c >= nT is A block c - nT).
     int32_t ni = 0, na = 0, nt = 0, nc = 0;
     const int32_t *ilist = nullptr, *alist = nullptr, *tlist = nullptr, *clist = nullptr;
+    // Decision record of an unrolled run (null otherwise): the step-decision
+    // kernel stores eta and omega of accepted step k of instance i at i * tape_K + k.
+    double *tape_eta = nullptr, *tape_omega = nullptr;
+    int64_t tape_K = 0;
 };
 
 // ------------------------------------------------------------ launchers
@@ -233,6 +237,12 @@ hipError_t launch_b_kkt(hipStream_t s, const DCsr &A, const DCsr &AT, const Batc
                         const double *const *p1, const double *d1, const double *d2, Vecs orig,
                         int mode, double *part, double *out, double *r_out, double *x_out,
                         double *y_out);
+// checkpoint of a recorded run: instances with slot[i] >= 0 copy x | y | Sx | Sy into
+// ck + slot[i] * 2 (N + M)
+hipError_t launch_b_checkpoint(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                               const int32_t *slot, const double *x, const double *y,
+                               const double *sx, const double *sy, double *ck, int64_t N,
+                               int64_t M);
 // normalized duality gap per instance: begin = radius, slopes and the first
 // abscissa; then active-set steps first .. first+count-1 of at most `total`
 hipError_t launch_b_gap_begin(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
@@ -243,5 +253,35 @@ hipError_t launch_b_gap_steps(hipStream_t s, const DCsr &A, const DCsr &AT, cons
                               const int32_t *mask, Vecs v, const double *x, const double *y,
                               const double *ax, const double *aty, double *part, GapState *gs,
                               int first, int count, int total);
+
+// unrolled (differentiable) map: decisions of step s of every instance
+struct UStepArgs {
+    const double *eta, *omega;  // recorded [B * K]
+    int64_t K, s;
+    const int32_t *ablk_inst, *tblk_inst;
+};
+// one replayed step for every instance: x -> xn, y -> yn with products, sums;
+// seg_* (nullable) receive w = 2 xn - x, y, the interior flags and the dual
+// cases; sig (nullable) counts interior and moving coordinates per instance
+hipError_t launch_u_step(hipStream_t s, const DCsr &A, const DCsr &AT, Vecs v, UStepArgs u,
+                         const double *x, const double *y, const double *ax, const double *aty,
+                         double *xn, double *yn, double *axn, double *atyn, double *sx, double *sy,
+                         double *seg_w, double *seg_y, uint8_t *seg_p, uint8_t *seg_q,
+                         unsigned long long *sig);
+hipError_t launch_u_restart_adj(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                                const int32_t *rt, const double *seta, double *xb, double *yb,
+                                double *sxb, double *syb);
+// adjoint of one step for every instance (xb, yb: adjoint of the state, in place)
+hipError_t launch_u_reverse(hipStream_t s, const DCsr &A, const DCsr &AT, UStepArgs u,
+                            const double *seg_w, const double *seg_y, const uint8_t *seg_p,
+                            const uint8_t *seg_q, double *xb, double *yb, const double *sxb,
+                            const double *syb, double *yhb, double *vb, double *gc, double *glc,
+                            double *guc, double *gval);
+hipError_t launch_u_scale_values(hipStream_t s, const DCsr &A, const double *val, const double *d1,
+                                 const double *d2, const int32_t *a2t, double *va, double *vt);
+hipError_t launch_u_finish(hipStream_t s, const DCsr &A, int64_t N, const double *d1,
+                           const double *d2, const double *lc, const double *uc, const double *gc,
+                           const double *glc, const double *guc, const double *gval, double *oc,
+                           double *olc, double *ouc, double *oval);
 
 }  // namespace pdlp

@@ -34,7 +34,7 @@ def test_struct_layout_matches_header(tmp_path):
     structs = {"pdlp_params": pd.Params, "pdlp_result": pd.Result,
                "pdlp_iter_info": pd.IterInfo, "pdlp_state_blob": pd.StateBlob,
                "pdlp_kernel_stats": pd.KernelStats, "pdlp_device_rates": pd.DeviceRates,
-               "pdlp_batch_stats": pd.BatchStats}
+               "pdlp_batch_stats": pd.BatchStats, "pdlp_unroll_stats": pd.UnrollStats}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "pdlp.h"', "int main(void){"]
     for cname, py in structs.items():
         src.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
