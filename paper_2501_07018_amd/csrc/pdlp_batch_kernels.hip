@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kThreads) void kb_primal(DCsr AT, Vecs v, Iter it, 
     }
 }
 
-struct BatchDualEpi {
+struct BatchDualEpi : NoPrefetch {
     const Ctrl *ctrl;
     BatchMaps bm;
     Iter it;
@@ -64,15 +64,18 @@ struct BatchDualEpi {
         if (b < 0) return false;
         const Ctrl &c = ctrl[bm.ablk_inst[b]];
         if (c.stop) return false;
-        const int cur = c.cur;
-        gsrc = it.X[cur ^ 1];
-        row = DualRow{it.Y[cur], it.AX[cur], v.lc, v.uc, it.AX[cur ^ 1], it.Y[cur ^ 1], it.sy,
+        // buffers chosen by select, not by indexing (keeps Iter out of scratch)
+        const bool one = c.cur != 0;
+        gsrc = one ? it.X[0] : it.X[1];
+        row = DualRow{one ? it.Y[1] : it.Y[0], one ? it.AX[1] : it.AX[0], v.lc, v.uc,
+                      one ? it.AX[0] : it.AX[1], one ? it.Y[0] : it.Y[1], it.sy,
                       c.eta * c.omega, c.eta_avg_y, c.pending_sy};
         return true;
     }
     __device__ __forceinline__ const double *src() const { return gsrc; }
-    __device__ __forceinline__ void operator()(int r, double s, double (&acc)[2]) const {
-        row(r, s, acc);
+    // no early operand loads: they would cost this kernel an occupancy step
+    __device__ __forceinline__ void apply(int r, double s, double (&acc)[2], const Pre &) const {
+        row.apply(r, s, acc, row.pre(r));
     }
     __device__ __forceinline__ void end(int b, double (&acc)[2], double *red) {
         block_reduce<2>(acc, red);
@@ -84,7 +87,7 @@ struct BatchDualEpi {
     }
 };
 
-__global__ __launch_bounds__(kThreads) void kb_spmv_dual(DCsr A, Vecs v, Iter it, const Ctrl *ctrl,
+PDLP_STREAM_KERNEL void kb_spmv_dual(DCsr A, Vecs v, Iter it, const Ctrl *ctrl,
                                                          BatchMaps bm, double *part) {
     __shared__ double prod[kStage];
     __shared__ double red[2 * (kThreads / 64)];
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void kb_spmv_dual(DCsr A, Vecs v, Iter it
     stream_spmv<2>(A, epi, acc, prod, red);
 }
 
-struct BatchPrimalEpi {
+struct BatchPrimalEpi : NoPrefetch {
     const Ctrl *ctrl;
     BatchMaps bm;
     Iter it;
@@ -112,15 +115,15 @@ struct BatchPrimalEpi {
         if (b < 0) return false;
         const Ctrl &c = ctrl[bm.tblk_inst[b]];
         if (!c.run_at) return false;
-        const int cur = c.cur;
-        gsrc = it.Y[cur];
-        row = PrimalRow{it.X[cur], v.c, v.lv, v.uv, it.ATY[cur], it.X[cur ^ 1], it.sx,
-                        c.eta_used, c.eta / c.omega, !c.stop};
+        const bool one = c.cur != 0;
+        gsrc = one ? it.Y[1] : it.Y[0];
+        row = PrimalRow{one ? it.X[1] : it.X[0], v.c, v.lv, v.uv, one ? it.ATY[1] : it.ATY[0],
+                        one ? it.X[0] : it.X[1], it.sx, c.eta_used, c.eta / c.omega, !c.stop};
         return true;
     }
     __device__ __forceinline__ const double *src() const { return gsrc; }
-    __device__ __forceinline__ void operator()(int j, double s, double (&acc)[1]) const {
-        row(j, s, acc);
+    __device__ __forceinline__ void apply(int j, double s, double (&acc)[1], const Pre &) const {
+        row.apply(j, s, acc, row.pre(j));
     }
     __device__ __forceinline__ void end(int b, double (&acc)[1], double *red) {
         if (row.next) {
@@ -131,7 +134,7 @@ struct BatchPrimalEpi {
     }
 };
 
-__global__ __launch_bounds__(kThreads) void kb_spmv_primal(DCsr AT, Vecs v, Iter it,
+PDLP_STREAM_KERNEL void kb_spmv_primal(DCsr AT, Vecs v, Iter it,
                                                            const Ctrl *ctrl, BatchMaps bm,
                                                            double *part) {
     __shared__ double prod[kStage];
@@ -273,7 +276,7 @@ __global__ __launch_bounds__(kThreads) void kb_elementwise(DCsr A, DCsr AT, Batc
     }
 }
 
-struct BatchPlainEpi {
+struct BatchPlainEpi : NoPrefetch {
     const int32_t *inst, *mask, *list;
     int nlist;
     const double *gsrc;
@@ -283,18 +286,20 @@ struct BatchPlainEpi {
     __device__ __forceinline__ bool begin(int b) const { return b >= 0 && mask[inst[b]] != 0; }
     __device__ __forceinline__ const double *src() const { return gsrc; }
     template <int N>
-    __device__ __forceinline__ void operator()(int r, double s, double (&)[N]) const { out[r] = s; }
+    __device__ __forceinline__ void apply(int r, double s, double (&)[N], const Pre &) const {
+        out[r] = s;
+    }
     template <int N>
     __device__ __forceinline__ void end(int, double (&)[N], double *) {}
 };
 
-__global__ __launch_bounds__(kThreads) void kb_spmv_plain(DCsr M, const int32_t *blk_inst,
+PDLP_STREAM_KERNEL void kb_spmv_plain(DCsr M, const int32_t *blk_inst,
                                                           const int32_t *list, int nlist,
                                                           const int32_t *mask, const double *x,
                                                           double *out) {
     __shared__ double prod[kStage];
     __shared__ double red[kThreads / 64];
-    BatchPlainEpi epi{blk_inst, mask, list, nlist, x, out};
+    BatchPlainEpi epi{{}, blk_inst, mask, list, nlist, x, out};
     double acc[1] = {0.0};
     stream_spmv<1>(M, epi, acc, prod, red);
 }
@@ -712,7 +717,7 @@ static inline int wave_grid(int ni) {
 }
 static inline int list_grid(int n, int cap) { return n < cap ? (n > 0 ? n : 1) : cap; }
 constexpr int kBatchGridCap = 4096;   // elementwise / check kernels
-constexpr int kBatchSpmvCap = 2048;   // persistent CSR stream kernels
+constexpr int kBatchSpmvCap = 2048;   // persistent CSR stream kernels (8 per CU)
 
 hipError_t launch_b_attempt(hipStream_t s, const DCsr &A, const DCsr &AT, Vecs v, Iter it,
                             Ctrl *ctrl, const BatchMaps &bm, double *pd, double *pps,

@@ -107,8 +107,10 @@ __device__ __forceinline__ T stream_load(const T *p) {
 // Hooks of the epilogue: count(A) blocks are visited, the bi-th being
 // block(bi) (all blocks in order for one LP, a list of the blocks of running
 // instances in a batch); begin(b) says whether block b runs (and may load
-// per-block parameters), src() is the gathered vector, end(b, acc, red) is
-// called after the block (per-block partial sums in the batched solver).
+// per-block parameters), src() is the gathered vector, prefetch(r) loads the
+// row work's operands (type Pre) and apply(r, s, acc, pre) does the row work
+// with the row's product s; end(b, acc, red) is called after the block
+// (per-block partial sums in the batched solver).
 template <int NACC, class Epi>
 __device__ __forceinline__ void stream_spmv(const DCsr &A, Epi &epi, double (&acc)[NACC],
                                             double *prod, double *red) {
@@ -132,9 +134,19 @@ __device__ __forceinline__ void stream_spmv(const DCsr &A, Epi &epi, double (&ac
                 for (int e = a + lane; e < z; e += 64)
                     s += stream_load(A.val + e) * x[stream_load(A.col + e)];
                 s = wave_sum(s);
-                if (lane == 0) epi(r, s, acc);
+                if (lane == 0) epi.apply(r, s, acc, epi.prefetch(r));
             }
         } else if (len <= kStage && len0 <= kMedRow) {
+            // the first row of each lane: its slice bounds and epilogue operands
+            // are loaded before the matrix stream so they arrive with it
+            const int rr = r0 + threadIdx.x;
+            int ra = 0, rz = 0;
+            typename Epi::Pre pre{};
+            if (rr < r1) {
+                ra = A.row_ptr[rr] - e0;
+                rz = A.row_ptr[rr + 1] - e0;
+                pre = epi.prefetch(rr);
+            }
             int ci[kPer];
             double vv[kPer];
 #pragma unroll
@@ -154,11 +166,16 @@ __device__ __forceinline__ void stream_spmv(const DCsr &A, Epi &epi, double (&ac
                 if (q < len) prod[q] = vv[i] * x[ci[i]];
             }
             __syncthreads();
-            for (int r = r0 + threadIdx.x; r < r1; r += kThreads) {
+            if (rr < r1) {
+                double s = 0.0;
+                for (int q = ra; q < rz; ++q) s += prod[q];
+                epi.apply(rr, s, acc, pre);
+            }
+            for (int r = rr + kThreads; r < r1; r += kThreads) {
                 const int a = A.row_ptr[r] - e0, z = A.row_ptr[r + 1] - e0;
                 double s = 0.0;
                 for (int q = a; q < z; ++q) s += prod[q];
-                epi(r, s, acc);
+                epi.apply(r, s, acc, epi.prefetch(r));
             }
             __syncthreads();
         } else {
@@ -167,7 +184,7 @@ __device__ __forceinline__ void stream_spmv(const DCsr &A, Epi &epi, double (&ac
                 s += stream_load(A.val + e) * x[stream_load(A.col + e)];
             double t[1] = {s};
             block_reduce<1>(t, red);
-            if (threadIdx.x == 0) epi(r0, t[0], acc);
+            if (threadIdx.x == 0) epi.apply(r0, t[0], acc, epi.prefetch(r0));
         }
         epi.end(b, acc, red);
     }
@@ -181,13 +198,25 @@ struct DualRow {
     double *ax_new, *y_new, *sy;
     double sigma, eta_avg;
     int pend;
-    __device__ __forceinline__ void operator()(int r, double s, double (&acc)[2]) const {
+    struct Pre {
+        double y, ax, lc, uc, sy;
+    };
+    __device__ __forceinline__ Pre pre(int r) const {
+        Pre p;
+        p.y = y[r];
+        p.ax = ax[r];
+        p.lc = lc[r];
+        p.uc = uc[r];
+        p.sy = pend ? sy[r] : 0.0;
+        return p;
+    }
+    __device__ __forceinline__ void apply(int r, double s, double (&acc)[2], const Pre &p) const {
         ax_new[r] = s;
-        const double yr = y[r];
-        if (pend) sy[r] += eta_avg * yr;
-        const double axr = ax[r];
+        const double yr = p.y;
+        if (pend) sy[r] = p.sy + eta_avg * yr;
+        const double axr = p.ax;
         const double yhat = yr - sigma * (2.0 * s - axr);
-        const double yn = dual_case(yhat, sigma, lc[r], uc[r]);
+        const double yn = dual_case(yhat, sigma, p.lc, p.uc);
         y_new[r] = yn;
         const double dy = yn - yr;
         acc[0] += dy * dy;
@@ -202,13 +231,29 @@ struct PrimalRow {
     double *aty, *x_new, *sx;
     double eta_used, tau;
     int next;
-    __device__ __forceinline__ void operator()(int j, double s, double (&acc)[1]) const {
-        aty[j] = s;
-        const double xj = x[j];
-        sx[j] += eta_used * xj;
+    struct Pre {
+        double x, c, lv, uv, sx;
+    };
+    __device__ __forceinline__ Pre pre(int j) const {
+        Pre p;
+        p.x = x[j];
+        p.sx = sx[j];
         if (next) {
-            const double g = c[j] - s;
-            const double xn = clampd(xj - tau * g, lv[j], uv[j]);
+            p.c = c[j];
+            p.lv = lv[j];
+            p.uv = uv[j];
+        } else {
+            p.c = p.lv = p.uv = 0.0;
+        }
+        return p;
+    }
+    __device__ __forceinline__ void apply(int j, double s, double (&acc)[1], const Pre &p) const {
+        aty[j] = s;
+        const double xj = p.x;
+        sx[j] = p.sx + eta_used * xj;
+        if (next) {
+            const double g = p.c - s;
+            const double xn = clampd(xj - tau * g, p.lv, p.uv);
             x_new[j] = xn;
             const double d = xn - xj;
             acc[0] += d * d;
@@ -220,7 +265,13 @@ struct PrimalRow {
 
 // Epilogue base for a single LP: every block runs, one gathered vector,
 // partial sums accumulate per thread across blocks.
-struct SingleEpi {
+// Epilogues without operands to prefetch.
+struct NoPrefetch {
+    struct Pre {};
+    __device__ __forceinline__ Pre prefetch(int) const { return {}; }
+};
+
+struct SingleEpi : NoPrefetch {
     const double *gsrc;
     __device__ __forceinline__ int count(const DCsr &A) const { return A.nblk; }
     __device__ __forceinline__ int block(int bi) const { return bi; }

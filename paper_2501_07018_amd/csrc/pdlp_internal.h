@@ -18,6 +18,13 @@ constexpr int kMaxBlockRows = 1024;  // rows per stream block
 constexpr int kMedRow = 64;          // rows longer than this leave the stream path ...
 constexpr int kWaveMax = 1024;       // ... for one wave per row up to this length, then a workgroup
 constexpr int kWaveRows = kThreads / 64;
+// Persistent CSR stream kernels keep 8 waves per SIMD (8 workgroups per CU,
+// the persistent grid of 2048 on 256 CUs): at most 64 VGPRs.
+#ifndef PDLP_STREAM_WAVES
+#define PDLP_STREAM_WAVES 8
+#endif
+#define PDLP_STREAM_KERNEL \
+    __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(PDLP_STREAM_WAVES)))
 // [hot-path constants end]
 constexpr int kGapPts = 32;          // abscissae per multisection pass of the gap search
 constexpr int kGapMaxPass = 24;

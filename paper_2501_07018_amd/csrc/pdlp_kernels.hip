@@ -24,10 +24,12 @@ namespace pdlp {
 struct PlainEpi : SingleEpi {
     double *out;
     template <int N>
-    __device__ __forceinline__ void operator()(int r, double s, double (&)[N]) const { out[r] = s; }
+    __device__ __forceinline__ void apply(int r, double s, double (&)[N], const Pre &) const {
+        out[r] = s;
+    }
 };
 
-__global__ __launch_bounds__(kThreads) void k_spmv_plain(DCsr A, const double *__restrict__ x,
+PDLP_STREAM_KERNEL void k_spmv_plain(DCsr A, const double *__restrict__ x,
                                                          double *__restrict__ out) {
     __shared__ double prod[kStage];
     __shared__ double red[kThreads / 64];
@@ -40,12 +42,14 @@ __global__ __launch_bounds__(kThreads) void k_spmv_plain(DCsr A, const double *_
 
 struct DualEpi : SingleEpi {
     DualRow row;
-    __device__ __forceinline__ void operator()(int r, double s, double (&acc)[2]) const {
-        row(r, s, acc);
+    using Pre = DualRow::Pre;
+    __device__ __forceinline__ Pre prefetch(int r) const { return row.pre(r); }
+    __device__ __forceinline__ void apply(int r, double s, double (&acc)[2], const Pre &p) const {
+        row.apply(r, s, acc, p);
     }
 };
 
-__global__ __launch_bounds__(kThreads) void k_spmv_dual(DCsr A, Vecs v, Iter it, const Ctrl *ctrl,
+PDLP_STREAM_KERNEL void k_spmv_dual(DCsr A, Vecs v, Iter it, const Ctrl *ctrl,
                                                         double *part) {
     if (ctrl->stop) return;
     __shared__ double prod[kStage];
@@ -62,12 +66,14 @@ __global__ __launch_bounds__(kThreads) void k_spmv_dual(DCsr A, Vecs v, Iter it,
 
 struct PrimalEpi : SingleEpi {
     PrimalRow row;
-    __device__ __forceinline__ void operator()(int j, double s, double (&acc)[1]) const {
-        row(j, s, acc);
+    using Pre = PrimalRow::Pre;
+    __device__ __forceinline__ Pre prefetch(int j) const { return row.pre(j); }
+    __device__ __forceinline__ void apply(int j, double s, double (&acc)[1], const Pre &p) const {
+        row.apply(j, s, acc, p);
     }
 };
 
-__global__ __launch_bounds__(kThreads) void k_spmv_primal(DCsr AT, Vecs v, Iter it,
+PDLP_STREAM_KERNEL void k_spmv_primal(DCsr AT, Vecs v, Iter it,
                                                           const Ctrl *ctrl, double *part) {
     if (!ctrl->run_at) return;
     __shared__ double prod[kStage];

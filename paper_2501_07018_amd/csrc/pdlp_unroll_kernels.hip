@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kThreads) void ku_primal(DCsr AT, Vecs v, UStep us,
     }
 }
 
-struct UDualEpi {
+struct UDualEpi : NoPrefetch {
     UStep us;
     Vecs v;
     const double *gsrc, *y, *ax;
@@ -82,7 +82,7 @@ struct UDualEpi {
         return true;
     }
     __device__ __forceinline__ const double *src() const { return gsrc; }
-    __device__ __forceinline__ void operator()(int r, double s, double (&acc)[1]) const {
+    __device__ __forceinline__ void apply(int r, double s, double (&acc)[1], const Pre &) const {
         axn[r] = s;
         const double yr = y[r];
         const double yhat = yr - sigma * (2.0 * s - ax[r]);
@@ -100,14 +100,14 @@ struct UDualEpi {
     }
 };
 
-__global__ __launch_bounds__(kThreads) void ku_dual(DCsr A, UDualEpi epi) {
+PDLP_STREAM_KERNEL void ku_dual(DCsr A, UDualEpi epi) {
     __shared__ double prod[kStage];
     __shared__ double red[kThreads / 64];
     double acc[1] = {0.0};
     stream_spmv<1>(A, epi, acc, prod, red);
 }
 
-struct UPrimalEpi {
+struct UPrimalEpi : NoPrefetch {
     UStep us;
     const double *gsrc, *x, *xn;
     double *atyn, *sx, *seg_w;
@@ -119,7 +119,7 @@ struct UPrimalEpi {
         return true;
     }
     __device__ __forceinline__ const double *src() const { return gsrc; }
-    __device__ __forceinline__ void operator()(int j, double s, double (&)[1]) const {
+    __device__ __forceinline__ void apply(int j, double s, double (&)[1], const Pre &) const {
         atyn[j] = s;
         const double xj = xn[j];
         sx[j] += eta * xj;
@@ -128,7 +128,7 @@ struct UPrimalEpi {
     __device__ __forceinline__ void end(int, double (&)[1], double *) {}
 };
 
-__global__ __launch_bounds__(kThreads) void ku_aty(DCsr AT, UPrimalEpi epi) {
+PDLP_STREAM_KERNEL void ku_aty(DCsr AT, UPrimalEpi epi) {
     __shared__ double prod[kStage];
     __shared__ double red[kThreads / 64];
     double acc[1] = {0.0};
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kThreads) void ku_rrow(DCsr A, UStep us, const doub
 }
 
 // Columns: wb = -sigma A~^T yhb, through w = 2 x+ - x, the projection and v.
-struct URColEpi {
+struct URColEpi : NoPrefetch {
     UStep us;
     const double *gsrc, *sxb;
     const uint8_t *pm;
@@ -200,7 +200,7 @@ struct URColEpi {
         return true;
     }
     __device__ __forceinline__ const double *src() const { return gsrc; }
-    __device__ __forceinline__ void operator()(int j, double s, double (&)[1]) const {
+    __device__ __forceinline__ void apply(int j, double s, double (&)[1], const Pre &) const {
         const double wb = -sigma * s;
         const double xplus_b = (xb[j] + eta * sxb[j]) + 2.0 * wb;
         const double v = pm[j] ? xplus_b : 0.0;
@@ -211,7 +211,7 @@ struct URColEpi {
     __device__ __forceinline__ void end(int, double (&)[1], double *) {}
 };
 
-__global__ __launch_bounds__(kThreads) void ku_rcol(DCsr AT, URColEpi epi) {
+PDLP_STREAM_KERNEL void ku_rcol(DCsr AT, URColEpi epi) {
     __shared__ double prod[kStage];
     __shared__ double red[kThreads / 64];
     double acc[1] = {0.0};
@@ -362,10 +362,10 @@ hipError_t launch_u_step(hipStream_t s, const DCsr &A, const DCsr &AT, Vecs v, U
     hipLaunchKernelGGL(ku_primal, dim3(blk_grid(AT.nblk, 4096)), dim3(kThreads), 0, s, AT, v, us,
                        x, aty, xn, seg_p, sig);
     if (A.nblk > 0) {
-        UDualEpi de{us, v, xn, y, ax, axn, yn, sy, seg_y, seg_q, sig, 0, 0.0, 0.0};
+        UDualEpi de{{}, us, v, xn, y, ax, axn, yn, sy, seg_y, seg_q, sig, 0, 0.0, 0.0};
         hipLaunchKernelGGL(ku_dual, dim3(blk_grid(A.nblk, 2048)), dim3(kThreads), 0, s, A, de);
     }
-    UPrimalEpi pe{us, yn, x, xn, atyn, sx, seg_w, 0.0};
+    UPrimalEpi pe{{}, us, yn, x, xn, atyn, sx, seg_w, 0.0};
     hipLaunchKernelGGL(ku_aty, dim3(blk_grid(AT.nblk, 2048)), dim3(kThreads), 0, s, AT, pe);
     return hipGetLastError();
 }
@@ -388,7 +388,7 @@ hipError_t launch_u_reverse(hipStream_t s, const DCsr &A, const DCsr &AT, UStepA
     if (A.nblk > 0)
         hipLaunchKernelGGL(ku_rrow, dim3(blk_grid(A.nblk, 4096)), dim3(kThreads), 0, s, A, us, yb,
                            syb, seg_q, yhb, glc, guc);
-    URColEpi ce{us, yhb, sxb, seg_p, xb, gc, vb, 0.0, 0.0, 0.0};
+    URColEpi ce{{}, us, yhb, sxb, seg_p, xb, gc, vb, 0.0, 0.0, 0.0};
     hipLaunchKernelGGL(ku_rcol, dim3(blk_grid(AT.nblk, 2048)), dim3(kThreads), 0, s, AT, ce);
     if (A.nblk > 0)
         hipLaunchKernelGGL(ku_rA, dim3(blk_grid(A.nblk, 2048)), dim3(kThreads), 0, s, A, us, vb,
