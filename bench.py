@@ -40,9 +40,9 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel source they were taken on (hash of the hot-path
 # region of the kernels and constants); reported as null otherwise.
 TRAFFIC_RECORD = {
-    "hot_source": "4d154ae9979947ad",
-    "k_spmv_dual": 12496203049,
-    "k_spmv_primal": 18287447559,
+    "hot_source": "0ae3c435557efd6e",
+    "k_spmv_dual": 12554419091,
+    "k_spmv_primal": 18342510980,
 }
 
 
