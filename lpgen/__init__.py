@@ -37,7 +37,7 @@ import scipy.sparse as sp
 INF = np.inf
 
 # config ids used to derive seeds
-CFG_SMALL, CFG_GRID, CFG_SKEWED, CFG_BATCH, CFG_LAYER = 0, 1, 2, 3, 4
+CFG_SMALL, CFG_GRID, CFG_SKEWED, CFG_BATCH, CFG_LAYER, CFG_INFEAS = 0, 1, 2, 3, 4, 5
 
 
 def seed_of(config: int, instance: int = 0) -> int:
@@ -64,6 +64,13 @@ class LP:
     r_star: np.ndarray | None = None
     p_star: float | None = None
     name: str = ""
+    # planted infeasibility rays (None when not planted)
+    ray_y: np.ndarray | None = None   # Farkas ray of a primal-infeasible instance
+    ray_r: np.ndarray | None = None
+    ray_x: np.ndarray | None = None   # recession ray of a dual-infeasible instance
+    x_feas: np.ndarray | None = None  # a primal feasible point
+    y_feas: np.ndarray | None = None  # a dual feasible pair (c - A^T y = r, y in Y, r in R)
+    r_feas: np.ndarray | None = None
 
     @property
     def nnz(self) -> int:
@@ -380,3 +387,148 @@ def tiny_random_lp(seed: int, m: int, n: int, density: float = 0.6,
     c = np.round(rng.standard_normal(n) * 4) / 4
     return LP(m, n, A.indptr.astype(np.int32), A.indices.astype(np.int32),
               A.data.astype(np.float64), c, lc, uc, lv, uv, 0.0, name=f"tiny_{seed}")
+
+
+# ------------------------------------------------------- infeasible instances
+#
+# Both generators start from a random point x0 and bounds placed around it,
+# so that the constraints without the planted conflict are satisfiable, and
+# mix every bound kind: variables boxed, lower-bounded, upper-bounded or free;
+# rows equalities, >=, <=, two-sided ranges or free.
+
+
+def _ray_matrix(rng, m, n, per_col):
+    colptr, rows = _distinct_rows_fixed_degree(rng, m, n, per_col)
+    vals = rng.standard_normal(rows.size)
+    row_ptr, col, val = _csr_from_csc(m, n, colptr, rows, vals)
+    return row_ptr, col, val, sp.csr_matrix((val, col, row_ptr), shape=(m, n))
+
+
+def _var_bounds(rng, x0, kind):
+    """kind: 0 boxed, 1 lower only, 2 upper only, 3 free."""
+    n = x0.size
+    a = rng.uniform(0.2, 1.0, n)
+    b = rng.uniform(0.2, 1.0, n)
+    lv = np.where((kind == 0) | (kind == 1), x0 - a, -INF)
+    uv = np.where((kind == 0) | (kind == 2), x0 + b, INF)
+    return lv, uv
+
+
+def _row_bounds(rng, ax0, kind):
+    """kind: 0 equality, 1 >=, 2 <=, 3 range, 4 free."""
+    m = ax0.size
+    s1 = rng.uniform(0.1, 1.0, m)
+    s2 = rng.uniform(0.1, 1.0, m)
+    lc = np.full(m, -INF)
+    uc = np.full(m, INF)
+    lc = np.where(kind == 0, ax0, lc)
+    uc = np.where(kind == 0, ax0, uc)
+    lc = np.where((kind == 1) | (kind == 3), ax0 - s1, lc)
+    uc = np.where((kind == 2) | (kind == 3), ax0 + s2, uc)
+    return lc, uc
+
+
+def planted_primal_infeasible(m: int, n: int, per_col: int, seed: int, support: float = 0.1,
+                              margin: float = 1.0, name: str = "") -> LP:
+    """Primal-infeasible LP with a planted Farkas ray (y*, r*).
+
+    y* lives on about ``support * m`` rows with the sign each row kind allows
+    (free rows excluded); r* = -A^T y*, and every column it touches gets a
+    bound kind that admits that sign (boxed, or one-sided on the matching
+    side).  The bounds of one ray row are then moved until
+    lc^T y*+ - uc^T y*- + lv^T r*+ - uv^T r*- equals ``margin`` > 0, which
+    makes the constraint system inconsistent (Farkas' lemma) while every
+    other row keeps its slack around x0.  The objective is c = A^T y_f + r_f
+    for a random (y_f in Y, r_f in R), so the dual is feasible (and, the
+    primal being infeasible, unbounded); (y_f, r_f) is kept.
+    """
+    rng = np.random.default_rng(seed)
+    row_ptr, col, val, A = _ray_matrix(rng, m, n, per_col)
+    x0 = rng.uniform(-1.0, 1.0, n)
+    rkind = rng.choice(5, size=m, p=[0.3, 0.25, 0.25, 0.15, 0.05])
+    cand = np.flatnonzero(rkind != 4)
+    k = max(1, int(round(support * m)))
+    S = rng.choice(cand, size=min(k, cand.size), replace=False)
+    y = np.zeros(m)
+    mag = np.abs(rng.standard_normal(S.size)) + 0.1
+    sgn = np.where(rng.random(S.size) < 0.5, 1.0, -1.0)
+    sgn = np.where(rkind[S] == 1, 1.0, np.where(rkind[S] == 2, -1.0, sgn))
+    y[S] = sgn * mag
+    g = A.T @ y
+    r = -g
+    vkind = rng.choice(4, size=n, p=[0.6, 0.15, 0.15, 0.1])
+    touched = g != 0.0
+    side = np.where(r > 0.0, 1, 2)            # lower-only admits r > 0, upper-only r < 0
+    pick = rng.random(n) < 0.5
+    vkind = np.where(touched, np.where(pick, 0, side), vkind)
+    lv, uv = _var_bounds(rng, x0, vkind)
+    lc, uc = _row_bounds(rng, A @ x0, rkind)
+    r = np.where(touched, r, 0.0)
+    yp, yn, rp, rn = y > 0, y < 0, r > 0, r < 0
+    obj = (math.fsum(lc[yp] * y[yp]) + math.fsum(uc[yn] * y[yn])
+           + math.fsum(lv[rp] * r[rp]) + math.fsum(uv[rn] * r[rn]))
+    i0 = S[int(np.argmax(np.abs(y[S])))]
+    delta = (margin - obj) / abs(y[i0])        # > 0: obj <= 0 while x0 is feasible
+    if y[i0] > 0:
+        lc[i0] += delta
+        if rkind[i0] == 0 or uc[i0] < lc[i0]:
+            uc[i0] = lc[i0]
+    else:
+        uc[i0] -= delta
+        if rkind[i0] == 0 or lc[i0] > uc[i0]:
+            lc[i0] = uc[i0]
+    yf = rng.standard_normal(m)
+    yf = np.where(np.isfinite(lc), yf, np.minimum(yf, 0.0))
+    yf = np.where(np.isfinite(uc), yf, np.maximum(yf, 0.0))
+    rf = rng.standard_normal(n)
+    rf = np.where(np.isfinite(lv), rf, np.minimum(rf, 0.0))
+    rf = np.where(np.isfinite(uv), rf, np.maximum(rf, 0.0))
+    c = A.T @ yf + rf
+    lp = LP(m, n, row_ptr, col, val, c, lc, uc, lv, uv, 0.0,
+            name=name or f"primal_infeasible_{m}x{n}_k{per_col}")
+    lp.ray_y, lp.ray_r = y, r
+    lp.y_feas, lp.r_feas = yf, rf
+    return lp
+
+
+def planted_dual_infeasible(m: int, n: int, per_col: int, seed: int, support: float = 0.1,
+                            margin: float = 1.0, name: str = "") -> LP:
+    """Feasible but unbounded LP (dual infeasible) with a planted ray x*.
+
+    x* lives on about ``support * n`` columns, each one-sided on the side x*
+    moves away from (or free); every row it touches becomes >= or <= in the
+    direction A x* moves (or free), so x0 + t x* stays feasible for all
+    t >= 0, and c is corrected so that c^T x* = -``margin``.  x0 is kept as
+    a feasible point.
+    """
+    rng = np.random.default_rng(seed)
+    row_ptr, col, val, A = _ray_matrix(rng, m, n, per_col)
+    x0 = rng.uniform(-1.0, 1.0, n)
+    k = max(1, int(round(support * n)))
+    J = rng.choice(n, size=k, replace=False)
+    x = np.zeros(n)
+    x[J] = np.where(rng.random(k) < 0.5, 1.0, -1.0) * rng.uniform(0.5, 1.5, k)
+    vkind = rng.choice(4, size=n, p=[0.6, 0.15, 0.15, 0.1])
+    free = rng.random(n) < 0.2
+    vkind = np.where(x > 0, np.where(free, 3, 1), np.where(x < 0, np.where(free, 3, 2), vkind))
+    ax = A @ x
+    rkind = rng.choice(5, size=m, p=[0.3, 0.25, 0.25, 0.15, 0.05])
+    freer = rng.random(m) < 0.1
+    rkind = np.where(ax > 0, np.where(freer, 4, 1), np.where(ax < 0, np.where(freer, 4, 2), rkind))
+    lv, uv = _var_bounds(rng, x0, vkind)
+    lc, uc = _row_bounds(rng, A @ x0, rkind)
+    c = rng.standard_normal(n)
+    c -= ((c @ x + margin) / (x @ x)) * x
+    lp = LP(m, n, row_ptr, col, val, c, lc, uc, lv, uv, 0.0,
+            name=name or f"dual_infeasible_{m}x{n}_k{per_col}")
+    lp.ray_x = x
+    lp.x_feas = x0
+    return lp
+
+
+def infeasible_lp(kind: str, i: int, m: int, n: int, per_col: int = 4) -> LP:
+    """Seeded member ``i`` of the primal- ('primal') or dual- ('dual') infeasible family."""
+    seed = seed_of(CFG_INFEAS, 2 * i + (kind == "dual"))
+    if kind == "primal":
+        return planted_primal_infeasible(m, n, per_col, seed)
+    return planted_dual_infeasible(m, n, per_col, seed)

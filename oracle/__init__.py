@@ -52,7 +52,8 @@ class _Params(C.Structure):
                 ("red_exp", C.c_double), ("grow_exp", C.c_double),
                 ("reduced_cost_mode", C.c_int32), ("polish", C.c_int32),
                 ("polish_first", C.c_int64), ("fixed_step", C.c_int32),
-                ("fixed_eta", C.c_double), ("adaptive_restarts", C.c_int32)]
+                ("fixed_eta", C.c_double), ("adaptive_restarts", C.c_int32),
+                ("detect_infeas", C.c_int32), ("eps_infeas", C.c_double)]
 
 
 class _State(C.Structure):
@@ -83,11 +84,16 @@ class _Result(C.Structure):
                 ("dual_res_abs", C.c_double), ("dual_res_rel", C.c_double),
                 ("omega", C.c_double), ("eta", C.c_double),
                 ("polish_attempts", C.c_int64), ("polish_iters", C.c_int64),
-                ("polished", C.c_int32)]
+                ("polished", C.c_int32), ("cert_source", C.c_int32),
+                ("cert_obj", C.c_double), ("cert_res", C.c_double)]
 
 
 class _Tape(C.Structure):
     _fields_ = [("cap", C.c_int64), ("eta", D), ("omega", D), ("restart", I32)]
+
+
+class _Cert(C.Structure):
+    _fields_ = [("obj", C.c_double), ("res", C.c_double), ("ok", C.c_int32)]
 
 
 class _KKT(C.Structure):
@@ -126,6 +132,12 @@ def lib():
         L.orc_primal_weight_update.restype = C.c_double
         L.orc_kkt_eval.argtypes = [C.POINTER(_Unscale), D, D, C.c_int32, D, D, D, D, D,
                                    C.POINTER(_KKT)]
+        L.orc_primal_infeas_test.argtypes = [C.POINTER(_Unscale), D, C.c_double, D, D, D,
+                                             C.POINTER(_Cert)]
+        L.orc_primal_infeas_test.restype = None
+        L.orc_dual_infeas_test.argtypes = [C.POINTER(_Unscale), D, C.c_double, D, D,
+                                           C.POINTER(_Cert)]
+        L.orc_dual_infeas_test.restype = None
         L.orc_pdlp.argtypes = [C.POINTER(_LP), C.POINTER(_Unscale), C.POINTER(_Params),
                                C.POINTER(_State), C.POINTER(_Scratch), D, D, C.POINTER(_Result)]
         L.orc_pdlp.restype = C.c_int32
@@ -237,6 +249,8 @@ class Params:
     adaptive_restarts: bool = True
     ruiz_iters: int = 10
     pc: bool = True
+    detect_infeasibility: bool = True
+    eps_infeas: float = 1e-9
 
     def cstruct(self) -> _Params:
         rc = self.reduced_cost_mode
@@ -246,10 +260,44 @@ class Params:
                        int(bool(self.terminate)), self.beta_suff, self.beta_nec, self.beta_art,
                        self.theta, self.eps_zero, self.red_exp, self.grow_exp, int(rc),
                        int(bool(self.polish)), int(self.polish_first), int(bool(self.fixed_step)),
-                       float(self.fixed_eta), int(bool(self.adaptive_restarts)))
+                       float(self.fixed_eta), int(bool(self.adaptive_restarts)),
+                       int(bool(self.detect_infeasibility)), float(self.eps_infeas))
 
 
-STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 3: "NUMERICAL_ERROR"}
+STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 3: "NUMERICAL_ERROR", 4: "PRIMAL_INFEASIBLE",
+          5: "DUAL_INFEASIBLE"}
+
+
+def _unit_unscale(view: "LPView"):
+    ones = (np.ones(max(view.m, 1)), np.ones(max(view.n, 1)))
+    return _Unscale(view.s, _d(ones[0]), _d(ones[1]), 0.0), ones
+
+
+def primal_infeas_test(lp, y, eps: float = 1e-9) -> dict:
+    """Appendix D primal-infeasibility test of y (original units, no scaling).
+
+    Returns obj, res, ok and the projected y, A^T y and r.
+    """
+    view = LPView.of(lp)
+    u, keep = _unit_unscale(view)
+    yo, atyo, ro = np.empty(lp.m), np.empty(lp.n), np.empty(lp.n)
+    ct = _Cert()
+    lib().orc_primal_infeas_test(C.byref(u), _d(_f64(y)), float(eps), _d(yo), _d(atyo), _d(ro),
+                                 C.byref(ct))
+    return dict(obj=ct.obj, res=ct.res, ok=bool(ct.ok), y=yo, aty=atyo, r=ro)
+
+
+def dual_infeas_test(lp, x, eps: float = 1e-9) -> dict:
+    """Appendix D dual-infeasibility test of x (original units, no scaling).
+
+    Returns obj, res, ok and the projected x and A x.
+    """
+    view = LPView.of(lp)
+    u, keep = _unit_unscale(view)
+    xo, axo = np.empty(lp.n), np.empty(lp.m)
+    ct = _Cert()
+    lib().orc_dual_infeas_test(C.byref(u), _d(_f64(x)), float(eps), _d(xo), _d(axo), C.byref(ct))
+    return dict(obj=ct.obj, res=ct.res, ok=bool(ct.ok), x=xo, ax=axo)
 
 
 class Solver:

@@ -24,6 +24,8 @@
  *                                                "rescaled-termination-criteria"
  *   - relative gap ............................. Section 4, eq. "relative-gap"
  *   - reduced-cost choice ...................... Section 2 and Appendix A
+ *   - infeasibility detection .................. Section 3, "Infeasibility
+ *                                                detection", and Appendix D
  *
  * Readings of points the paper leaves open are listed in the design notes and
  * repeated at the place they apply ("reading: ...").
@@ -40,6 +42,8 @@
 #define ORC_OK 0
 #define ORC_LIMIT 1
 #define ORC_NUMERR 3
+#define ORC_PINF 4
+#define ORC_DINF 5
 #define ORC_POLISHED 10
 
 static int is_fin(double v) { return isfinite(v); }
@@ -579,6 +583,109 @@ void orc_kkt_eval(const orc_unscale *u, const double *xs, const double *ys, int3
     out->dual_res_rel = dres_rel;
 }
 
+/* ------------------------------------------ infeasibility certificates */
+
+/*
+ * Appendix D, primal infeasibility.  A point (y, r) in Y x R certifies it
+ * when lc^T y+ - uc^T y- + lv^T r+ - uv^T r- > 0 and ||A^T y + r||_inf is at
+ * most eps times that objective.
+ *
+ * Readings: the candidate arrives in the scaled space and is taken to
+ * original units (y = D1 y~) on the instance as given; it is projected onto
+ * Y (eq. "lp": {0}, R-, R+ or R by the finiteness of lc_i, uc_i), which
+ * changes only components of the wrong sign; r is the projection of
+ * -A^T y onto R, the reduced-cost rule of the dual objective with c = 0.
+ * The paper states the test on instances rescaled so that objective entries
+ * are -1, 0 or 1 (Section 6); on the instance as given that weights residual
+ * component j by 1/|c_j| (1 where c_j = 0), the weights of the dual residual
+ * in eq. "rescaled-termination-criteria", and leaves the objective unchanged.
+ * Outputs: yo (m), atyo and ro (n), all original units.
+ */
+void orc_primal_infeas_test(const orc_unscale *u, const double *ys, double eps, double *yo,
+                            double *atyo, double *ro, orc_cert *out) {
+    const orc_lp *lp = &u->orig;
+    for (int32_t i = 0; i < lp->m; ++i) {
+        double y = u->d1[i] * ys[i];
+        int lf = is_fin(lp->lc[i]), uf = is_fin(lp->uc[i]);
+        if (!lf && !uf) y = 0.0;
+        else if (!lf && y > 0.0) y = 0.0;      /* Y_i = R- */
+        else if (!uf && y < 0.0) y = 0.0;      /* Y_i = R+ */
+        yo[i] = y;
+    }
+    orc_spmv_t(lp, yo, atyo);
+    double obj = 0.0, res = 0.0;
+    for (int32_t i = 0; i < lp->m; ++i) {
+        if (yo[i] > 0.0) obj += lp->lc[i] * yo[i];
+        else if (yo[i] < 0.0) obj += lp->uc[i] * yo[i];
+    }
+    for (int32_t j = 0; j < lp->n; ++j) {
+        double g = -atyo[j];
+        int lf = is_fin(lp->lv[j]), uf = is_fin(lp->uv[j]);
+        double r;
+        if (!lf && !uf) r = 0.0;
+        else if (!lf) r = g < 0.0 ? g : 0.0;   /* R_j = R- */
+        else if (!uf) r = g > 0.0 ? g : 0.0;   /* R_j = R+ */
+        else r = g;
+        ro[j] = r;
+        if (r > 0.0) obj += lp->lv[j] * r;
+        else if (r < 0.0) obj += lp->uv[j] * r;
+        double w = lp->c[j] != 0.0 ? fabs(lp->c[j]) : 1.0;
+        double e = fabs(atyo[j] + r) / w;
+        if (e > res || e != e) res = e;        /* NaN propagates */
+    }
+    out->obj = obj;
+    out->res = res;
+    out->ok = obj > 0.0 && res <= eps * obj;
+}
+
+/*
+ * Appendix D, dual infeasibility.  A point (x, s) in Xbar x Sbar certifies
+ * it when c^T x < 0 and ||A x + s||_inf is at most eps |c^T x|; Xbar and Sbar
+ * are the recession cones of the variable and constraint bounds.
+ *
+ * Readings: x = D2 x~ projected onto Xbar ({0} for boxed variables, R+ or R-
+ * for one-sided ones, R for free ones); s is the projection of -A x onto
+ * Sbar, so each residual component is the distance of -(A x)_i to Sbar_i.
+ * As for the primal test, residual component i is weighted by 1/q_i with
+ * the q of eq. "rescaled-termination-criteria" (the row scaling that takes
+ * right-hand sides to -1, 0 or 1).  Outputs: xo (n), axo (m), original units.
+ */
+void orc_dual_infeas_test(const orc_unscale *u, const double *xs, double eps, double *xo,
+                          double *axo, orc_cert *out) {
+    const orc_lp *lp = &u->orig;
+    for (int32_t j = 0; j < lp->n; ++j) {
+        double x = u->d2[j] * xs[j];
+        int lf = is_fin(lp->lv[j]), uf = is_fin(lp->uv[j]);
+        if (lf && uf) x = 0.0;
+        else if (lf && x < 0.0) x = 0.0;       /* Xbar_j = R+ */
+        else if (uf && x > 0.0) x = 0.0;       /* Xbar_j = R- */
+        xo[j] = x;
+    }
+    orc_spmv(lp, xo, axo);
+    double res = 0.0;
+    for (int32_t i = 0; i < lp->m; ++i) {
+        double lc = lp->lc[i], uc = lp->uc[i];
+        int lf = is_fin(lc), uf = is_fin(uc);
+        double g = -axo[i], sv;
+        if (lf && uf) sv = 0.0;
+        else if (uf) sv = g > 0.0 ? g : 0.0;   /* Sbar_i = R+ */
+        else if (lf) sv = g < 0.0 ? g : 0.0;   /* Sbar_i = R- */
+        else sv = g;
+        int l_big = lf && lc != 0.0, u_big = uf && uc != 0.0;
+        double q;
+        if (l_big && !u_big) q = fabs(lc);
+        else if (!l_big && u_big) q = fabs(uc);
+        else if (l_big && u_big) q = fabs(lc) > fabs(uc) ? fabs(lc) : fabs(uc);
+        else q = 1.0;
+        double e = fabs(axo[i] + sv) / q;
+        if (e > res || e != e) res = e;
+    }
+    double obj = dot(lp->c, xo, lp->n);
+    out->obj = obj;
+    out->res = res;
+    out->ok = obj < 0.0 && res <= eps * fabs(obj);
+}
+
 /* ------------------------------------------------------------ main loop */
 
 /*
@@ -606,6 +713,8 @@ typedef struct {
     double *xp, *yp;                   /* previous restart point */
     double *gs, *bps;                  /* gap scratch */
     double *kx, *kr, *katy, *ky, *kax; /* kkt scratch */
+    double *xprev, *yprev;             /* iterate before the latest accepted step */
+    double *xc, *yc;                   /* infeasibility candidate */
 } loop_ctx;
 
 static int term_met(const loop_ctx *L, int mode, const orc_kkt *k) {
@@ -628,6 +737,61 @@ static void compute_average(loop_ctx *L) {
     orc_spmv(lp, L->xb, L->axb);
     orc_spmv_t(lp, L->yb, L->atyb);
     st->kkt_passes += 1;
+}
+
+/* Projection of a scaled point onto Xbar x Y (sign-only, as in the tests). */
+static void project_cones(const orc_lp *lp, const double *xs, const double *ys, double *px,
+                          double *py) {
+    for (int32_t j = 0; j < lp->n; ++j) {
+        double x = xs[j];
+        int lf = is_fin(lp->lv[j]), uf = is_fin(lp->uv[j]);
+        if ((lf && uf) || (lf && x < 0.0) || (uf && x > 0.0)) x = 0.0;
+        px[j] = x;
+    }
+    for (int32_t i = 0; i < lp->m; ++i) {
+        double y = ys[i];
+        int lf = is_fin(lp->lc[i]), uf = is_fin(lp->uc[i]);
+        if ((!lf && !uf) || (!lf && y > 0.0) || (!uf && y < 0.0)) y = 0.0;
+        py[i] = y;
+    }
+}
+
+/*
+ * Infeasibility detection (Section 3, "Infeasibility detection", with the
+ * tests of Appendix D).  Three candidates, in this order: the difference of
+ * the two latest iterates, the current iterate, and the average since the
+ * last restart.  The paper normalizes the last two by the iteration count;
+ * both tests are invariant under positive scaling of the candidate, so they
+ * are tested as they are.  Reading: primal infeasibility is tested on all
+ * three candidates before dual infeasibility.  Returns 0, ORC_PINF or
+ * ORC_DINF; on detection out_x/out_y (scaled) receive the certifying
+ * candidate projected onto Xbar x Y.
+ */
+static int infeas_check(loop_ctx *L, double *out_x, double *out_y, orc_result *res) {
+    const orc_lp *lp = L->lp;
+    const orc_state *st = L->st;
+    const double eps = L->prm->eps_infeas;
+    int32_t m = lp->m, n = lp->n;
+    for (int32_t j = 0; j < n; ++j) L->xc[j] = st->x[j] - L->xprev[j];
+    for (int32_t i = 0; i < m; ++i) L->yc[i] = st->y[i] - L->yprev[i];
+    const double *cx[3] = {L->xc, st->x, L->xb};
+    const double *cy[3] = {L->yc, st->y, L->yb};
+    orc_cert ct;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int c = 0; c < 3; ++c) {
+            if (pass == 0)
+                orc_primal_infeas_test(L->u, cy[c], eps, L->ky, L->katy, L->kr, &ct);
+            else
+                orc_dual_infeas_test(L->u, cx[c], eps, L->kx, L->kax, &ct);
+            if (!ct.ok) continue;
+            project_cones(lp, cx[c], cy[c], out_x, out_y);
+            res->cert_source = c + 1;
+            res->cert_obj = ct.obj;
+            res->cert_res = ct.res;
+            return pass == 0 ? ORC_PINF : ORC_DINF;
+        }
+    }
+    return 0;
 }
 
 static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish,
@@ -778,7 +942,12 @@ static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish
         if (term_met(L, term_mode, &kk)) return ORC_OK;
         if (st->k >= max_k) return ORC_LIMIT;
     }
+    const int detect = term_mode == TERM_FULL && prm->detect_infeas;
     while (st->k < max_k) {
+        if (detect) {
+            memcpy(L->xprev, st->x, sizeof(double) * n);
+            memcpy(L->yprev, st->y, sizeof(double) * m);
+        }
         int rc = orc_adaptive_step(lp, prm, st, L->scr);
         if (rc != ORC_OK) return ORC_NUMERR;
         double eta = st->last_eta;
@@ -830,6 +999,10 @@ static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish
             memcpy(out_y, cy, sizeof(double) * m);
             *out_kkt = kk;
             if (term_met(L, term_mode, &kk)) return ORC_OK;
+            if (detect) {
+                int inf = infeas_check(L, out_x, out_y, res);
+                if (inf) return inf;
+            }
             if (capchk) return ORC_LIMIT;
         }
 
@@ -882,15 +1055,18 @@ static int alloc_ctx(loop_ctx *L, int32_t m, int32_t n) {
     L->kx = malloc(bn); L->kr = malloc(bn); L->katy = malloc(bn);
     L->yb = malloc(bm); L->axb = malloc(bm); L->yp = malloc(bm);
     L->ky = malloc(bm); L->kax = malloc(bm);
+    L->xprev = malloc(bn); L->xc = malloc(bn);
+    L->yprev = malloc(bm); L->yc = malloc(bm);
     L->bps = malloc(sizeof(double) * (2 * ((size_t)m + n) + 1));
     return L->xb && L->atyb && L->xp && L->gs && L->kx && L->kr && L->katy && L->yb &&
-           L->axb && L->yp && L->ky && L->kax && L->bps;
+           L->axb && L->yp && L->ky && L->kax && L->bps && L->xprev && L->xc && L->yprev &&
+           L->yc;
 }
 
 static void free_ctx(loop_ctx *L) {
     free(L->xb); free(L->atyb); free(L->xp); free(L->gs); free(L->kx); free(L->kr);
     free(L->katy); free(L->yb); free(L->axb); free(L->yp); free(L->ky); free(L->kax);
-    free(L->bps);
+    free(L->bps); free(L->xprev); free(L->xc); free(L->yprev); free(L->yc);
 }
 
 /*
@@ -899,7 +1075,8 @@ static void free_ctx(loop_ctx *L) {
  * max_iters - st->k further accepted steps with restart checks and no
  * termination test.  out_x/out_y (scaled, caller owned) receive the returned
  * point (the candidate of the last termination evaluation; the current
- * iterate in the no-termination mode).  Returns the status code.  When
+ * iterate in the no-termination mode; the certificate on an infeasible
+ * status).  Returns the status code.  When
  * `tape` is not NULL the decisions of every accepted step are recorded in it
  * (see orc_tape).
  */
@@ -912,6 +1089,8 @@ int32_t orc_pdlp_record(const orc_lp *lp, const orc_unscale *u, const orc_params
     if (!alloc_ctx(&L, lp->m, lp->n)) { free_ctx(&L); return -3; }
     orc_kkt kk;
     memset(&kk, 0, sizeof kk);
+    res->cert_source = 0;
+    res->cert_obj = res->cert_res = 0.0;
     int term_mode = prm->terminate ? TERM_FULL : TERM_NONE;
     int rc = pdlp_loop(&L, prm->max_iters, term_mode, prm->polish && prm->terminate,
                        out_x, out_y, &kk, res);

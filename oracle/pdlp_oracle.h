@@ -42,6 +42,8 @@ typedef struct {
     int32_t fixed_step;            /* test mode: constant eta, no adaptive rule */
     double fixed_eta;
     int32_t adaptive_restarts;     /* 0: only condition (iii) */
+    int32_t detect_infeas;         /* Appendix D tests at every termination check */
+    double eps_infeas;             /* their threshold (1e-9) */
 } orc_params;
 
 /* Iterate state; every array is owned by the caller. */
@@ -72,7 +74,8 @@ typedef struct {
 } orc_unscale;
 
 typedef struct {
-    int32_t status;                /* 0 optimal, 1 iteration limit, 3 numerical error */
+    int32_t status;                /* 0 optimal, 1 iteration limit, 3 numerical error,
+                                      4 primal infeasible, 5 dual infeasible */
     int64_t iterations, attempts, kkt_passes;
     int64_t restarts, restarts_i, restarts_ii, restarts_iii;
     double primal_obj, dual_obj, rel_gap;
@@ -80,6 +83,9 @@ typedef struct {
     double omega, eta;
     int64_t polish_attempts, polish_iters;
     int32_t polished;
+    int32_t cert_source;           /* infeasible status: 1 difference of consecutive
+                                      iterates, 2 current iterate, 3 average */
+    double cert_obj, cert_res;     /* objective and weighted residual of that certificate */
 } orc_result;
 
 typedef struct {
@@ -98,6 +104,22 @@ typedef struct {
     double *eta, *omega;
     int32_t *restart;
 } orc_tape;
+
+/*
+ * Outcome of one Appendix D test: `obj` is the certificate's objective
+ * (primal test: lc^T y+ - uc^T y- + lv^T r+ - uv^T r-; dual test: c^T x),
+ * `res` the largest weighted residual component, `ok` 1 when the candidate
+ * certifies infeasibility at the threshold.
+ */
+typedef struct {
+    double obj, res;
+    int32_t ok;
+} orc_cert;
+
+void orc_primal_infeas_test(const orc_unscale *u, const double *ys, double eps, double *yo,
+                            double *atyo, double *ro, orc_cert *out);
+void orc_dual_infeas_test(const orc_unscale *u, const double *xs, double eps, double *xo,
+                          double *axo, orc_cert *out);
 
 /* Sparse products and the dual case step (pdlp_oracle.c). */
 void orc_spmv(const orc_lp *lp, const double *x, double *out);
