@@ -46,6 +46,8 @@ extern "C" {
 #define PDLP_STATUS_ITERATION_LIMIT 1
 #define PDLP_STATUS_TIME_LIMIT 2
 #define PDLP_STATUS_NUMERICAL_ERROR 3
+#define PDLP_STATUS_PRIMAL_INFEASIBLE 4  /* Appendix D certificate (y, r) found */
+#define PDLP_STATUS_DUAL_INFEASIBLE 5    /* Appendix D certificate (x, s) found */
 
 typedef struct pdlp_problem pdlp_problem; /* opaque: device copy of A, A^T, scaling */
 typedef struct pdlp_state pdlp_state;     /* opaque: iterate state on the device */
@@ -79,13 +81,31 @@ typedef struct pdlp_params {
     int32_t profile;          /* 1: time the step kernels with HIP events (pdlp_state_kernel_stats) */
     int32_t reorder;          /* 1 (default): relabel rows/columns by decreasing length inside the
                                  library (cache locality of the gathers); results are unaffected */
-    int32_t reserved;
+    int32_t detect_infeasibility; /* 1 (default): Appendix D tests at every termination check */
+    double eps_infeasible;    /* threshold of those tests (1e-9) */
 } pdlp_params;
 
 /* Result of a solve.  x, y, r are caller buffers of length n, m, n (or NULL);
  * they receive the unscaled solution x = D2 x~, y = D1 y~ and the reduced
  * costs used in the termination test.  Residuals follow Section 6, eq.
- * "rescaled-termination-criteria" (relative) and its l_inf absolute form. */
+ * "rescaled-termination-criteria" (relative) and its l_inf absolute form.
+ *
+ * Infeasibility (Section 3, "Infeasibility detection"; Appendix D): at every
+ * termination check that does not terminate, three candidates are tested in
+ * this order -- the difference of the two latest iterates, the current
+ * iterate, and the average since the last restart (the tests are invariant
+ * under positive scaling, so the paper's normalization is implied) -- first
+ * for primal, then for dual infeasibility.  A candidate's y is projected onto
+ * Y and its x onto the recession cone Xbar of the variable bounds; the primal
+ * test takes r = proj_R(-A^T y) and needs lc^T y+ - uc^T y- + lv^T r+ - uv^T r-
+ * > 0 with max_j |A^T y + r|_j / w_j <= eps_infeasible times it (w_j = |c_j|,
+ * or 1 where c_j = 0); the dual test takes s = proj_Sbar(-A x) and needs
+ * c^T x < 0 with max_i |A x + s|_i / q_i <= eps_infeasible |c^T x| (q as in
+ * the relative primal residual).  The weights are those of the termination
+ * criteria: the paper states the tests on instances rescaled to unit
+ * objective and right-hand-side entries.  On an infeasible status x, y hold
+ * the certifying candidate projected onto Xbar x Y (unscaled) and r holds
+ * proj_R(-A^T y); the KKT fields keep the last termination evaluation. */
 typedef struct pdlp_result {
     double *x, *y, *r;        /* in: caller buffers or NULL */
     int32_t status;
@@ -100,6 +120,11 @@ typedef struct pdlp_result {
     double omega, eta;        /* final primal weight and step size */
     double seconds;           /* wall time inside pdlp_solve */
     double seconds_setup;     /* preconditioning + initialization part of it */
+    int32_t certificate;      /* infeasible status: 1 difference of iterates, 2 iterate,
+                                 3 average; else 0 */
+    int32_t reserved;
+    double certificate_objective; /* the test's objective (> 0 primal, < 0 dual) */
+    double certificate_residual;  /* its weighted residual */
 } pdlp_result;
 
 /* Counters after pdlp_iterate_k. */

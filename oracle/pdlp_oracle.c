@@ -635,7 +635,7 @@ void orc_primal_infeas_test(const orc_unscale *u, const double *ys, double eps, 
     }
     out->obj = obj;
     out->res = res;
-    out->ok = obj > 0.0 && res <= eps * obj;
+    out->ok = is_fin(obj) && is_fin(res) && obj > 0.0 && res <= eps * obj;
 }
 
 /*
@@ -683,7 +683,7 @@ void orc_dual_infeas_test(const orc_unscale *u, const double *xs, double eps, do
     double obj = dot(lp->c, xo, lp->n);
     out->obj = obj;
     out->res = res;
-    out->ok = obj < 0.0 && res <= eps * fabs(obj);
+    out->ok = is_fin(obj) && is_fin(res) && obj < 0.0 && res <= eps * fabs(obj);
 }
 
 /* ------------------------------------------------------------ main loop */
@@ -763,13 +763,15 @@ static void project_cones(const orc_lp *lp, const double *xs, const double *ys, 
  * last restart.  The paper normalizes the last two by the iteration count;
  * both tests are invariant under positive scaling of the candidate, so they
  * are tested as they are.  Reading: primal infeasibility is tested on all
- * three candidates before dual infeasibility.  Returns 0, ORC_PINF or
- * ORC_DINF; on detection out_x/out_y (scaled) receive the certifying
- * candidate projected onto Xbar x Y.
+ * three candidates before dual infeasibility.  Each candidate costs one
+ * A x and one A^T y, counted as three KKT passes per check.  Returns 0,
+ * ORC_PINF or ORC_DINF; on detection out_x/out_y (scaled) receive the
+ * certifying candidate projected onto Xbar x Y.
  */
 static int infeas_check(loop_ctx *L, double *out_x, double *out_y, orc_result *res) {
     const orc_lp *lp = L->lp;
-    const orc_state *st = L->st;
+    orc_state *st = L->st;
+    st->kkt_passes += 3;
     const double eps = L->prm->eps_infeas;
     int32_t m = lp->m, n = lp->n;
     for (int32_t j = 0; j < n; ++j) L->xc[j] = st->x[j] - L->xprev[j];

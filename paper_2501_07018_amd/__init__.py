@@ -23,7 +23,8 @@ PDLP_ERR_INVALID_ARGUMENT = -1
 PDLP_ERR_HIP = -2
 PDLP_ERR_OUT_OF_MEMORY = -3
 PDLP_ERR_STATE = -4
-STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR"}
+STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "TIME_LIMIT", 3: "NUMERICAL_ERROR",
+          4: "PRIMAL_INFEASIBLE", 5: "DUAL_INFEASIBLE"}
 
 D = C.POINTER(C.c_double)
 I32 = C.POINTER(C.c_int32)
@@ -44,7 +45,7 @@ class Params(C.Structure):
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("theta", C.c_double),
                 ("eps_zero", C.c_double), ("red_exp", C.c_double), ("grow_exp", C.c_double),
                 ("verbose", C.c_int32), ("profile", C.c_int32), ("reorder", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("detect_infeasibility", C.c_int32), ("eps_infeasible", C.c_double)]
 
 
 class Result(C.Structure):
@@ -57,7 +58,9 @@ class Result(C.Structure):
                 ("primal_res_abs", C.c_double), ("primal_res_rel", C.c_double),
                 ("dual_res_abs", C.c_double), ("dual_res_rel", C.c_double),
                 ("omega", C.c_double), ("eta", C.c_double), ("seconds", C.c_double),
-                ("seconds_setup", C.c_double)]
+                ("seconds_setup", C.c_double), ("certificate", C.c_int32),
+                ("reserved", C.c_int32), ("certificate_objective", C.c_double),
+                ("certificate_residual", C.c_double)]
 
 
 class IterInfo(C.Structure):

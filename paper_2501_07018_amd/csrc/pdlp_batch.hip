@@ -50,6 +50,7 @@ struct pdlp::host::BatchWork {
     Arena arena;
     Iter it{};
     double *x0, *y0, *xb, *yb, *axb, *atyb, *xp, *yp, *xo, *yo, *ro;
+    double *cx, *cy, *cax, *caty;  // infeasibility candidate and its products
     Ctrl *ctrl_d, *ctrl_h;
     double *part_dual, *part_ps, *part_pf, *part_chk;
     GapState *gs_d, *gs_h;
@@ -68,7 +69,10 @@ pdlp_batch::~pdlp_batch() {
 
 namespace {
 
-enum { MASK_CHK = 0, MASK_KKT, MASK_RST, MASK_RST_AVG, kMasks };
+enum { MASK_CHK = 0, MASK_KKT, MASK_RST, MASK_RST_AVG, MASK_INF, kMasks };
+// per-instance values pulled at once: 7 of the termination test, or
+// kCertVals for each of the three infeasibility candidates
+constexpr int kOutVals = 3 * pdlp::kCertVals > 7 ? 3 * pdlp::kCertVals : 7;
 
 BatchWork *make_work(pdlp_batch *b) {
     pdlp_problem *P = b->P;
@@ -86,9 +90,9 @@ BatchWork *make_work(pdlp_batch *b) {
         }
         W->it.sx = a.dev<double>(N);
         W->it.sy = a.dev<double>(M);
-        double **vn[] = {&W->x0, &W->xb, &W->atyb, &W->xp, &W->xo, &W->ro};
+        double **vn[] = {&W->x0, &W->xb, &W->atyb, &W->xp, &W->xo, &W->ro, &W->cx, &W->caty};
         for (auto p : vn) *p = a.dev<double>(N);
-        double **vm[] = {&W->y0, &W->yb, &W->axb, &W->yp, &W->yo};
+        double **vm[] = {&W->y0, &W->yb, &W->axb, &W->yp, &W->yo, &W->cy, &W->cax};
         for (auto p : vm) *p = a.dev<double>(M);
         W->ctrl_d = a.dev<Ctrl>(B);
         W->ctrl_h = a.host<Ctrl>(B);
@@ -98,8 +102,8 @@ BatchWork *make_work(pdlp_batch *b) {
         W->part_chk = a.dev<double>(7 * (size_t)std::max(ncb, 1));
         W->gs_d = a.dev<GapState>(3 * (size_t)B);
         W->gs_h = a.host<GapState>(3 * (size_t)B);
-        W->out_d = a.dev<double>(7 * (size_t)B);
-        W->out_h = a.host<double>(7 * (size_t)B);
+        W->out_d = a.dev<double>(kOutVals * (size_t)B);
+        W->out_h = a.host<double>(kOutVals * (size_t)B);
         W->mask_d = a.dev<int32_t>(kMasks * (size_t)B);
         W->mask_h = a.host<int32_t>(kMasks * (size_t)B);
         W->sel_d = a.dev<int32_t>(B);
@@ -133,6 +137,8 @@ struct Inst {
     int out_sel = 0;    // its buffers: 0 current iterate, 1 average
     // flags of the current round
     bool full = false, art = false, capchk = false, chk = false, use_cur = false;
+    int cert_src = 0;   // infeasibility certificate: candidate 1..3
+    pdlp::CertOut cert{};
     double mu_c = 0.0;
 };
 
@@ -538,6 +544,71 @@ class BatchSolver {
     }
 
     // Periodic checks of Section 3 for the instances at a boundary.
+    // Infeasibility candidate c (0 difference of the current and previous
+    // iterate, 1 current iterate, 2 average) of the instances in mask mk,
+    // projected onto Xbar x Y, with its products.
+    struct CertPoint {
+        const double *px, *py, *pax, *paty;
+    };
+    CertPoint cert_point(int c, const int32_t *mk) {
+        const BatchMaps &bm = bm_;
+        const Vecs orig{P_->c, P_->lc, P_->uc, P_->lv, P_->uv};
+        HIPCHECK(pdlp::launch_b_cert_point(s(), P_->A, P_->AT, bm, mk, c, W_.it, W_.xb, orig,
+                                           W_.cx, W_.cy));
+        HIPCHECK(pdlp::launch_b_spmv_plain(s(), P_->A, bm.ablk_inst, bm.alist, bm.na, mk, W_.cx,
+                                           W_.cax));
+        if (c == 0) {
+            HIPCHECK(pdlp::launch_b_spmv_plain(s(), P_->AT, bm.tblk_inst, bm.tlist, bm.nt, mk,
+                                               W_.cy, W_.caty));
+            return {W_.cx, W_.cy, W_.cax, W_.caty};
+        }
+        if (c == 1) return {W_.cx, W_.it.Y[0], W_.cax, W_.it.ATY[0]};
+        return {W_.cx, W_.yb, W_.cax, W_.atyb};
+    }
+
+    // Appendix D tests on the three candidates of the instances in
+    // MASK_INF (the single-LP order: primal infeasibility on each candidate,
+    // then dual infeasibility); an instance at its iteration cap that is not
+    // declared infeasible stops with ITERATION_LIMIT.
+    void detect_infeasible() {
+        push_masks();
+        const int32_t *mk = mask_dev(MASK_INF);
+        const Vecs orig{P_->c, P_->lc, P_->uc, P_->lv, P_->uv};
+        const size_t nv = pdlp::kCertVals;
+        for (int c = 0; c < 3; ++c) {
+            const CertPoint q = cert_point(c, mk);
+            HIPCHECK(pdlp::launch_b_cert(s(), P_->A, P_->AT, bm_, mk, q.px, q.py, q.pax, q.paty,
+                                         P_->d1, P_->d2, orig, W_.part_chk,
+                                         W_.out_d + (size_t)c * nv * B()));
+        }
+        pull_out(3 * (int)nv);
+        const double eps = prm_.eps_infeasible;
+        for (int i = 0; i < B(); ++i) {
+            if (!mask(MASK_INF)[i]) continue;
+            Inst &st = inst_[i];
+            st.kkt_passes += 3;
+            for (int pass = 0; pass < 2 && st.status < 0; ++pass) {
+                for (int c = 0; c < 3; ++c) {
+                    const double *v = W_.out_h + ((size_t)c * B() + i) * nv;
+                    const pdlp::CertOut o{v[0], v[1], v[2], v[3], v[4]};
+                    if (o.nonfinite > 0.0) continue;
+                    const bool ok = pass == 0 ? (std::isfinite(o.pobj) && o.pobj > 0.0 &&
+                                                 o.pres <= eps * o.pobj)
+                                              : (std::isfinite(o.dobj) && o.dobj < 0.0 &&
+                                                 o.dres <= eps * std::fabs(o.dobj));
+                    if (!ok) continue;
+                    st.status = pass == 0 ? PDLP_STATUS_PRIMAL_INFEASIBLE
+                                          : PDLP_STATUS_DUAL_INFEASIBLE;
+                    st.cert_src = c + 1;
+                    st.cert = o;
+                    break;
+                }
+            }
+            if (st.status < 0 && st.capchk) st.status = PDLP_STATUS_ITERATION_LIMIT;
+            if (st.status >= 0) st.chk = false;
+        }
+    }
+
     void check_round(long long max_k) {
         const BatchMaps &bm = bm_;
         const Vecs v = P_->scaled();
@@ -595,6 +666,7 @@ class BatchSolver {
             }
         }
         if (any_kkt) {
+            bool any_inf = false;
             eval_kkt();
             for (int i = 0; i < B(); ++i) {
                 Inst &st = inst_[i];
@@ -608,11 +680,15 @@ class BatchSolver {
                     st.status = PDLP_STATUS_NUMERICAL_ERROR;
                 } else if (met(prm_, kkt_[i])) {
                     st.status = PDLP_STATUS_OPTIMAL;
+                } else if (prm_.detect_infeasibility) {
+                    mask(MASK_INF)[i] = 1;
+                    any_inf = true;
                 } else if (st.capchk) {
                     st.status = PDLP_STATUS_ITERATION_LIMIT;
                 }
                 if (st.status >= 0) st.chk = false;
             }
+            if (any_inf) detect_infeasible();
         }
         // restart decisions (criteria (i)-(iii))
         bool any_rst = false;
@@ -705,6 +781,24 @@ class BatchSolver {
                                     p1, P_->d1, P_->d2, orig, rc_mode_, W_.part_chk, W_.out_d,
                                     W_.ro, W_.xo, W_.yo));
         pull_out(7);
+        std::vector<double> kout(W_.out_h, W_.out_h + 7 * (size_t)B());
+        // certificates of the instances declared infeasible replace their outputs
+        for (int c = 0; c < 3; ++c) {
+            bool any = false;
+            for (int i = 0; i < B(); ++i) {
+                const Inst &st = inst_[i];
+                const bool inf = st.status == PDLP_STATUS_PRIMAL_INFEASIBLE ||
+                                 st.status == PDLP_STATUS_DUAL_INFEASIBLE;
+                mask(MASK_INF)[i] = inf && st.cert_src == c + 1;
+                any = any || mask(MASK_INF)[i];
+            }
+            if (!any) continue;
+            push_masks();
+            const int32_t *mk = mask_dev(MASK_INF);
+            const CertPoint q = cert_point(c, mk);
+            HIPCHECK(pdlp::launch_b_cert_out(s(), P_->A, P_->AT, bm_, mk, q.px, q.py, q.paty,
+                                             P_->d1, P_->d2, orig, W_.xo, W_.yo, W_.ro));
+        }
         const int64_t M = P_->m, N = P_->n;
         if (x_host && N > 0)
             HIPCHECK(hipMemcpyAsync(x_host, W_.xo, sizeof(double) * N, hipMemcpyDeviceToHost, s()));
@@ -716,7 +810,7 @@ class BatchSolver {
         for (int i = 0; i < B(); ++i) {
             const Inst &st = inst_[i];
             const Ctrl &c = W_.ctrl_h[i];
-            const KktHost k = kkt_from(W_.out_h + 7 * i, b_->obj_offset[i]);
+            const KktHost k = kkt_from(kout.data() + 7 * i, b_->obj_offset[i]);
             pdlp_result &r = res[i];
             std::memset(&r, 0, sizeof r);
             r.status = st.status >= 0 ? st.status : PDLP_STATUS_ITERATION_LIMIT;
@@ -736,6 +830,12 @@ class BatchSolver {
             r.dual_res_rel = k.dres_rel;
             r.omega = c.omega;
             r.eta = c.eta_hat;
+            if (st.cert_src) {
+                const bool pinf = st.status == PDLP_STATUS_PRIMAL_INFEASIBLE;
+                r.certificate = st.cert_src;
+                r.certificate_objective = pinf ? st.cert.pobj : st.cert.dobj;
+                r.certificate_residual = pinf ? st.cert.pres : st.cert.dres;
+            }
             r.seconds = secs;
             r.seconds_setup = setup;
         }

@@ -219,6 +219,8 @@ __global__ __launch_bounds__(kThreads) void kb_decide(Ctrl *ctrl, BatchMaps bm, 
 
 // Dual average owed by the last accepted step, then the current iterate is
 // moved to buffer 0 so the checks see every instance in the same buffers.
+// The move is a swap: buffer 1 keeps the previous iterate, the other point
+// of the difference candidate of infeasibility detection.
 __global__ __launch_bounds__(kThreads) void kb_settle(DCsr A, DCsr AT, Iter it, const Ctrl *ctrl,
                                                       BatchMaps bm) {
     for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
@@ -228,8 +230,11 @@ __global__ __launch_bounds__(kThreads) void kb_settle(DCsr A, DCsr AT, Iter it, 
         if (cb < bm.nT) {
             if (c.cur != 1) continue;
             for (int j = AT.blk[cb] + threadIdx.x; j < AT.blk[cb + 1]; j += kThreads) {
+                const double x0 = it.X[0][j], a0 = it.ATY[0][j];
                 it.X[0][j] = it.X[1][j];
                 it.ATY[0][j] = it.ATY[1][j];
+                it.X[1][j] = x0;
+                it.ATY[1][j] = a0;
             }
         } else {
             const int b = cb - bm.nT;
@@ -239,8 +244,11 @@ __global__ __launch_bounds__(kThreads) void kb_settle(DCsr A, DCsr AT, Iter it, 
                 const double yr = it.Y[cur][r];
                 if (pend) it.sy[r] += c.eta_avg_y * yr;
                 if (cur == 1) {
+                    const double y0 = it.Y[0][r], a0 = it.AX[0][r];
                     it.Y[0][r] = yr;
                     it.AX[0][r] = it.AX[1][r];
+                    it.Y[1][r] = y0;
+                    it.AX[1][r] = a0;
                 }
             }
         }
@@ -477,6 +485,84 @@ __device__ __forceinline__ bool coord_range(const DCsr &A, const DCsr &AT, const
     lo = A.blk[cb - bm.nT];
     hi = A.blk[cb - bm.nT + 1];
     return false;
+}
+
+// Infeasibility candidate per check block of masked instances (Section 3,
+// "Infeasibility detection"): cand 0 the difference of buffers 0 and 1
+// (current and previous iterate), 1 the current iterate, 2 the average
+// (xb, yb); x projected onto Xbar into px; for cand 0 y projected onto Y
+// into py (the iterate's and the average's y already lie in Y).
+__global__ __launch_bounds__(kThreads) void kb_cert_point(DCsr A, DCsr AT, BatchMaps bm,
+                                                          const int32_t *mask, int cand, Iter it,
+                                                          const double *xb, Vecs orig,
+                                                          double *px, double *py) {
+    for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
+        const int cb = bm.clist[ci];
+        if (cb < 0) continue;
+        if (!mask[cb_inst(bm, cb)]) continue;
+        if (cb < bm.nT) {
+            const double *xa = cand == 2 ? xb : it.X[0];
+            for (int j = AT.blk[cb] + threadIdx.x; j < AT.blk[cb + 1]; j += kThreads) {
+                const double x = cand == 0 ? xa[j] - it.X[1][j] : xa[j];
+                px[j] = proj_xbar(x, orig.lv[j], orig.uv[j]);
+            }
+        } else if (cand == 0) {
+            const int b = cb - bm.nT;
+            for (int r = A.blk[b] + threadIdx.x; r < A.blk[b + 1]; r += kThreads)
+                py[r] = proj_ycone(it.Y[0][r] - it.Y[1][r], orig.lc[r], orig.uc[r]);
+        }
+    }
+}
+
+// Appendix D test values per check block (cert_row / cert_col).
+__global__ __launch_bounds__(kThreads) void kb_cert(DCsr A, DCsr AT, BatchMaps bm,
+                                                    const int32_t *mask, const double *px,
+                                                    const double *py, const double *pax,
+                                                    const double *paty, const double *d1,
+                                                    const double *d2, Vecs orig, double *part) {
+    __shared__ double red[kCertVals * (kThreads / 64)];
+    for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
+        const int cb = bm.clist[ci];
+        if (cb < 0) continue;
+        if (!mask[cb_inst(bm, cb)]) continue;
+        double acc[kCertVals] = {0, 0, 0, 0, 0};
+        if (cb < bm.nT) {
+            for (int j = AT.blk[cb] + threadIdx.x; j < AT.blk[cb + 1]; j += kThreads)
+                cert_col(px[j], paty[j], d2[j], orig.c[j], orig.lv[j], orig.uv[j], acc);
+        } else {
+            const int b = cb - bm.nT;
+            for (int r = A.blk[b] + threadIdx.x; r < A.blk[b + 1]; r += kThreads)
+                cert_row(py[r], pax[r], d1[r], orig.lc[r], orig.uc[r], acc);
+        }
+        block_reduce<kCertVals, kCertMax>(acc, red);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < kCertVals; ++k) part[(size_t)cb * kCertVals + k] = acc[k];
+    }
+}
+
+// Unscaled certificate outputs of masked instances: x = D2 px, y = D1 py,
+// r = proj_R(-(A^T y)).
+__global__ __launch_bounds__(kThreads) void kb_cert_out(DCsr A, DCsr AT, BatchMaps bm,
+                                                        const int32_t *mask, const double *px,
+                                                        const double *py, const double *paty,
+                                                        const double *d1, const double *d2,
+                                                        Vecs orig, double *x_out, double *y_out,
+                                                        double *r_out) {
+    for (int ci = blockIdx.x; ci < bm.nc; ci += gridDim.x) {
+        const int cb = bm.clist[ci];
+        if (cb < 0) continue;
+        if (!mask[cb_inst(bm, cb)]) continue;
+        if (cb < bm.nT) {
+            for (int j = AT.blk[cb] + threadIdx.x; j < AT.blk[cb + 1]; j += kThreads) {
+                x_out[j] = d2[j] * px[j];
+                r_out[j] = proj_rcone(-(paty[j] / d2[j]), orig.lv[j], orig.uv[j]);
+            }
+        } else {
+            const int b = cb - bm.nT;
+            for (int r = A.blk[b] + threadIdx.x; r < A.blk[b + 1]; r += kThreads)
+                y_out[r] = d1[r] * py[r];
+        }
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void kb_gap_setup(DCsr A, DCsr AT, BatchMaps bm,
@@ -786,6 +872,37 @@ hipError_t launch_b_kkt(hipStream_t s, const DCsr &A, const DCsr &AT, const Batc
                        d2, orig, mode, part, r_out, x_out, y_out);
     hipLaunchKernelGGL(kb_inst_reduce, dim3(wave_grid(bm.ni)), dim3(kThreads), 0, s, part, 7, 0x0Fu,
                        bm, mask, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_cert_point(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                              const int32_t *mask, int cand, Iter it, const double *xb,
+                              Vecs orig, double *px, double *py) {
+    if (bm.nc > 0)
+        hipLaunchKernelGGL(kb_cert_point, dim3(list_grid(bm.nc, kBatchGridCap)), dim3(kThreads), 0,
+                           s, A, AT, bm, mask, cand, it, xb, orig, px, py);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_cert(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                         const int32_t *mask, const double *px, const double *py,
+                         const double *pax, const double *paty, const double *d1,
+                         const double *d2, Vecs orig, double *part, double *out) {
+    if (bm.ni == 0) return hipSuccess;
+    hipLaunchKernelGGL(kb_cert, dim3(list_grid(bm.nc, kBatchGridCap)), dim3(kThreads), 0, s, A,
+                       AT, bm, mask, px, py, pax, paty, d1, d2, orig, part);
+    hipLaunchKernelGGL(kb_inst_reduce, dim3(wave_grid(bm.ni)), dim3(kThreads), 0, s, part,
+                       kCertVals, kCertMax, bm, mask, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_b_cert_out(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                             const int32_t *mask, const double *px, const double *py,
+                             const double *paty, const double *d1, const double *d2, Vecs orig,
+                             double *x_out, double *y_out, double *r_out) {
+    if (bm.nc > 0)
+        hipLaunchKernelGGL(kb_cert_out, dim3(list_grid(bm.nc, kBatchGridCap)), dim3(kThreads), 0,
+                           s, A, AT, bm, mask, px, py, paty, d1, d2, orig, x_out, y_out, r_out);
     return hipGetLastError();
 }
 

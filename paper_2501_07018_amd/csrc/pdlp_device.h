@@ -64,6 +64,80 @@ __device__ __forceinline__ double clampd(double v, double lo, double hi) {
     return v < lo ? lo : (v > hi ? hi : v);
 }
 
+// ------------------------------------------ infeasibility certificates
+//
+// Appendix D tests, evaluated in original units from scaled candidates
+// (x = D2 x~, y = D1 y~, A x = (A~ x~)/D1, A^T y = (A~^T y~)/D2).  Projections
+// depend only on signs and on which bounds are finite, so they commute with
+// the positive diagonal scalings.  Values accumulated per coordinate:
+//   0 primal-test objective lc^T y+ - uc^T y- + lv^T r+ - uv^T r-   (sum)
+//   1 primal-test residual max_j |A^T y + r|_j / w_j                (max)
+//   2 dual-test objective c^T x                                     (sum)
+//   3 dual-test residual max_i |A x + s|_i / q_i                    (max)
+//   4 count of non-finite inputs                                     (sum)
+// with r = proj_R(-A^T y), s = proj_Sbar(-A x), w_j = |c_j| (1 if c_j = 0)
+// and q_i the weight of the relative primal residual.
+// x onto Xbar: {0} boxed, R+ lower bound only, R- upper bound only, R free.
+__device__ __forceinline__ double proj_xbar(double x, double l, double u) {
+    const bool lf = isfinite(l), uf = isfinite(u);
+    return ((lf && uf) || (lf && x < 0.0) || (uf && x > 0.0)) ? 0.0 : x;
+}
+
+// y onto Y (Section 2): {0} free row, R- upper bound only, R+ lower bound only.
+__device__ __forceinline__ double proj_ycone(double y, double l, double u) {
+    const bool lf = isfinite(l), uf = isfinite(u);
+    return ((!lf && !uf) || (!lf && y > 0.0) || (!uf && y < 0.0)) ? 0.0 : y;
+}
+
+// g onto R_j: {0} free variable, R- upper bound only, R+ lower bound only.
+__device__ __forceinline__ double proj_rcone(double g, double l, double u) {
+    const bool lf = isfinite(l), uf = isfinite(u);
+    if (!lf && !uf) return 0.0;
+    if (!lf) return g < 0.0 ? g : 0.0;
+    if (!uf) return g > 0.0 ? g : 0.0;
+    return g;
+}
+
+__device__ __forceinline__ double row_weight(double l, double u) {
+    const bool lb = isfinite(l) && l != 0.0, ub = isfinite(u) && u != 0.0;
+    if (lb && !ub) return fabs(l);
+    if (!lb && ub) return fabs(u);
+    if (lb && ub) return fmax(fabs(l), fabs(u));
+    return 1.0;
+}
+
+// Row i of a projected scaled candidate: y~ (py) and A~ x~ (pax).
+__device__ __forceinline__ void cert_row(double py, double pax, double d1, double l, double u,
+                                         double (&acc)[kCertVals]) {
+    const double y = d1 * py;
+    if (y > 0.0) acc[0] += l * y;
+    else if (y < 0.0) acc[0] += u * y;
+    const double ax = pax / d1;
+    const bool lf = isfinite(l), uf = isfinite(u);
+    const double g = -ax;
+    double sv;
+    if (lf && uf) sv = 0.0;
+    else if (uf) sv = g > 0.0 ? g : 0.0;     // Sbar_i = R+
+    else if (lf) sv = g < 0.0 ? g : 0.0;     // Sbar_i = R-
+    else sv = g;
+    acc[3] = nan_max(acc[3], fabs(ax + sv) / row_weight(l, u));
+    if (!isfinite(y) || !isfinite(ax)) acc[4] += 1.0;
+}
+
+// Column j: x~ (px) and A~^T y~ (paty).
+__device__ __forceinline__ void cert_col(double px, double paty, double d2, double c, double l,
+                                         double u, double (&acc)[kCertVals]) {
+    const double aty = paty / d2;
+    const double r = proj_rcone(-aty, l, u);
+    if (r > 0.0) acc[0] += l * r;
+    else if (r < 0.0) acc[0] += u * r;
+    const double w = c != 0.0 ? fabs(c) : 1.0;
+    acc[1] = nan_max(acc[1], fabs(aty + r) / w);
+    const double x = d2 * px;
+    acc[2] += c * x;
+    if (!isfinite(x) || !isfinite(aty)) acc[4] += 1.0;
+}
+
 // Dual update in case form (Section 2): with yhat = y - sigma A(2x' - x),
 // y' = yhat + sigma uc if yhat < -sigma uc; yhat + sigma lc if yhat > -sigma lc; else 0.
 __device__ __forceinline__ double dual_case(double yhat, double sigma, double lc, double uc) {

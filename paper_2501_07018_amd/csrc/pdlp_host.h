@@ -128,6 +128,8 @@ inline void check_params(const pdlp_params &p) {
     if (p.max_iters < 0) invalid("max_iters must be >= 0");
     if (!(p.theta >= 0.0 && p.theta <= 1.0)) invalid("theta must lie in [0, 1]");
     if (!(p.beta_art > 0.0)) invalid("beta_art must be > 0");
+    if (p.detect_infeasibility && !(p.eps_infeasible >= 0.0))
+        invalid("eps_infeasible must be >= 0");
 }
 
 // Input checks of a problem (conventions of the C ABI); throws

@@ -262,7 +262,8 @@ void precondition(pdlp_problem *P, const pdlp_params &prm) {
 namespace {
 
 enum { TERM_NONE = 0, TERM_FULL = 1, TERM_PRIMAL = 2, TERM_DUAL = 3 };
-enum { RUN_OK = 0, RUN_LIMIT = 1, RUN_TIME = 2, RUN_NUMERR = 3, RUN_POLISHED = 10 };
+enum { RUN_OK = 0, RUN_LIMIT = 1, RUN_TIME = 2, RUN_NUMERR = 3, RUN_PINF = 4, RUN_DINF = 5,
+       RUN_POLISHED = 10 };
 
 // One PDLP run (the main run or a feasibility-polishing run) on the device.
 struct Engine {
@@ -280,6 +281,10 @@ struct Engine {
     KktOut *kkt_d = nullptr, *kkt_h = nullptr;
     double *gap_part = nullptr;
     int ggrid = 0;
+    // infeasibility candidate and its products (allocated at the first test)
+    Arena cert_arena;
+    double *cx = nullptr, *cy = nullptr, *cax = nullptr, *caty = nullptr;
+    pdlp::CertOut *cert_d = nullptr, *cert_h = nullptr;
     // host-side counters of Algorithm 1
     long long n_outer = 0, kkt_passes = 0, restarts_i = 0, restarts_ii = 0, restarts_iii = 0;
     double mu_ref = INFINITY, mu_c_prev = INFINITY;
@@ -458,6 +463,73 @@ struct Engine {
         HIPCHECK(hipStreamSynchronize(s()));
     }
 
+    // Infeasibility candidate c (0 difference of the two latest iterates,
+    // 1 current iterate, 2 average since the restart) projected onto
+    // Xbar x Y, with its products, at (cpx, cpy, cpax, cpaty).  After an
+    // accepted step the other buffer of the pair still holds the previous
+    // iterate: the step that ends a block does not start the next primal
+    // update.  The iterate's and the average's y already lie in Y (the dual
+    // step and averaging keep it there), so their cached A^T y serve; x needs
+    // its projection (boxed coordinates go to 0) and a fresh product.
+    const double *cpx = nullptr, *cpy = nullptr, *cpax = nullptr, *cpaty = nullptr;
+    void cert_point(int c) {
+        if (!cx) {
+            cx = cert_arena.dev<double>(n);
+            caty = cert_arena.dev<double>(n);
+            cy = cert_arena.dev<double>(m);
+            cax = cert_arena.dev<double>(m);
+            cert_d = cert_arena.dev<pdlp::CertOut>(3);
+            cert_h = cert_arena.host<pdlp::CertOut>(3);
+        }
+        const int cur = ctrl_h->cur;
+        if (c == 0) {
+            HIPCHECK(pdlp::launch_cert_point(s(), m, n, it.X[cur], it.X[cur ^ 1], it.Y[cur],
+                                             it.Y[cur ^ 1], P->lc, P->uc, P->lv, P->uv, cx, cy));
+            HIPCHECK(pdlp::launch_spmv_plain(s(), P->AT, cy, caty));
+            cpy = cy;
+            cpaty = caty;
+        } else {
+            HIPCHECK(pdlp::launch_cert_point(s(), 0, n, c == 1 ? it.X[cur] : xb, nullptr, nullptr,
+                                             nullptr, P->lc, P->uc, P->lv, P->uv, cx, nullptr));
+            cpy = c == 1 ? it.Y[cur] : yb;
+            cpaty = c == 1 ? it.ATY[cur] : atyb;
+        }
+        HIPCHECK(pdlp::launch_spmv_plain(s(), P->A, cx, cax));
+        cpx = cx;
+        cpax = cax;
+    }
+
+    // Appendix D tests of the three candidates: primal infeasibility on each
+    // in order, then dual infeasibility.  Returns RUN_PINF, RUN_DINF or 0 and
+    // the certifying candidate (1-based) with its values.
+    int infeasible(double eps, int &src, pdlp::CertOut &val) {
+        for (int c = 0; c < 3; ++c) {
+            cert_point(c);
+            HIPCHECK(pdlp::launch_cert(s(), m, n, cpx, cpy, cpax, cpaty, P->d1, P->d2, P->c,
+                                       P->lc, P->uc, P->lv, P->uv, P->red_part,
+                                       red_grid((int64_t)m + n), cert_d + c));
+        }
+        HIPCHECK(hipMemcpyAsync(cert_h, cert_d, 3 * sizeof(pdlp::CertOut), hipMemcpyDeviceToHost,
+                                s()));
+        HIPCHECK(hipStreamSynchronize(s()));
+        kkt_passes += 3;
+        for (int pass = 0; pass < 2; ++pass) {
+            for (int c = 0; c < 3; ++c) {
+                const pdlp::CertOut &o = cert_h[c];
+                if (o.nonfinite > 0.0) continue;
+                const bool ok = pass == 0 ? (std::isfinite(o.pobj) && o.pobj > 0.0 &&
+                                             o.pres <= eps * o.pobj)
+                                          : (std::isfinite(o.dobj) && o.dobj < 0.0 &&
+                                             o.dres <= eps * std::fabs(o.dobj));
+                if (!ok) continue;
+                src = c + 1;
+                val = o;
+                return pass == 0 ? RUN_PINF : RUN_DINF;
+            }
+        }
+        return 0;
+    }
+
     KktOut kkt(const double *x, const double *y, const double *ax, const double *aty, int mode,
                double *r_out = nullptr, double *x_out = nullptr, double *y_out = nullptr) {
         HIPCHECK(pdlp::launch_kkt(s(), m, n, x, y, ax, aty, P->d1, P->d2, P->c, P->lc, P->uc,
@@ -477,6 +549,8 @@ struct RunOut {
     Candidate cand{};
     KktOut kkt{};
     bool have = false;
+    int cert_src = 0;             // infeasibility certificate: candidate 1..3
+    pdlp::CertOut cert{};
 };
 
 bool term_met(const pdlp_params &prm, int mode, const KktOut &k) {
@@ -651,6 +725,10 @@ int run_loop(Ctx &X, Engine &E, long long max_k, int term_mode, bool allow_polis
                              out.kkt.dual_res_rel, out.kkt.rel_gap, out.kkt.primal_obj);
             if (!std::isfinite(out.kkt.rel_gap)) return RUN_NUMERR;
             if (term_met(prm, term_mode, out.kkt)) return RUN_OK;
+            if (term_mode == TERM_FULL && prm.detect_infeasibility) {
+                const int inf = E.infeasible(prm.eps_infeasible, out.cert_src, out.cert);
+                if (inf) return inf;
+            }
             if (capchk) return RUN_LIMIT;
         }
         int why = 0;
@@ -783,6 +861,8 @@ void pdlp_params_default(pdlp_params *p) {
     p->grow_exp = 0.6;
     p->verbose = 0;
     p->reorder = 1;
+    p->detect_infeasibility = 1;
+    p->eps_infeasible = 1e-9;
 }
 
 }  // extern "C"
@@ -1156,6 +1236,11 @@ void state_solve(pdlp_state *S, long long k, pdlp_result *res, double t0, double
         Arena tmp;
         double *rx = tmp.dev<double>(p->n), *ry = tmp.dev<double>(p->m), *rr = tmp.dev<double>(p->n);
         kk = E.kkt(out.cand.x, out.cand.y, out.cand.ax, out.cand.aty, rc_mode, rr, rx, ry);
+        if (rc == RUN_PINF || rc == RUN_DINF) {
+            E.cert_point(out.cert_src - 1);
+            HIPCHECK(pdlp::launch_cert_out(p->stream, p->m, p->n, E.cpx, E.cpy, E.cpaty, p->d1,
+                                           p->d2, p->lv, p->uv, rx, ry, rr));
+        }
         download_unperm(p, rx, p->n, p->col_order, ux);
         download_unperm(p, ry, p->m, p->row_order, uy);
         download_unperm(p, rr, p->n, p->col_order, ur);
@@ -1165,7 +1250,14 @@ void state_solve(pdlp_state *S, long long k, pdlp_result *res, double t0, double
     res->status = rc == RUN_OK || rc == RUN_POLISHED ? PDLP_STATUS_OPTIMAL
                   : rc == RUN_TIME                   ? PDLP_STATUS_TIME_LIMIT
                   : rc == RUN_NUMERR                 ? PDLP_STATUS_NUMERICAL_ERROR
+                  : rc == RUN_PINF                   ? PDLP_STATUS_PRIMAL_INFEASIBLE
+                  : rc == RUN_DINF                   ? PDLP_STATUS_DUAL_INFEASIBLE
                                                      : PDLP_STATUS_ITERATION_LIMIT;
+    if (rc == RUN_PINF || rc == RUN_DINF) {
+        res->certificate = out.cert_src;
+        res->certificate_objective = rc == RUN_PINF ? out.cert.pobj : out.cert.dobj;
+        res->certificate_residual = rc == RUN_PINF ? out.cert.pres : out.cert.dres;
+    }
     res->polished = rc == RUN_POLISHED;
     res->iterations = E.ctrl_h->k;
     res->attempts = E.ctrl_h->attempts;

@@ -104,6 +104,15 @@ struct KktOut {
     double pad;
 };
 
+// Appendix D test values of one infeasibility candidate: primal-test
+// objective and weighted residual, c^T x and the dual-test weighted
+// residual, and the count of non-finite inputs.
+struct CertOut {
+    double pobj, pres, dobj, dres, nonfinite;
+};
+constexpr int kCertVals = 5;           // the fields of CertOut, in order
+constexpr unsigned kCertMax = 0x0Au;   // pres and dres reduce by max, the rest by sum
+
 // Block maps of a batch of LPs packed block-diagonally: rows (columns) of
 // instance i are [roff[i], roff[i+1]) ([coff[i], coff[i+1])); row blocks of
 // A and of A^T never straddle two instances.
@@ -205,6 +214,22 @@ hipError_t launch_kkt(hipStream_t s, int m, int n, const double *xs, const doubl
                       const double *uv, int mode, double obj_offset, double *part, int grid,
                       double *r_out, double *x_out, double *y_out, KktOut *out);
 
+// infeasibility certificates (Appendix D): candidate (xa - xb, ya - yb), or
+// (xa, ya) when xb/yb are null, projected onto Xbar x Y; its test values from
+// the products of the projected point; its unscaled output (x, y, r).
+hipError_t launch_cert_point(hipStream_t s, int m, int n, const double *xa, const double *xb,
+                             const double *ya, const double *yb, const double *lc,
+                             const double *uc, const double *lv, const double *uv, double *px,
+                             double *py);
+hipError_t launch_cert(hipStream_t s, int m, int n, const double *px, const double *py,
+                       const double *pax, const double *paty, const double *d1, const double *d2,
+                       const double *c, const double *lc, const double *uc, const double *lv,
+                       const double *uv, double *part, int grid, CertOut *out);
+hipError_t launch_cert_out(hipStream_t s, int m, int n, const double *px, const double *py,
+                           const double *paty, const double *d1, const double *d2,
+                           const double *lv, const double *uv, double *x_out, double *y_out,
+                           double *r_out);
+
 // normalized duality gap
 hipError_t launch_gap(hipStream_t s, int m, int n, Vecs v, const double *x, const double *y,
                       const double *ax, const double *aty, const double *xr, const double *yr,
@@ -252,6 +277,18 @@ hipError_t launch_b_checkpoint(hipStream_t s, const DCsr &A, const DCsr &AT, con
                                int64_t M);
 // normalized duality gap per instance: begin = radius, slopes and the first
 // abscissa; then active-set steps first .. first+count-1 of at most `total`
+// infeasibility candidates of masked instances (see launch_cert_point)
+hipError_t launch_b_cert_point(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                              const int32_t *mask, int cand, Iter it, const double *xb,
+                              Vecs orig, double *px, double *py);
+hipError_t launch_b_cert(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                         const int32_t *mask, const double *px, const double *py,
+                         const double *pax, const double *paty, const double *d1,
+                         const double *d2, Vecs orig, double *part, double *out);
+hipError_t launch_b_cert_out(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
+                             const int32_t *mask, const double *px, const double *py,
+                             const double *paty, const double *d1, const double *d2, Vecs orig,
+                             double *x_out, double *y_out, double *r_out);
 hipError_t launch_b_gap_begin(hipStream_t s, const DCsr &A, const DCsr &AT, const BatchMaps &bm,
                               const int32_t *mask, Vecs v, const double *x, const double *y,
                               const double *ax, const double *aty, const double *xr,

@@ -534,6 +534,74 @@ __global__ void k_kkt_final(const double *part, int grid, double obj_offset, Kkt
     }
 }
 
+// ------------------------------------------- infeasibility certificates
+//
+// Section 3, "Infeasibility detection", Appendix D: a candidate (difference
+// of the two latest iterates, the iterate, or the average) projected onto
+// Xbar x Y in the scaled space, then its products, then the test values of
+// cert_row / cert_col.
+
+__global__ __launch_bounds__(kThreads) void k_cert_point(int m, int n, const double *xa,
+                                                         const double *xb, const double *ya,
+                                                         const double *yb, const double *lc,
+                                                         const double *uc, const double *lv,
+                                                         const double *uv, double *px,
+                                                         double *py) {
+    const int stride = gridDim.x * kThreads;
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
+        const double x = xb ? xa[j] - xb[j] : xa[j];
+        px[j] = proj_xbar(x, lv[j], uv[j]);
+    }
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) {
+        const double y = yb ? ya[i] - yb[i] : ya[i];
+        py[i] = proj_ycone(y, lc[i], uc[i]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_cert(int m, int n, const double *px,
+                                                   const double *py, const double *pax,
+                                                   const double *paty, const double *d1,
+                                                   const double *d2, const double *c,
+                                                   const double *lc, const double *uc,
+                                                   const double *lv, const double *uv,
+                                                   double *part) {
+    __shared__ double red[kCertVals * (kThreads / 64)];
+    double acc[kCertVals] = {0, 0, 0, 0, 0};
+    const int stride = gridDim.x * kThreads;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride)
+        cert_row(py[i], pax[i], d1[i], lc[i], uc[i], acc);
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride)
+        cert_col(px[j], paty[j], d2[j], c[j], lv[j], uv[j], acc);
+    write_partials<kCertVals, kCertMax>(acc, red, part);
+}
+
+__global__ void k_cert_final(const double *part, int grid, CertOut *out) {
+    __shared__ double red[kCertVals * (kThreads / 64)];
+    double v[kCertVals] = {0, 0, 0, 0, 0};
+    for (int g = threadIdx.x; g < grid; g += kThreads) {
+        for (int i = 0; i < kCertVals; ++i) {
+            const double p = part[g * kCertVals + i];
+            v[i] = ((kCertMax >> i) & 1u) ? nan_max(v[i], p) : v[i] + p;
+        }
+    }
+    block_reduce<kCertVals, kCertMax>(v, red);
+    if (threadIdx.x == 0) *out = CertOut{v[0], v[1], v[2], v[3], v[4]};
+}
+
+__global__ __launch_bounds__(kThreads) void k_cert_out(int m, int n, const double *px,
+                                                       const double *py, const double *paty,
+                                                       const double *d1, const double *d2,
+                                                       const double *lv, const double *uv,
+                                                       double *x_out, double *y_out,
+                                                       double *r_out) {
+    const int stride = gridDim.x * kThreads;
+    for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
+        x_out[j] = d2[j] * px[j];
+        r_out[j] = proj_rcone(-(paty[j] / d2[j]), lv[j], uv[j]);
+    }
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) y_out[i] = d1[i] * py[i];
+}
+
 // -------------------------------------------------- normalized duality gap
 //
 // mu(z, z_ref) = (1/r) max { L(x, y^) - L(x^, y) : z^ in X x Y, ||z^ - z||_omega <= r },
@@ -1146,6 +1214,38 @@ hipError_t launch_transpose_finish(hipStream_t s, int64_t nnz, int n, const int3
     const int64_t len = nnz > (int64_t)n + 1 ? nnz : (int64_t)n + 1;
     hipLaunchKernelGGL(k_transpose_finish, dim3(grid_for(len, 65535)), dim3(kThreads), 0, s, nnz,
                        n, sorted_cols, perm, rowid, val, t_row_ptr, t_col, t_val);
+    return hipGetLastError();
+}
+
+hipError_t launch_cert_point(hipStream_t s, int m, int n, const double *xa, const double *xb,
+                             const double *ya, const double *yb, const double *lc,
+                             const double *uc, const double *lv, const double *uv, double *px,
+                             double *py) {
+    const int64_t len = std::max(m, n);
+    if (len > 0)
+        hipLaunchKernelGGL(k_cert_point, dim3(grid_for(len)), dim3(kThreads), 0, s, m, n, xa, xb,
+                           ya, yb, lc, uc, lv, uv, px, py);
+    return hipGetLastError();
+}
+
+hipError_t launch_cert(hipStream_t s, int m, int n, const double *px, const double *py,
+                       const double *pax, const double *paty, const double *d1, const double *d2,
+                       const double *c, const double *lc, const double *uc, const double *lv,
+                       const double *uv, double *part, int grid, CertOut *out) {
+    hipLaunchKernelGGL(k_cert, dim3(grid), dim3(kThreads), 0, s, m, n, px, py, pax, paty, d1, d2,
+                       c, lc, uc, lv, uv, part);
+    hipLaunchKernelGGL(k_cert_final, dim3(1), dim3(kThreads), 0, s, part, grid, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cert_out(hipStream_t s, int m, int n, const double *px, const double *py,
+                           const double *paty, const double *d1, const double *d2,
+                           const double *lv, const double *uv, double *x_out, double *y_out,
+                           double *r_out) {
+    const int64_t len = std::max(m, n);
+    if (len > 0)
+        hipLaunchKernelGGL(k_cert_out, dim3(grid_for(len)), dim3(kThreads), 0, s, m, n, px, py,
+                           paty, d1, d2, lv, uv, x_out, y_out, r_out);
     return hipGetLastError();
 }
 

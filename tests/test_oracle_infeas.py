@@ -154,6 +154,9 @@ def test_non_finite_candidates_never_certify():
     lp = make_lp([[1.0]], [-1.0], [2.0], [INF], [0.0], [INF])
     assert not oracle.primal_infeas_test(lp, [np.nan])["ok"]
     assert not oracle.dual_infeas_test(lp, [np.nan])["ok"]
+    # an infinite ray would pass the ratio test as inf <= eps * inf
+    assert not oracle.primal_infeas_test(lp, [INF])["ok"]
+    assert not oracle.dual_infeas_test(lp, [INF])["ok"]
 
 
 # ------------------------------------------------------- Farkas invariants
