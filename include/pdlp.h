@@ -41,7 +41,7 @@ extern "C" {
 #define PDLP_ERR_OUT_OF_MEMORY (-3)
 #define PDLP_ERR_STATE (-4)
 
-/* Solve status (Section 6 outcomes: solved, time limit, numerical error). */
+/* Solve status (Section 7 outcomes: solved, time limit, numerical error). */
 #define PDLP_STATUS_OPTIMAL 0
 #define PDLP_STATUS_ITERATION_LIMIT 1
 #define PDLP_STATUS_TIME_LIMIT 2
@@ -87,7 +87,7 @@ typedef struct pdlp_params {
 
 /* Result of a solve.  x, y, r are caller buffers of length n, m, n (or NULL);
  * they receive the unscaled solution x = D2 x~, y = D1 y~ and the reduced
- * costs used in the termination test.  Residuals follow Section 6, eq.
+ * costs used in the termination test.  Residuals follow Section 7, eq.
  * "rescaled-termination-criteria" (relative) and its l_inf absolute form.
  *
  * Infeasibility (Section 3, "Infeasibility detection"; Appendix D): at every

@@ -20,7 +20,7 @@
  *                                                the primal weights"
  *   - Ruiz + Pock-Chambolle preconditioning ... Section 3, "Diagonal Preconditioning"
  *   - feasibility polishing .................... Algorithm 4 (Section 4)
- *   - termination criteria ..................... Section 6, eq.
+ *   - termination criteria ..................... Section 7, eq.
  *                                                "rescaled-termination-criteria"
  *   - relative gap ............................. Section 4, eq. "relative-gap"
  *   - reduced-cost choice ...................... Section 2 and Appendix A

@@ -391,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void kb_norms(DCsr A, DCsr AT, BatchMaps 
     }
 }
 
-// Termination evaluation per check block (Section 6, original units), for
+// Termination evaluation per check block (Section 7, original units), for
 // the point chosen per instance by sel (0: buffers *0, 1: buffers *1).
 __global__ __launch_bounds__(kThreads) void kb_kkt(DCsr A, DCsr AT, BatchMaps bm,
                                                    const int32_t *mask, const int32_t *sel,

@@ -97,7 +97,7 @@ struct GapState {
     int exact;            // 1 when the root was found on its segment (no cap, no bracket fallback)
 };
 
-// Results of the termination evaluation (Section 6).
+// Results of the termination evaluation (Section 7).
 struct KktOut {
     double primal_obj, dual_obj, rel_gap;
     double primal_res_abs, primal_res_rel, dual_res_abs, dual_res_rel;

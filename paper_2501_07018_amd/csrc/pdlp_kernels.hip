@@ -444,7 +444,7 @@ __global__ __launch_bounds__(kThreads) void k_transpose_finish(int64_t nnz, int 
 
 // ------------------------------------------------- termination evaluation
 //
-// Section 6, eq. "rescaled-termination-criteria", in original units from a
+// Section 7, eq. "rescaled-termination-criteria", in original units from a
 // scaled point: x = D2 x~, y = D1 y~, A x = (A~ x~)/D1, A^T y = (A~^T y~)/D2.
 // Values: 0 primal abs (max), 1 primal rel (max), 2 dual abs (max),
 // 3 dual rel (max), 4 c^T x (sum), 5 dual objective terms (sum),
