@@ -429,7 +429,7 @@ def _row_bounds(rng, ax0, kind):
 
 
 def planted_primal_infeasible(m: int, n: int, per_col: int, seed: int, support: float = 0.1,
-                              margin: float = 1.0, name: str = "") -> LP:
+                              margin: float = 1.0, boxed: bool = False, name: str = "") -> LP:
     """Primal-infeasible LP with a planted Farkas ray (y*, r*).
 
     y* lives on about ``support * m`` rows with the sign each row kind allows
@@ -440,7 +440,8 @@ def planted_primal_infeasible(m: int, n: int, per_col: int, seed: int, support: 
     makes the constraint system inconsistent (Farkas' lemma) while every
     other row keeps its slack around x0.  The objective is c = A^T y_f + r_f
     for a random (y_f in Y, r_f in R), so the dual is feasible (and, the
-    primal being infeasible, unbounded); (y_f, r_f) is kept.
+    primal being infeasible, unbounded); (y_f, r_f) is kept.  ``boxed``
+    makes every variable boxed.
     """
     rng = np.random.default_rng(seed)
     row_ptr, col, val, A = _ray_matrix(rng, m, n, per_col)
@@ -461,6 +462,8 @@ def planted_primal_infeasible(m: int, n: int, per_col: int, seed: int, support: 
     side = np.where(r > 0.0, 1, 2)            # lower-only admits r > 0, upper-only r < 0
     pick = rng.random(n) < 0.5
     vkind = np.where(touched, np.where(pick, 0, side), vkind)
+    if boxed:
+        vkind = np.zeros(n, dtype=vkind.dtype)
     lv, uv = _var_bounds(rng, x0, vkind)
     lc, uc = _row_bounds(rng, A @ x0, rkind)
     r = np.where(touched, r, 0.0)
@@ -527,8 +530,9 @@ def planted_dual_infeasible(m: int, n: int, per_col: int, seed: int, support: fl
 
 
 def infeasible_lp(kind: str, i: int, m: int, n: int, per_col: int = 4) -> LP:
-    """Seeded member ``i`` of the primal- ('primal') or dual- ('dual') infeasible family."""
+    """Seeded member ``i`` of the primal- ('primal'), boxed primal- ('primal_boxed') or
+    dual- ('dual') infeasible family."""
     seed = seed_of(CFG_INFEAS, 2 * i + (kind == "dual"))
-    if kind == "primal":
-        return planted_primal_infeasible(m, n, per_col, seed)
+    if kind in ("primal", "primal_boxed"):
+        return planted_primal_infeasible(m, n, per_col, seed, boxed=kind == "primal_boxed")
     return planted_dual_infeasible(m, n, per_col, seed)

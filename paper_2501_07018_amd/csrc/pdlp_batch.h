@@ -46,6 +46,7 @@ struct pdlp_batch {
     int32_t B = 0;
     std::vector<int32_t> m, n, roff, coff;
     std::vector<double> obj_offset;
+    std::vector<int64_t> ray_cols;    // per instance: variables with an infinite bound
     pdlp_problem *P = nullptr;
     pdlp::host::Arena arena;
     pdlp::BatchMaps bm;

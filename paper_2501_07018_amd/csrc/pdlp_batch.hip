@@ -550,20 +550,31 @@ class BatchSolver {
     struct CertPoint {
         const double *px, *py, *pax, *paty;
     };
-    CertPoint cert_point(int c, const int32_t *mk) {
+    // When no instance of the mask has a variable with an infinite bound
+    // (Xbar = {0}), the x part and its product are skipped: null pointers
+    // read as zeros.
+    CertPoint cert_point(int c, const int32_t *mk, bool xs) {
         const BatchMaps &bm = bm_;
         const Vecs orig{P_->c, P_->lc, P_->uc, P_->lv, P_->uv};
-        HIPCHECK(pdlp::launch_b_cert_point(s(), P_->A, P_->AT, bm, mk, c, W_.it, W_.xb, orig,
-                                           W_.cx, W_.cy));
-        HIPCHECK(pdlp::launch_b_spmv_plain(s(), P_->A, bm.ablk_inst, bm.alist, bm.na, mk, W_.cx,
-                                           W_.cax));
+        double *px = xs ? W_.cx : nullptr, *pax = xs ? W_.cax : nullptr;
+        if (xs || c == 0)
+            HIPCHECK(pdlp::launch_b_cert_point(s(), P_->A, P_->AT, bm, mk, c, W_.it, W_.xb, orig,
+                                               px, W_.cy));
+        if (xs)
+            HIPCHECK(pdlp::launch_b_spmv_plain(s(), P_->A, bm.ablk_inst, bm.alist, bm.na, mk,
+                                               W_.cx, W_.cax));
         if (c == 0) {
             HIPCHECK(pdlp::launch_b_spmv_plain(s(), P_->AT, bm.tblk_inst, bm.tlist, bm.nt, mk,
                                                W_.cy, W_.caty));
-            return {W_.cx, W_.cy, W_.cax, W_.caty};
+            return {px, W_.cy, pax, W_.caty};
         }
-        if (c == 1) return {W_.cx, W_.it.Y[0], W_.cax, W_.it.ATY[0]};
-        return {W_.cx, W_.yb, W_.cax, W_.atyb};
+        if (c == 1) return {px, W_.it.Y[0], pax, W_.it.ATY[0]};
+        return {px, W_.yb, pax, W_.atyb};
+    }
+    bool masked_ray_cols(int mk) {
+        for (int i = 0; i < B(); ++i)
+            if (mask(mk)[i] && b_->ray_cols[i] > 0) return true;
+        return false;
     }
 
     // Appendix D tests on the three candidates of the instances in
@@ -575,8 +586,9 @@ class BatchSolver {
         const int32_t *mk = mask_dev(MASK_INF);
         const Vecs orig{P_->c, P_->lc, P_->uc, P_->lv, P_->uv};
         const size_t nv = pdlp::kCertVals;
+        const bool xs = masked_ray_cols(MASK_INF);
         for (int c = 0; c < 3; ++c) {
-            const CertPoint q = cert_point(c, mk);
+            const CertPoint q = cert_point(c, mk, xs);
             HIPCHECK(pdlp::launch_b_cert(s(), P_->A, P_->AT, bm_, mk, q.px, q.py, q.pax, q.paty,
                                          P_->d1, P_->d2, orig, W_.part_chk,
                                          W_.out_d + (size_t)c * nv * B()));
@@ -795,7 +807,7 @@ class BatchSolver {
             if (!any) continue;
             push_masks();
             const int32_t *mk = mask_dev(MASK_INF);
-            const CertPoint q = cert_point(c, mk);
+            const CertPoint q = cert_point(c, mk, masked_ray_cols(MASK_INF));
             HIPCHECK(pdlp::launch_b_cert_out(s(), P_->A, P_->AT, bm_, mk, q.px, q.py, q.paty,
                                              P_->d1, P_->d2, orig, W_.xo, W_.yo, W_.ro));
         }
@@ -944,6 +956,10 @@ pdlp_batch *pdlp::host::make_batch(int32_t count, const int32_t *m, const int32_
         b->roff = roff;
         b->coff = coff;
         b->obj_offset.assign(count, 0.0);
+        b->ray_cols.assign(count, 0);
+        for (int32_t i = 0; i < count; ++i)
+            for (int64_t j = coff[i]; j < coff[i + 1]; ++j)
+                b->ray_cols[i] += !std::isfinite(lv[j]) || !std::isfinite(uv[j]);
         if (obj_offset)
             for (int32_t i = 0; i < count; ++i) {
                 if (!std::isfinite(obj_offset[i])) invalid("objective offset must be finite");

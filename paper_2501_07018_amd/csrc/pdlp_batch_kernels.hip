@@ -501,6 +501,7 @@ __global__ __launch_bounds__(kThreads) void kb_cert_point(DCsr A, DCsr AT, Batch
         if (cb < 0) continue;
         if (!mask[cb_inst(bm, cb)]) continue;
         if (cb < bm.nT) {
+            if (!px) continue;
             const double *xa = cand == 2 ? xb : it.X[0];
             for (int j = AT.blk[cb] + threadIdx.x; j < AT.blk[cb + 1]; j += kThreads) {
                 const double x = cand == 0 ? xa[j] - it.X[1][j] : xa[j];
@@ -528,11 +529,12 @@ __global__ __launch_bounds__(kThreads) void kb_cert(DCsr A, DCsr AT, BatchMaps b
         double acc[kCertVals] = {0, 0, 0, 0, 0};
         if (cb < bm.nT) {
             for (int j = AT.blk[cb] + threadIdx.x; j < AT.blk[cb + 1]; j += kThreads)
-                cert_col(px[j], paty[j], d2[j], orig.c[j], orig.lv[j], orig.uv[j], acc);
+                cert_col(px ? px[j] : 0.0, paty[j], d2[j], orig.c[j], orig.lv[j], orig.uv[j],
+                         acc);
         } else {
             const int b = cb - bm.nT;
             for (int r = A.blk[b] + threadIdx.x; r < A.blk[b + 1]; r += kThreads)
-                cert_row(py[r], pax[r], d1[r], orig.lc[r], orig.uc[r], acc);
+                cert_row(py[r], pax ? pax[r] : 0.0, d1[r], orig.lc[r], orig.uc[r], acc);
         }
         block_reduce<kCertVals, kCertMax>(acc, red);
         if (threadIdx.x == 0)
@@ -554,7 +556,7 @@ __global__ __launch_bounds__(kThreads) void kb_cert_out(DCsr A, DCsr AT, BatchMa
         if (!mask[cb_inst(bm, cb)]) continue;
         if (cb < bm.nT) {
             for (int j = AT.blk[cb] + threadIdx.x; j < AT.blk[cb + 1]; j += kThreads) {
-                x_out[j] = d2[j] * px[j];
+                x_out[j] = px ? d2[j] * px[j] : 0.0;
                 r_out[j] = proj_rcone(-(paty[j] / d2[j]), orig.lv[j], orig.uv[j]);
             }
         } else {

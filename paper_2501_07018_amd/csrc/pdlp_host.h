@@ -158,6 +158,7 @@ struct pdlp_problem {
     double *zero_n = nullptr;                                            // c = 0 (primal polish)
     double *lc0 = nullptr, *uc0 = nullptr, *lv0 = nullptr, *uv0 = nullptr;  // finite bounds -> 0
     double obj_offset = 0.0;
+    int64_t ray_cols = 0;        // variables with an infinite bound (recession cone Xbar_j != {0})
     double *red_part = nullptr;  // partials of generic reductions
     int red_cap = 0;
     // internal row/column labels: row_order[new] = caller's row, col_order likewise;

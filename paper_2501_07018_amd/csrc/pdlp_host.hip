@@ -471,6 +471,9 @@ struct Engine {
     // update.  The iterate's and the average's y already lie in Y (the dual
     // step and averaging keep it there), so their cached A^T y serve; x needs
     // its projection (boxed coordinates go to 0) and a fresh product.
+    // Without a variable that has an infinite bound, Xbar = {0}: every x
+    // candidate projects to 0 and the dual test cannot pass, so the x part
+    // and its product are skipped (null pointers read as 0).
     const double *cpx = nullptr, *cpy = nullptr, *cpax = nullptr, *cpaty = nullptr;
     void cert_point(int c) {
         if (!cx) {
@@ -482,21 +485,25 @@ struct Engine {
             cert_h = cert_arena.host<pdlp::CertOut>(3);
         }
         const int cur = ctrl_h->cur;
+        const bool xs = P->ray_cols > 0;
         if (c == 0) {
-            HIPCHECK(pdlp::launch_cert_point(s(), m, n, it.X[cur], it.X[cur ^ 1], it.Y[cur],
-                                             it.Y[cur ^ 1], P->lc, P->uc, P->lv, P->uv, cx, cy));
+            HIPCHECK(pdlp::launch_cert_point(s(), m, xs ? n : 0, it.X[cur], it.X[cur ^ 1],
+                                             it.Y[cur], it.Y[cur ^ 1], P->lc, P->uc, P->lv, P->uv,
+                                             cx, cy));
             HIPCHECK(pdlp::launch_spmv_plain(s(), P->AT, cy, caty));
             cpy = cy;
             cpaty = caty;
         } else {
-            HIPCHECK(pdlp::launch_cert_point(s(), 0, n, c == 1 ? it.X[cur] : xb, nullptr, nullptr,
-                                             nullptr, P->lc, P->uc, P->lv, P->uv, cx, nullptr));
+            if (xs)
+                HIPCHECK(pdlp::launch_cert_point(s(), 0, n, c == 1 ? it.X[cur] : xb, nullptr,
+                                                 nullptr, nullptr, P->lc, P->uc, P->lv, P->uv, cx,
+                                                 nullptr));
             cpy = c == 1 ? it.Y[cur] : yb;
             cpaty = c == 1 ? it.ATY[cur] : atyb;
         }
-        HIPCHECK(pdlp::launch_spmv_plain(s(), P->A, cx, cax));
-        cpx = cx;
-        cpax = cax;
+        if (xs) HIPCHECK(pdlp::launch_spmv_plain(s(), P->A, cx, cax));
+        cpx = xs ? cx : nullptr;
+        cpax = xs ? cax : nullptr;
     }
 
     // Appendix D tests of the three candidates: primal infeasibility on each
@@ -944,6 +951,8 @@ pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *r
             for (auto pp : vecs_n) *pp = a.dev<double>(n);
             double **vecs_m[] = {&P->lc, &P->uc, &P->lcs, &P->ucs, &P->d1, &P->lc0, &P->uc0};
             for (auto pp : vecs_m) *pp = a.dev<double>(m);
+            for (int32_t j = 0; j < n; ++j)
+                P->ray_cols += !std::isfinite(lv[j]) || !std::isfinite(uv[j]);
             upload_perm(P, c, n, P->col_order, P->c);
             upload_perm(P, lv, n, P->col_order, P->lv);
             upload_perm(P, uv, n, P->col_order, P->uv);

@@ -216,7 +216,8 @@ hipError_t launch_kkt(hipStream_t s, int m, int n, const double *xs, const doubl
 
 // infeasibility certificates (Appendix D): candidate (xa - xb, ya - yb), or
 // (xa, ya) when xb/yb are null, projected onto Xbar x Y; its test values from
-// the products of the projected point; its unscaled output (x, y, r).
+// the products of the projected point; its unscaled output (x, y, r).  A null
+// px / pax (no variable with an infinite bound) reads as zeros.
 hipError_t launch_cert_point(hipStream_t s, int m, int n, const double *xa, const double *xb,
                              const double *ya, const double *yb, const double *lc,
                              const double *uc, const double *lv, const double *uv, double *px,

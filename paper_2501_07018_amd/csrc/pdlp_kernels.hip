@@ -569,9 +569,9 @@ __global__ __launch_bounds__(kThreads) void k_cert(int m, int n, const double *p
     double acc[kCertVals] = {0, 0, 0, 0, 0};
     const int stride = gridDim.x * kThreads;
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride)
-        cert_row(py[i], pax[i], d1[i], lc[i], uc[i], acc);
+        cert_row(py[i], pax ? pax[i] : 0.0, d1[i], lc[i], uc[i], acc);
     for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride)
-        cert_col(px[j], paty[j], d2[j], c[j], lv[j], uv[j], acc);
+        cert_col(px ? px[j] : 0.0, paty[j], d2[j], c[j], lv[j], uv[j], acc);
     write_partials<kCertVals, kCertMax>(acc, red, part);
 }
 
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_cert_out(int m, int n, const doubl
                                                        double *r_out) {
     const int stride = gridDim.x * kThreads;
     for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
-        x_out[j] = d2[j] * px[j];
+        x_out[j] = px ? d2[j] * px[j] : 0.0;
         r_out[j] = proj_rcone(-(paty[j] / d2[j]), lv[j], uv[j]);
     }
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < m; i += stride) y_out[i] = d1[i] * py[i];

@@ -200,11 +200,12 @@ def test_dual_test_obeys_farkas_bound_on_dual_feasible_lps(seed):
 
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
 def test_planted_rays_are_certificates(seed):
-    lp = lpgen.infeasible_lp("primal", seed, 80, 120, 3)
-    t = oracle.primal_infeas_test(lp, lp.ray_y)
-    assert np.array_equal(t["y"], lp.ray_y)          # already in Y
-    assert t["obj"] == pytest.approx(1.0, rel=1e-12)   # the planted margin
-    assert t["res"] <= 1e-14 and t["ok"]
+    for kind in ("primal", "primal_boxed"):
+        lp = lpgen.infeasible_lp(kind, seed, 80, 120, 3)
+        t = oracle.primal_infeas_test(lp, lp.ray_y)
+        assert np.array_equal(t["y"], lp.ray_y)          # already in Y
+        assert t["obj"] == pytest.approx(1.0, rel=1e-12)   # the planted margin
+        assert t["res"] <= 1e-14 and t["ok"]
     lp = lpgen.infeasible_lp("dual", seed, 80, 120, 3)
     t = oracle.dual_infeas_test(lp, lp.ray_x)
     assert np.array_equal(t["x"], lp.ray_x)
