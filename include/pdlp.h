@@ -83,6 +83,14 @@ typedef struct pdlp_params {
                                  library (cache locality of the gathers); results are unaffected */
     int32_t detect_infeasibility; /* 1 (default): Appendix D tests at every termination check */
     double eps_infeasible;    /* threshold of those tests (1e-9) */
+    /* Algorithm 5 mode (Appendix C), single problems only: with restart_period > 0 every step
+       uses the constant step fixed_step_size (> 0) and primal weight fixed_primal_weight (> 0),
+       and after every restart_period accepted steps the iterate restarts to the plain average
+       of x with y = 0; no adaptive steps or restarts, no primal weight update, no polishing.
+       Termination checks (at check_every) test the average.  Default 0 (off). */
+    int64_t restart_period;
+    double fixed_step_size;
+    double fixed_primal_weight;
 } pdlp_params;
 
 /* Result of a solve.  x, y, r are caller buffers of length n, m, n (or NULL);
@@ -284,7 +292,8 @@ int pdlp_batch_dims(const pdlp_batch *b, int32_t *count, int64_t *m_total, int64
 
 /*
  * Solve every instance from (proj_X(0), 0) with the same params (NULL =
- * defaults; params->polish must be 0, else INVALID_ARGUMENT; max_iters and
+ * defaults; params->polish and params->restart_period must be 0, else
+ * INVALID_ARGUMENT; max_iters and
  * time_limit apply to each instance, the time limit measured from the start
  * of the call).  results: `count` entries, filled as by pdlp_solve (their
  * x, y, r pointers are ignored and set to NULL; seconds is the wall time of
@@ -353,7 +362,8 @@ int pdlp_unroll_set_data(pdlp_unroll *u, const double *c, const double *lc, cons
  * constants, NULL = defaults; tolerances and polishing are not used),
  * recording its decisions and checkpointing the state every ckpt_every
  * steps.  x (sum n) receives x_K in original units, or may be NULL.
- * K >= 0, ckpt_every >= 1.  Errors: STATE on a numerical error. */
+ * K >= 0, ckpt_every >= 1.  Errors: STATE on a numerical error;
+ * INVALID_ARGUMENT for params->restart_period > 0. */
 int pdlp_unroll_forward(pdlp_unroll *u, const pdlp_params *params, int64_t K, int32_t ckpt_every,
                         double *x);
 

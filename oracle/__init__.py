@@ -53,7 +53,8 @@ class _Params(C.Structure):
                 ("reduced_cost_mode", C.c_int32), ("polish", C.c_int32),
                 ("polish_first", C.c_int64), ("fixed_step", C.c_int32),
                 ("fixed_eta", C.c_double), ("adaptive_restarts", C.c_int32),
-                ("detect_infeas", C.c_int32), ("eps_infeas", C.c_double)]
+                ("detect_infeas", C.c_int32), ("eps_infeas", C.c_double),
+                ("restart_period", C.c_int64), ("fixed_omega", C.c_double)]
 
 
 class _State(C.Structure):
@@ -251,6 +252,8 @@ class Params:
     pc: bool = True
     detect_infeasibility: bool = True
     eps_infeas: float = 1e-9
+    restart_period: int = 0        # > 0: Algorithm 5 mode (needs fixed_step, fixed_eta)
+    fixed_omega: float = 1.0
 
     def cstruct(self) -> _Params:
         rc = self.reduced_cost_mode
@@ -261,7 +264,8 @@ class Params:
                        self.theta, self.eps_zero, self.red_exp, self.grow_exp, int(rc),
                        int(bool(self.polish)), int(self.polish_first), int(bool(self.fixed_step)),
                        float(self.fixed_eta), int(bool(self.adaptive_restarts)),
-                       int(bool(self.detect_infeasibility)), float(self.eps_infeas))
+                       int(bool(self.detect_infeasibility)), float(self.eps_infeas),
+                       int(self.restart_period), float(self.fixed_omega))
 
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 3: "NUMERICAL_ERROR", 4: "PRIMAL_INFEASIBLE",

@@ -26,6 +26,8 @@
  *   - reduced-cost choice ...................... Section 2 and Appendix A
  *   - infeasibility detection .................. Section 3, "Infeasibility
  *                                                detection", and Appendix D
+ *   - fixed-frequency restarts ................. Algorithm 5 and Theorem 1
+ *                                                (Appendix C)
  *
  * Readings of points the paper leaves open are listed in the design notes and
  * repeated at the place they apply ("reading: ...").
@@ -925,6 +927,56 @@ static int feasibility_polish(loop_ctx *L, double *out_x, double *out_y, orc_kkt
  * GetRestartCandidate goes to the average; rejected attempts advance no
  * counter of Algorithm 1.
  */
+/*
+ * Check of Algorithm 5 (Appendix C): a constant step (fixed_step) and a
+ * constant primal weight, and after every restart_period steps a restart to
+ * the plain average of x with y reset to 0 (the constant step makes the
+ * step-weighted average of Algorithm 1 the plain average).  No adaptive
+ * restart criteria and no primal weight update.  Readings: the termination
+ * test (at the usual cadence) takes the point a restart would produce,
+ * (x average, 0), as its candidate (for c = 0 this is optimal exactly when x
+ * is feasible: y = 0, r = 0 is dual feasible with the primal objective 0);
+ * the restart follows it at the same k; restarts are counted as (iii).
+ * Returns a status, or -1 to continue.
+ */
+static int fixed_period_check(loop_ctx *L, int full, int per, int capchk, int term_mode,
+                              int detect, double *out_x, double *out_y, orc_kkt *out_kkt,
+                              orc_result *res) {
+    const orc_lp *lp = L->lp;
+    orc_state *st = L->st;
+    int32_t m = lp->m, n = lp->n;
+    if ((full || capchk) && term_mode != TERM_NONE) {
+        orc_kkt kk;
+        memset(L->yc, 0, sizeof(double) * m);
+        orc_kkt_eval(L->u, L->xb, L->yc, L->prm->reduced_cost_mode, L->kx, L->kr, L->katy,
+                     L->ky, L->kax, &kk);
+        memcpy(out_x, L->xb, sizeof(double) * n);
+        memset(out_y, 0, sizeof(double) * m);
+        *out_kkt = kk;
+        if (term_met(L, term_mode, &kk)) return ORC_OK;
+        if (detect) {
+            int inf = infeas_check(L, out_x, out_y, res);
+            if (inf) return inf;
+        }
+        if (capchk) return ORC_LIMIT;
+    }
+    if (!per) return -1;
+    st->restarts_iii += 1;
+    if (L->tape && st->k - 1 < L->tape->cap) L->tape->restart[st->k - 1] = 2;
+    memcpy(st->x, L->xb, sizeof(double) * n);
+    memcpy(st->ax, L->axb, sizeof(double) * m);
+    memset(st->y, 0, sizeof(double) * m);
+    memset(st->aty, 0, sizeof(double) * n);
+    memcpy(st->x0, st->x, sizeof(double) * n);
+    memset(st->y0, 0, sizeof(double) * m);
+    st->n_outer += 1;
+    st->t = 0;
+    st->seta = 0.0;
+    memset(st->sx, 0, sizeof(double) * n);
+    memset(st->sy, 0, sizeof(double) * m);
+    return -1;
+}
+
 static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish,
                      double *out_x, double *out_y, orc_kkt *out_kkt, orc_result *res) {
     const orc_lp *lp = L->lp;
@@ -945,6 +997,8 @@ static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish
         if (st->k >= max_k) return ORC_LIMIT;
     }
     const int detect = term_mode == TERM_FULL && prm->detect_infeas;
+    const int fixed_period = prm->restart_period > 0;
+    if (fixed_period) st->omega = prm->fixed_omega;
     while (st->k < max_k) {
         if (detect) {
             memcpy(L->xprev, st->x, sizeof(double) * n);
@@ -965,13 +1019,20 @@ static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish
         st->k += 1;
 
         int full = (st->k % prm->check_every) == 0;
-        int art = (double)st->t >= prm->beta_art * (double)st->k;
+        int art = !fixed_period && (double)st->t >= prm->beta_art * (double)st->k;
+        int per = fixed_period && st->t >= prm->restart_period;
         int capchk = (term_mode != TERM_NONE) && st->k == max_k;
-        int pol = allow_polish && prm->polish && st->k == next_polish;
-        if (!(full || art || capchk || pol)) continue;
+        int pol = !fixed_period && allow_polish && prm->polish && st->k == next_polish;
+        if (!(full || art || per || capchk || pol)) continue;
 
         compute_average(L);
         if (!all_finite(L->xb, n) || !all_finite(L->yb, m)) return ORC_NUMERR;
+        if (fixed_period) {
+            int rc = fixed_period_check(L, full, per, capchk, term_mode, detect, out_x, out_y,
+                                        out_kkt, res);
+            if (rc >= 0) return rc;
+            continue;
+        }
 
         if (pol) {
             next_polish *= 2;

@@ -44,6 +44,9 @@ typedef struct {
     int32_t adaptive_restarts;     /* 0: only condition (iii) */
     int32_t detect_infeas;         /* Appendix D tests at every termination check */
     double eps_infeas;             /* their threshold (1e-9) */
+    int64_t restart_period;        /* > 0: Algorithm 5 (Appendix C) restarts every that
+                                      many steps; needs fixed_step */
+    double fixed_omega;            /* primal weight held in that mode */
 } orc_params;
 
 /* Iterate state; every array is owned by the caller. */

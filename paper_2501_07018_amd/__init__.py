@@ -45,7 +45,9 @@ class Params(C.Structure):
                 ("beta_nec", C.c_double), ("beta_art", C.c_double), ("theta", C.c_double),
                 ("eps_zero", C.c_double), ("red_exp", C.c_double), ("grow_exp", C.c_double),
                 ("verbose", C.c_int32), ("profile", C.c_int32), ("reorder", C.c_int32),
-                ("detect_infeasibility", C.c_int32), ("eps_infeasible", C.c_double)]
+                ("detect_infeasibility", C.c_int32), ("eps_infeasible", C.c_double),
+                ("restart_period", C.c_int64), ("fixed_step_size", C.c_double),
+                ("fixed_primal_weight", C.c_double)]
 
 
 class Result(C.Structure):

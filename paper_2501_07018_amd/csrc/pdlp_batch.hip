@@ -1029,6 +1029,7 @@ int pdlp_batch_solve(pdlp_batch *b, const pdlp_params *params, pdlp_result *resu
         if (params) prm = *params;
         check_params(prm);
         if (prm.polish) invalid("feasibility polishing is not available for batches");
+        if (prm.restart_period > 0) invalid("the Algorithm 5 mode is not available for batches");
         if (!b->W) b->W = make_work(b);
         BatchSolver solver(b, prm);
         solver.run(results, x, y, r);

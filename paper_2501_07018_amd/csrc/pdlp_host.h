@@ -130,6 +130,14 @@ inline void check_params(const pdlp_params &p) {
     if (!(p.beta_art > 0.0)) invalid("beta_art must be > 0");
     if (p.detect_infeasibility && !(p.eps_infeasible >= 0.0))
         invalid("eps_infeasible must be >= 0");
+    if (p.restart_period < 0) invalid("restart_period must be >= 0");
+    if (p.restart_period > 0) {
+        if (!(p.fixed_step_size > 0.0) || !std::isfinite(p.fixed_step_size))
+            invalid("restart_period > 0 needs a finite fixed_step_size > 0");
+        if (!(p.fixed_primal_weight > 0.0) || !std::isfinite(p.fixed_primal_weight))
+            invalid("restart_period > 0 needs a finite fixed_primal_weight > 0");
+        if (p.polish) invalid("restart_period > 0 excludes polishing");
+    }
 }
 
 // Input checks of a problem (conventions of the C ABI); throws

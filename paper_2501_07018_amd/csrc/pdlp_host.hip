@@ -285,6 +285,7 @@ struct Engine {
     Arena cert_arena;
     double *cx = nullptr, *cy = nullptr, *cax = nullptr, *caty = nullptr;
     pdlp::CertOut *cert_d = nullptr, *cert_h = nullptr;
+    double *zero_m = nullptr;  // y = 0 of the Algorithm 5 termination candidate
     // host-side counters of Algorithm 1
     long long n_outer = 0, kkt_passes = 0, restarts_i = 0, restarts_ii = 0, restarts_iii = 0;
     double mu_ref = INFINITY, mu_c_prev = INFINITY;
@@ -375,6 +376,12 @@ struct Engine {
         c.red_exp = prm.red_exp;
         c.grow_exp = prm.grow_exp;
         c.need_primal = 1;
+        if (prm.restart_period > 0) {
+            // Algorithm 5: constant step and primal weight
+            c.fixed_step = 1;
+            c.fixed_eta = c.eta = c.eta_hat = prm.fixed_step_size;
+            c.omega = prm.fixed_primal_weight;
+        }
         n_outer = 0;
         kkt_passes = 1;
         restarts_i = restarts_ii = restarts_iii = 0;
@@ -658,6 +665,48 @@ bool feasibility_polish(Ctx &X, Engine &E, RunOut &out) {
     return ok;
 }
 
+// Check of Algorithm 5 (Appendix C): the termination test (at the usual
+// cadence) on the point a restart would produce, (x average, 0), then, every
+// restart_period steps, that restart (counted as (iii)); no gap
+// evaluations, no primal weight update.  Returns a RUN_* status, or -1.
+int fixed_period_check(Ctx &X, Engine &E, bool full, bool per, bool capchk, int term_mode,
+                       int rc_mode, RunOut &out) {
+    const pdlp_params &prm = *X.prm;
+    Ctrl &C = *E.ctrl_h;
+    const int m = E.m, n = E.n;
+    if ((full || capchk) && term_mode != TERM_NONE) {
+        if (!E.zero_m) {
+            E.zero_m = E.cert_arena.dev<double>(std::max(m, 1));
+            HIPCHECK(pdlp::launch_fill(E.s(), m, E.zero_m, 0.0));
+        }
+        out.cand = Candidate{E.xb, E.zero_m, E.axb, E.P->zero_n};
+        out.kkt = E.kkt(out.cand.x, out.cand.y, out.cand.ax, out.cand.aty, rc_mode);
+        out.have = true;
+        if (!std::isfinite(out.kkt.rel_gap)) return RUN_NUMERR;
+        if (term_met(prm, term_mode, out.kkt)) return RUN_OK;
+        if (term_mode == TERM_FULL && prm.detect_infeasibility) {
+            const int inf = E.infeasible(prm.eps_infeasible, out.cert_src, out.cert);
+            if (inf) return inf;
+        }
+        if (capchk) return RUN_LIMIT;
+    }
+    if (!per) return -1;
+    E.restarts_iii += 1;
+    hipStream_t s = E.s();
+    HIPCHECK(pdlp::launch_copy(s, n, E.xb, E.X()));
+    HIPCHECK(pdlp::launch_copy(s, m, E.axb, E.AXc()));
+    HIPCHECK(pdlp::launch_fill(s, m, E.Y(), 0.0));
+    HIPCHECK(pdlp::launch_fill(s, n, E.ATYc(), 0.0));
+    HIPCHECK(pdlp::launch_copy(s, n, E.X(), E.x0));
+    HIPCHECK(pdlp::launch_fill(s, m, E.y0, 0.0));
+    E.n_outer += 1;
+    C.t = 0;
+    C.seta = 0.0;
+    HIPCHECK(pdlp::launch_fill(s, n, E.it.sx, 0.0));
+    HIPCHECK(pdlp::launch_fill(s, m, E.it.sy, 0.0));
+    return -1;
+}
+
 // Algorithm 1 with the periodic checks (same readings as the oracle: at
 // n = 0 only (iii); mu_c_prev is the previous evaluation in the outer loop;
 // restart = candidate, then omega update, then mu_ref under the new omega;
@@ -677,10 +726,14 @@ int run_loop(Ctx &X, Engine &E, long long max_k, int term_mode, bool allow_polis
         if (term_met(prm, term_mode, out.kkt)) return RUN_OK;
         if (C.k >= max_k) return RUN_LIMIT;
     }
+    const bool per_mode = prm.restart_period > 0;
     while (C.k < max_k) {
         if (term_mode != TERM_NONE && now_s() - X.t_start >= prm.time_limit) return RUN_TIME;
         long long kb = (C.k / prm.check_every + 1) * prm.check_every;
-        kb = std::min(kb, next_art(C.k, C.t, prm.beta_art, max_k));
+        if (per_mode)
+            kb = std::min(kb, C.k + std::max(1LL, (long long)prm.restart_period - C.t));
+        else
+            kb = std::min(kb, next_art(C.k, C.t, prm.beta_art, max_k));
         kb = std::min(kb, max_k);
         if (allow_polish && prm.polish) kb = std::min(kb, next_polish);
         E.run_block(kb - C.k);
@@ -692,12 +745,18 @@ int run_loop(Ctx &X, Engine &E, long long max_k, int term_mode, bool allow_polis
         } check_timer{E, now_s()};
 
         const bool full = (C.k % prm.check_every) == 0;
-        const bool art = (double)C.t >= prm.beta_art * (double)C.k;
+        const bool art = !per_mode && (double)C.t >= prm.beta_art * (double)C.k;
+        const bool per = per_mode && C.t >= prm.restart_period;
         const bool capchk = term_mode != TERM_NONE && C.k == max_k;
-        const bool pol = allow_polish && prm.polish && C.k == next_polish;
-        if (!(full || art || capchk || pol)) continue;
+        const bool pol = !per_mode && allow_polish && prm.polish && C.k == next_polish;
+        if (!(full || art || per || capchk || pol)) continue;
 
         E.average();
+        if (per_mode) {
+            const int rc = fixed_period_check(X, E, full, per, capchk, term_mode, rc_mode, out);
+            if (rc >= 0) return rc;
+            continue;
+        }
         if (pol) {
             next_polish *= 2;
             KktOut kb_ = E.kkt(E.xb, E.yb, E.axb, E.atyb, 0);
@@ -870,6 +929,9 @@ void pdlp_params_default(pdlp_params *p) {
     p->reorder = 1;
     p->detect_infeasibility = 1;
     p->eps_infeasible = 1e-9;
+    p->restart_period = 0;
+    p->fixed_step_size = 0.0;
+    p->fixed_primal_weight = 1.0;
 }
 
 }  // extern "C"

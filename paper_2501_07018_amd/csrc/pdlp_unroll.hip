@@ -325,6 +325,7 @@ int pdlp_unroll_forward(pdlp_unroll *u, const pdlp_params *params, int64_t K, in
         pdlp_params_default(&prm);
         if (params) prm = *params;
         check_params(prm);
+        if (prm.restart_period > 0) invalid("the Algorithm 5 mode is not available for unrolling");
         const double t0 = now_s();
         const int B = u->b->B;
         const int64_t N = u->N, M = u->M;
