@@ -166,4 +166,5 @@ def test_termination_in_the_mode():
     r = s.solve()
     assert r["status_name"] == "OPTIMAL" and r["iterations"] % 64 == 0
     x, _ = s.solution()
-    assert dist_to_simplices(x, b, 4) <= 1e-9 * 2.0
+    # dist <= ||A x - b||_2 (Hoffman constant >= 1) <= sqrt(m) * 1e-10 * max |b|
+    assert dist_to_simplices(x, b, 4) <= np.sqrt(lp.m) * 1e-10 * np.abs(b).max()
