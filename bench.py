@@ -140,6 +140,61 @@ def batch_section(pd, count, loop_n):
     }
 
 
+def tolerance_sweep_section(pd, grid_L, sample, time_limit):
+    """Feasibility tolerance 1e-8, 1e-10, 1e-12 (primal and dual), relative gap
+    1e-2, with and without feasibility polishing, on the planted 1,000 x 2,000
+    LP, an L x L multicommodity grid (8 commodities, 20 pairs each) and a
+    seeded sample of the batch workload's instances (single solves, and the
+    sample as one batch without polishing)."""
+    import lpgen
+    sizes = lpgen.batch_sizes()
+    work = [("planted_1000x2000", lpgen.small_lp()),
+            (f"grid_{grid_L}x{grid_L}_k8", lpgen.grid_flow_lp(L=grid_L))]
+    members = [lpgen.batch_lp(i, m, n) for i, (m, n) in enumerate(sizes[:sample])]
+    rows = []
+    for eps in (1e-8, 1e-10, 1e-12):
+        for polish in (0, 1):
+            prm = pd.pdlp_params_default(eps_feas=eps, eps_gap=1e-2, polish=polish,
+                                         max_iters=200_000, time_limit=time_limit)
+            for name, lp in work:
+                p = pd.Problem(lp)
+                t0 = time.perf_counter()
+                r = p.solve(prm)
+                dt = time.perf_counter() - t0
+                p.close()
+                rows.append({"workload": name, "eps_feas": eps, "polish": polish,
+                             "status": r["status_name"], "iterations": r["iterations"],
+                             "polish_iters": r["polish_iters"], "seconds": dt,
+                             "primal_res_rel": r["primal_res_rel"],
+                             "dual_res_rel": r["dual_res_rel"], "rel_gap": r["rel_gap"]})
+                log(f"sweep: {rows[-1]}")
+            solved, its, t_all = 0, 0, 0.0
+            for lp in members:
+                p = pd.Problem(lp)
+                t0 = time.perf_counter()
+                r = p.solve(prm)
+                t_all += time.perf_counter() - t0
+                p.close()
+                solved += r["status_name"] == "OPTIMAL"
+                its += r["iterations"] + r["polish_iters"]
+            rows.append({"workload": f"batch_members_x{len(members)}", "eps_feas": eps,
+                         "polish": polish, "solved": solved, "iterations": its,
+                         "seconds": t_all})
+            log(f"sweep: {rows[-1]}")
+        b = pd.Batch(members)
+        prm = pd.pdlp_params_default(eps_feas=eps, eps_gap=1e-2, max_iters=200_000,
+                                     time_limit=time_limit)
+        t0 = time.perf_counter()
+        res = b.solve(prm, want_solution=False)
+        dt = time.perf_counter() - t0
+        b.close()
+        rows.append({"workload": f"batch_of_{len(members)}", "eps_feas": eps, "polish": 0,
+                     "solved": sum(r["status_name"] == "OPTIMAL" for r in res),
+                     "iterations": sum(r["iterations"] for r in res), "seconds": dt})
+        log(f"sweep: {rows[-1]}")
+    return {"rows": rows, "iteration_cap": 200_000, "time_limit_s": time_limit}
+
+
 def unroll_section(pd, count, K):
     """Differentiable layer: `count` planted 2,000 x 4,000 LPs (10 rows per column),
     K unrolled steps with decisions recorded and checkpoints every 25 steps, an
@@ -196,6 +251,11 @@ def main():
     ap.add_argument("--unroll-count", type=int, default=256,
                     help="instances of the differentiable-layer measurement (0 skips it)")
     ap.add_argument("--unroll-k", type=int, default=500)
+    ap.add_argument("--tol-sweep", action="store_true",
+                    help="add the feasibility-tolerance sweep (1e-8/1e-10/1e-12, polishing on/off)")
+    ap.add_argument("--sweep-grid", type=int, default=100, help="grid side L of the sweep")
+    ap.add_argument("--sweep-sample", type=int, default=8, help="batch instances in the sweep")
+    ap.add_argument("--sweep-time-limit", type=float, default=30.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -313,6 +373,9 @@ def main():
         out["batched"] = batch_section(pd, args.batch_count, args.batch_loop)
     if args.unroll_count > 0:
         out["unroll"] = unroll_section(pd, args.unroll_count, args.unroll_k)
+    if args.tol_sweep:
+        out["tolerance_sweep"] = tolerance_sweep_section(pd, args.sweep_grid, args.sweep_sample,
+                                                         args.sweep_time_limit)
     if not args.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(lp, args.cpu_steps)

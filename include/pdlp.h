@@ -94,8 +94,9 @@ typedef struct pdlp_params {
 } pdlp_params;
 
 /* Result of a solve.  x, y, r are caller buffers of length n, m, n (or NULL);
- * they receive the unscaled solution x = D2 x~, y = D1 y~ and the reduced
- * costs used in the termination test.  Residuals follow Section 7, eq.
+ * they receive the unscaled solution x = D2 x~ (clamped to [lv, uv]: the
+ * scaled bounds carry the rounding of the preconditioning, a few ulps),
+ * y = D1 y~ and the reduced costs used in the termination test.  Residuals follow Section 7, eq.
  * "rescaled-termination-criteria" (relative) and its l_inf absolute form.
  *
  * Infeasibility (Section 3, "Infeasibility detection"; Appendix D): at every

@@ -438,9 +438,9 @@ __global__ __launch_bounds__(kThreads) void kb_kkt(DCsr A, DCsr AT, BatchMaps bm
             for (int j = AT.blk[cb] + threadIdx.x; j < AT.blk[cb + 1]; j += kThreads) {
                 const double x = d2[j] * xs[j];
                 const double aty = atys[j] / d2[j];
-                if (x_out) x_out[j] = x;
                 const double g = orig.c[j] - aty;
                 const double l = orig.lv[j], u = orig.uv[j];
+                if (x_out) x_out[j] = clampd(x, l, u);   // see k_kkt
                 double r;
                 if (mode == 0) {
                     if (!isfinite(l) && !isfinite(u)) r = 0.0;

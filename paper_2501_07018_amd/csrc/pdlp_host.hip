@@ -727,6 +727,12 @@ int run_loop(Ctx &X, Engine &E, long long max_k, int term_mode, bool allow_polis
         if (C.k >= max_k) return RUN_LIMIT;
     }
     const bool per_mode = prm.restart_period > 0;
+    if (per_mode) {
+        // Algorithm 5 constants, also over a state imported with other values
+        C.fixed_step = 1;
+        C.fixed_eta = C.eta = C.eta_hat = prm.fixed_step_size;
+        C.omega = prm.fixed_primal_weight;
+    }
     while (C.k < max_k) {
         if (term_mode != TERM_NONE && now_s() - X.t_start >= prm.time_limit) return RUN_TIME;
         long long kb = (C.k / prm.check_every + 1) * prm.check_every;

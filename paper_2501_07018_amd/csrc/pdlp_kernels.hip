@@ -483,9 +483,11 @@ __global__ __launch_bounds__(kThreads) void k_kkt(int m, int n, const double *xs
     for (int j = blockIdx.x * kThreads + threadIdx.x; j < n; j += stride) {
         const double x = d2[j] * xs[j];
         const double aty = atys[j] / d2[j];
-        if (x_out) x_out[j] = x;
         const double g = c[j] - aty;
         const double l = lv[j], u = uv[j];
+        // the scaled bounds carry the rounding of the preconditioning rounds:
+        // the output is clamped to the caller's bounds (a move of a few ulps)
+        if (x_out) x_out[j] = clampd(x, l, u);
         double r;
         if (mode == 0) {
             if (!isfinite(l) && !isfinite(u)) r = 0.0;
