@@ -91,6 +91,15 @@ typedef struct pdlp_params {
     int64_t restart_period;
     double fixed_step_size;
     double fixed_primal_weight;
+    int32_t graphs;           /* 1 (default): step attempts are replayed from HIP graphs captured
+                                 once (per vector set, or per set of running batch instances);
+                                 0: launched one by one.  Results are identical either way. */
+    int32_t stream_block;     /* nonzeros per block of the CSR stream products (problem and batch
+                                 creation): 0 (default) 2048; -1 autotune: time 256, 512, 1024
+                                 and 2048 on the device and keep the fastest, for A and A^T
+                                 separately; else a value in [64, 2048].  Row sums are the same
+                                 whatever the blocks; only the order in which the step norms'
+                                 partial sums combine changes. */
 } pdlp_params;
 
 /* Result of a solve.  x, y, r are caller buffers of length n, m, n (or NULL);

@@ -271,6 +271,11 @@ class BatchSolver {
     std::vector<KktHost> kkt_;
     BatchMaps bm_;       // maps with the lists of the instances launches serve
     int listed_ = -1;    // running instances when the lists were built (-1: all)
+    // Step attempts replayed from graphs once the running set has stayed the
+    // same for two rounds (capturing for sets that change every round costs
+    // more than it saves).
+    pdlp::host::AttemptGraphs graphs_;
+    int rounds_on_lists_ = 0;
 
     // Lists of the instances the launches serve and of their blocks: every
     // instance (all = true) or the running ones.  Rebuilt when that set
@@ -345,6 +350,8 @@ class BatchSolver {
         bm_.tlist = W_.list_d + ot;
         bm_.clist = W_.list_d + oc;
         listed_ = want;
+        graphs_.reset();       // the captured launches carry the old list sizes
+        rounds_on_lists_ = 0;
     }
 
     // Normalized duality gaps of up to three evaluations (slots of gs) for the
@@ -512,13 +519,20 @@ class BatchSolver {
         push_ctrl();
         const BatchMaps &bm = bm_;
         const Vecs v = P_->scaled();
+        auto attempt = [&](hipStream_t st) {
+            HIPCHECK(pdlp::launch_b_attempt(st, P_->A, P_->AT, v, W_.it, W_.ctrl_d, bm,
+                                            W_.part_dual, W_.part_ps, W_.part_pf));
+        };
+        const bool use_graphs = prm_.graphs && ++rounds_on_lists_ > 2;
+        if (use_graphs && !graphs_.ready()) graphs_.capture(attempt);
         while (rem > 0) {
             long long n_att = rem + rem / 8 + 1;
             if (n_att > 4096) n_att = 4096;
             b_->stats.attempt_launches += n_att;
-            for (long long a = 0; a < n_att; ++a)
-                HIPCHECK(pdlp::launch_b_attempt(s(), P_->A, P_->AT, v, W_.it, W_.ctrl_d, bm,
-                                                W_.part_dual, W_.part_ps, W_.part_pf));
+            if (use_graphs)
+                graphs_.launch(s(), n_att);
+            else
+                for (long long a = 0; a < n_att; ++a) attempt(s());
             pull_ctrl();
             rem = 0;
             for (int i = 0; i < B(); ++i) {

@@ -121,6 +121,47 @@ int guarded(F &&f) {
     }
 }
 
+// Replays of a fixed launch sequence from HIP graphs: the sequence of one
+// step attempt is captured for 64, 8 and 1 attempts, and n attempts are
+// enqueued as graph launches of those sizes (greedily), i.e. exactly the
+// launches an eager loop would make.  Capture runs on a private stream
+// (capturing executes nothing); replays go to the caller's stream.
+struct AttemptGraphs {
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+    static constexpr long long kSizes[3] = {64, 8, 1};
+    bool ready() const { return exec[0] != nullptr; }
+    void reset() {
+        for (auto &e : exec)
+            if (e) {
+                (void)hipGraphExecDestroy(e);
+                e = nullptr;
+            }
+    }
+    template <class F>
+    void capture(F &&attempt) {
+        reset();
+        if (!cap) HIPCHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        for (int g = 0; g < 3; ++g) {
+            hipGraph_t graph = nullptr;
+            HIPCHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+            for (long long a = 0; a < kSizes[g]; ++a) attempt(cap);
+            HIPCHECK(hipStreamEndCapture(cap, &graph));
+            const hipError_t e = hipGraphInstantiate(&exec[g], graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPCHECK(e);
+        }
+    }
+    void launch(hipStream_t s, long long n) const {
+        for (int g = 0; g < 3; ++g)
+            for (; n >= kSizes[g]; n -= kSizes[g]) HIPCHECK(hipGraphLaunch(exec[g], s));
+    }
+    ~AttemptGraphs() {
+        reset();
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
 inline void check_params(const pdlp_params &p) {
     if (!(p.check_every >= 1)) invalid("check_every must be >= 1");
     if (p.ruiz_iters < 0) invalid("ruiz_iters must be >= 0");
@@ -131,6 +172,9 @@ inline void check_params(const pdlp_params &p) {
     if (p.detect_infeasibility && !(p.eps_infeasible >= 0.0))
         invalid("eps_infeasible must be >= 0");
     if (p.restart_period < 0) invalid("restart_period must be >= 0");
+    if (p.stream_block != 0 && p.stream_block != -1 &&
+        !(p.stream_block >= 64 && p.stream_block <= pdlp::kStage))
+        invalid("stream_block must be 0, -1 or in [64, 2048]");
     if (p.restart_period > 0) {
         if (!(p.fixed_step_size > 0.0) || !std::isfinite(p.fixed_step_size))
             invalid("restart_period > 0 needs a finite fixed_step_size > 0");
