@@ -1,0 +1,189 @@
+"""Parity at the full sizes of the measured workloads, in the launch
+configuration bench.py times (default parameters: persistent stream grid of
+2,048 workgroups, 2,048-nonzero stream blocks, graphs).
+
+The oracle cannot run these solves, so what it can compute one by one is
+compared directly and the rest is checked through properties that hold at
+any size:
+
+* the 20M x 25M skewed LP and the 300 x 300 multicommodity grid: the whole
+  preconditioning (D1, D2, scaled values and vectors) and both products of
+  the scaled matrix against the oracle's; the first accepted step against
+  its definition (primal projection, case-form dual step on the GPU's own
+  verified products, step-size test of Algorithm 2) recomputed in numpy
+  from the full vectors;
+* the 1,024-instance batch: every returned point checked independently
+  (q-weighted primal residual, dual residual, objective against the
+  planted optimum) at the solve tolerance 1e-6;
+* the 256-instance differentiable layer at K = 500: the replay reproduces
+  the forward bitwise and the adjoint is linear in the upstream gradient.
+"""
+import numpy as np
+import pytest
+
+import lpgen
+import oracle
+import paper_2501_07018_amd as pd
+from tests.test_gpu_parity import rel, say
+
+pytestmark = pytest.mark.gpu
+
+STAGE = 64  # longest row summed sequentially in the oracle's order
+
+
+def _bench_params(**kw):
+    return pd.pdlp_params_default(**kw)
+
+
+def _compare_scaling(g, lp, val, d1, d2):
+    c, lc, uc, lv, uv = oracle.scale_vectors(lp, d1, d2)
+    for name, a, b in [("d1", g["d1"], d1), ("d2", g["d2"], d2), ("val", g["val"], val),
+                       ("c", g["c"], c), ("lc", g["lc"], lc), ("uc", g["uc"], uc),
+                       ("lv", g["lv"], lv), ("uv", g["uv"], uv)]:
+        fin = np.isfinite(b)
+        assert np.array_equal(np.isfinite(a), fin), name
+        assert np.array_equal(a[~fin], b[~fin]), name
+        np.testing.assert_allclose(a[fin], b[fin], rtol=1e-15, atol=0, err_msg=name)
+
+
+def _compare_products(prob, lp, val, seed):
+    """Both scaled products against the oracle's on the oracle's scaled
+    matrix: rows of at most 64 nonzeros bitwise, longer ones to 1e-14 of the
+    row's |A||x|."""
+    rng = np.random.default_rng(seed)
+    x, y = rng.standard_normal(lp.n), rng.standard_normal(lp.m)
+    ax, _ = prob.spmv(x)
+    aty, _ = prob.spmv(y, transpose=True)
+    zn, zm = np.zeros(lp.n), np.zeros(lp.m)
+    view = oracle.LPView(lp.m, lp.n, lp.row_ptr, lp.col, val, zn, zm, zm, zn, zn)
+    ax_o, aty_o = oracle.spmv(view, x), oracle.spmv_t(view, y)
+    rl = np.diff(lp.row_ptr)
+    cl = np.bincount(lp.col, minlength=lp.n)
+    assert np.array_equal(ax[rl <= STAGE], ax_o[rl <= STAGE])
+    assert np.array_equal(aty[cl <= STAGE], aty_o[cl <= STAGE])
+    import scipy.sparse as sp
+    absA = sp.csr_matrix((np.abs(val), lp.col, lp.row_ptr), shape=(lp.m, lp.n))
+    assert np.all(np.abs(ax - ax_o) <= 1e-14 * (absA @ np.abs(x)))
+    assert np.all(np.abs(aty - aty_o) <= 1e-14 * (absA.T @ np.abs(y)))
+
+
+def _dual_case(yhat, sigma, l, u):
+    """Section 2's case form, vectorized (independent of both libraries)."""
+    out = np.zeros_like(yhat)
+    su = np.where(np.isfinite(u), sigma * u, np.inf)
+    sl = np.where(np.isfinite(l), sigma * l, -np.inf)
+    lo = np.isfinite(u) & (yhat < -su)
+    hi = ~lo & np.isfinite(l) & (yhat > -sl)
+    out[lo] = (yhat + su)[lo]
+    out[hi] = (yhat + sl)[hi]
+    return out
+
+
+def _check_first_step(prob, lp, val):
+    """One accepted step from the initial point, against its definition."""
+    st = prob.state(_bench_params())
+    g0 = st.get()
+    info = st.iterate(1)
+    g1 = st.get()
+    sc = prob.scaled()
+    eta, omega = info["last_eta"], g0["omega"]
+    tau, sigma = eta / omega, eta * omega
+    x1 = np.clip(g0["x"] - tau * (sc["c"] - g0["aty"]), sc["lv"], sc["uv"])
+    assert rel(g1["x"], x1) <= 1e-15
+    # the GPU's A x1 (its products were checked against the oracle above)
+    ax1 = prob.spmv(g1["x"])[0]
+    assert rel(g1["ax"], ax1) <= 1e-15
+    y1 = _dual_case(g0["y"] - sigma * (2.0 * ax1 - g0["ax"]), sigma, sc["lc"], sc["uc"])
+    assert rel(g1["y"], y1) <= 1e-14
+    # Algorithm 2: the accepted eta does not exceed eta_bar of that step
+    dx, dy = x1 - g0["x"], y1 - g0["y"]
+    cross = abs(dy @ (ax1 - g0["ax"]))
+    eta_bar = (omega * (dx @ dx) + (dy @ dy) / omega) / (2.0 * cross) if cross > 0 else np.inf
+    assert eta <= eta_bar * (1 + 1e-12)
+    assert info["k"] == 1 and info["attempts"] >= 1
+
+
+@pytest.fixture(scope="module")
+def skewed():
+    say("full size: generating the 20M x 25M skewed LP")
+    lp = lpgen.skewed_lp()
+    say("full size: oracle preconditioning (125M nonzeros)")
+    val, d1, d2 = oracle.precondition(lp, 10, True)
+    return lp, val, d1, d2
+
+
+def test_skewed_full_size_scaling_products_first_step(skewed):
+    lp, val, d1, d2 = skewed
+    say("full size skewed: GPU problem")
+    prob = pd.Problem(lp, _bench_params(eps_feas=1e-8, eps_gap=1e-2, polish=1))
+    _compare_scaling(prob.scaled(), lp, val, d1, d2)
+    say("full size skewed: products")
+    _compare_products(prob, lp, val, 11)
+    say("full size skewed: first step")
+    _check_first_step(prob, lp, val)
+
+
+def test_grid_full_size_scaling_products_first_step():
+    say("full size: 300 x 300 multicommodity grid")
+    lp = lpgen.grid_flow_lp()
+    assert lp.nnz == 8_611_200
+    val, d1, d2 = oracle.precondition(lp, 10, True)
+    prob = pd.Problem(lp, _bench_params())
+    _compare_scaling(prob.scaled(), lp, val, d1, d2)
+    _compare_products(prob, lp, val, 12)
+    _check_first_step(prob, lp, val)
+
+
+def _q(lc, uc):
+    lb = np.isfinite(lc) & (lc != 0.0)
+    ub = np.isfinite(uc) & (uc != 0.0)
+    al = np.where(lb, np.abs(np.where(np.isfinite(lc), lc, 0.0)), 0.0)
+    au = np.where(ub, np.abs(np.where(np.isfinite(uc), uc, 0.0)), 0.0)
+    return np.where(lb | ub, np.maximum(al, au), 1.0)
+
+
+def test_batch_full_workload_points_verified():
+    say("full size: 1,024-instance batch at relative KKT 1e-6")
+    sizes = lpgen.batch_sizes()
+    lps = [lpgen.batch_lp(i, m, n) for i, (m, n) in enumerate(sizes)]
+    assert len(lps) == 1024
+    b = pd.Batch(lps)
+    res = b.solve(pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6, max_iters=200_000))
+    optimal = 0
+    for lp, r in zip(lps, res):
+        assert r["status_name"] in ("OPTIMAL", "ITERATION_LIMIT"), lp.name
+        if r["status_name"] != "OPTIMAL":
+            assert r["iterations"] == 200_000
+            continue
+        optimal += 1
+        A = lp.csr()
+        x, y, rc = r["x"], r["y"], r["r"]
+        assert np.all(x >= lp.lv) and np.all(x <= lp.uv)
+        ax = A @ x
+        viol = np.maximum(np.maximum(np.where(np.isfinite(lp.lc), lp.lc - ax, 0.0),
+                                     np.where(np.isfinite(lp.uc), ax - lp.uc, 0.0)), 0.0)
+        slack = 1e-14 * (abs(A) @ np.abs(x) + 1.0)
+        assert np.all(viol <= 1e-6 * _q(lp.lc, lp.uc) + slack), lp.name
+        res_d = np.abs(lp.c - A.T @ y - rc)
+        assert np.all(res_d <= 1e-6 * np.where(lp.c != 0, np.abs(lp.c), 1.0)
+                      + 1e-14 * (abs(A).T @ np.abs(y) + np.abs(lp.c))), lp.name
+        assert lp.c @ x == pytest.approx(lp.p_star, rel=1e-5), lp.name
+    assert optimal >= 1000
+
+
+def test_unroll_full_config_replay_and_linearity():
+    say("full size: differentiable layer, 256 x 2,000 x 4,000, K = 500")
+    lps = [lpgen.layer_lp(i) for i in range(256)]
+    u = pd.Unroll(lps)
+    x = u.forward(500, 25)
+    xr, sig = u.replay()
+    assert np.array_equal(x, xr)
+    rng = np.random.default_rng(5)
+    g1, g2 = rng.standard_normal(x.size), rng.standard_normal(x.size)
+    b1, b2 = u.backward(g1), u.backward(g2)
+    b12 = u.backward(2.0 * g1 - 3.0 * g2)
+    for key in b1:
+        lin = 2.0 * b1[key] - 3.0 * b2[key]
+        den = np.abs(2.0 * b1[key]) + np.abs(3.0 * b2[key])
+        assert np.all(np.abs(b12[key] - lin) <= 1e-9 * den + 1e-12 * den.max()), key
+    u.close()
