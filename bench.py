@@ -53,7 +53,7 @@ def hot_source_hash():
         text = open(os.path.join(base, fname)).read()
         return text.split(f"// [hot-path {tag} begin]")[1].split(f"// [hot-path {tag} end]")[0]
     parts = (region("pdlp_kernels.hip", "kernels"), region("pdlp_device.h", "device"),
-             region("pdlp_internal.h", "constants"))
+             region("pdlp_internal.h", "constants"), region("pdlp_host.hip", "layout"))
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 

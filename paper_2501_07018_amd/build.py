@@ -15,6 +15,7 @@ FLAGS = [
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    "-pthread",
 ]
 
 

@@ -335,25 +335,43 @@ struct PrimalRow {
     }
 };
 
-// [hot-path device end]
-
-// Epilogue base for a single LP: every block runs, one gathered vector,
-// partial sums accumulate per thread across blocks.
 // Epilogues without operands to prefetch.
 struct NoPrefetch {
     struct Pre {};
     __device__ __forceinline__ Pre prefetch(int) const { return {}; }
 };
 
+// Epilogue base for a single LP: one gathered vector, partial sums
+// accumulate per thread across blocks.  Blocks are dealt to the XCDs in
+// chunks of kXcdChunk consecutive blocks: workgroup w of a launch runs on
+// XCD w mod 8 and, with the persistent grid a multiple of 8, visits loop
+// indices bi = w (mod 8), so each XCD works through whole chunks of
+// neighbouring rows (which, after the library's relabelling, share cache
+// lines of the gathered vector) while the chunks still spread the heavy
+// first rows over all XCDs.  Every block is visited exactly once for any
+// grid (indices past the blocks skip).
+#ifndef PDLP_XCD_CHUNK
+#define PDLP_XCD_CHUNK 64
+#endif
+constexpr int kXcdChunk = PDLP_XCD_CHUNK;
 struct SingleEpi : NoPrefetch {
     const double *gsrc;
-    __device__ __forceinline__ int count(const DCsr &A) const { return A.nblk; }
-    __device__ __forceinline__ int block(int bi) const { return bi; }
-    __device__ __forceinline__ bool begin(int) { return true; }
+    int nblk = 0;
+    __device__ __forceinline__ int count(const DCsr &A) {
+        nblk = A.nblk;
+        constexpr int span = 8 * kXcdChunk;
+        return (A.nblk + span - 1) / span * span;
+    }
+    __device__ __forceinline__ int block(int bi) const {
+        const int x = bi & 7, p = bi >> 3;
+        return ((p / kXcdChunk) * 8 + x) * kXcdChunk + p % kXcdChunk;
+    }
+    __device__ __forceinline__ bool begin(int b) const { return b < nblk; }
     __device__ __forceinline__ const double *src() const { return gsrc; }
     template <int N>
     __device__ __forceinline__ void end(int, double (&)[N], double *) {}
 };
+// [hot-path device end]
 
 // Proximal-path segments of one coordinate for the normalized duality gap
 // (Section 3): D_i(s) = a1 s^2 (s < b1), c (b1 <= s < b2), a3 s^2 (s >= b2);

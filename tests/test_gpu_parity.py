@@ -327,8 +327,11 @@ def test_internal_reordering_is_invisible():
     (g0, s0, r0), (g1, s1, r1) = outs
     for k in ("d1", "d2", "val", "c", "lc", "uc", "lv", "uv"):
         assert np.array_equal(g0[k], g1[k]), k
+    # the labels change only the order in which the step norms' partial sums
+    # combine; such rounding differences grow along the trajectory (the
+    # single path against the oracle: 2e-9 at k = 64, 2e-7 at 150)
     for k in ("x", "y", "x0", "y0"):
-        assert rel(s0[k], s1[k]) <= 1e-10, k
+        assert rel(s0[k], s1[k]) <= 1e-8, k
     # long runs may end at different points of a non-unique optimal face:
     # compare what is unique
     assert r0["status"] == r1["status"]
