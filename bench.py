@@ -31,6 +31,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+GRAPHS = 1   # step attempts replayed from HIP graphs (--no-graphs: eager launches)
+
 METRIC = "PDHG iters/s + SpMV HBM GB/s at 125M nnz; batched LPs/s; bwd/fwd time at KKT tol"
 HBM_PEAK_GBS = 8000.0
 
@@ -40,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel source they were taken on (hash of the hot-path
 # region of the kernels and constants); reported as null otherwise.
 TRAFFIC_RECORD = {
-    "hot_source": "0ae3c435557efd6e",
-    "k_spmv_dual": 12554419091,
-    "k_spmv_primal": 18342510980,
+    "hot_source": "e2108c1d9f1b6671",
+    "k_spmv_dual": 9186985002,
+    "k_spmv_primal": 14235492696,
 }
 
 
@@ -102,7 +104,7 @@ def batch_section(pd, count, loop_n):
     lps = [lpgen.batch_lp(i, m, n) for i, (m, n) in enumerate(sizes)]
     nnz = sum(lp.nnz for lp in lps)
     log(f"batch: generated {count} LPs ({nnz} nonzeros) in {time.perf_counter() - t0:.1f}s")
-    prm = pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6, max_iters=200000)
+    prm = pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6, max_iters=200000, graphs=GRAPHS)
     b = pd.Batch(lps)
     t0 = time.perf_counter()
     res = b.solve(prm, want_solution=False)
@@ -154,7 +156,7 @@ def tolerance_sweep_section(pd, grid_L, sample, time_limit):
     rows = []
     for eps in (1e-8, 1e-10, 1e-12):
         for polish in (0, 1):
-            prm = pd.pdlp_params_default(eps_feas=eps, eps_gap=1e-2, polish=polish,
+            prm = pd.pdlp_params_default(eps_feas=eps, eps_gap=1e-2, polish=polish, graphs=GRAPHS,
                                          max_iters=200_000, time_limit=time_limit)
             for name, lp in work:
                 p = pd.Problem(lp)
@@ -182,7 +184,7 @@ def tolerance_sweep_section(pd, grid_L, sample, time_limit):
                          "seconds": t_all})
             log(f"sweep: {rows[-1]}")
         b = pd.Batch(members)
-        prm = pd.pdlp_params_default(eps_feas=eps, eps_gap=1e-2, max_iters=200_000,
+        prm = pd.pdlp_params_default(eps_feas=eps, eps_gap=1e-2, max_iters=200_000, graphs=GRAPHS,
                                      time_limit=time_limit)
         t0 = time.perf_counter()
         res = b.solve(prm, want_solution=False)
@@ -207,11 +209,12 @@ def unroll_section(pd, count, K):
     log(f"unroll: generated {count} LPs in {time.perf_counter() - t0:.1f}s")
     u = pd.Unroll(lps)
     gx = np.random.default_rng(2501).standard_normal(u.N)
-    u.forward(K, 25)          # warm-up pair (first-touch allocation of the work buffers)
+    # warm-up pair (first-touch allocation of the work buffers)
+    u.forward(K, 25, pd.pdlp_params_default(graphs=GRAPHS))
     u.backward(gx)
     fw, bw, rp = [], [], []
     for _ in range(3):
-        u.forward(K, 25)
+        u.forward(K, 25, pd.pdlp_params_default(graphs=GRAPHS))
         u.backward(gx)
         u.replay()
         st = u.stats()
@@ -251,12 +254,16 @@ def main():
     ap.add_argument("--unroll-count", type=int, default=256,
                     help="instances of the differentiable-layer measurement (0 skips it)")
     ap.add_argument("--unroll-k", type=int, default=500)
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch step attempts one by one (same results; for tracing tools)")
     ap.add_argument("--tol-sweep", action="store_true",
                     help="add the feasibility-tolerance sweep (1e-8/1e-10/1e-12, polishing on/off)")
     ap.add_argument("--sweep-grid", type=int, default=100, help="grid side L of the sweep")
     ap.add_argument("--sweep-sample", type=int, default=8, help="batch instances in the sweep")
     ap.add_argument("--sweep-time-limit", type=float, default=30.0)
     args = ap.parse_args()
+    global GRAPHS
+    GRAPHS = 0 if args.no_graphs else 1
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
