@@ -204,9 +204,11 @@ std::vector<int32_t> order_rows(const std::vector<int32_t> &rlen, const int32_t 
 
 // Column labels: decreasing degree (hot columns first, and at low labels,
 // where the rows' keys above look); inside a class of equal degree, by the
-// smallest new label of the column's rows, so that the columns of a row --
-// most of them of degree 1 or 2 -- sit next to each other and a row of A
-// gathers from fewer cache lines of x.
+// smallest new label of the column's rows.  The cold columns (degree at most
+// kColdDeg, most of them of degree 1 or 2) form one class, ordered by that
+// first row alone, so that all cold columns of a row sit next to each other
+// and a row of A gathers them from one run of cache lines of x.
+constexpr int32_t kColdDeg = 8;
 std::vector<int32_t> order_cols(const std::vector<int32_t> &cdeg, const int32_t *rp,
                                 const int32_t *col, int32_t m,
                                 const std::vector<int32_t> &new_row, bool reorder) {
@@ -220,7 +222,10 @@ std::vector<int32_t> order_cols(const std::vector<int32_t> &cdeg, const int32_t 
     while (lo < n) {
         int32_t hi = lo;
         const int32_t d = cdeg[order[lo]];
-        while (hi < n && cdeg[order[hi]] == d) ++hi;
+        if (d <= kColdDeg)
+            hi = n;   // degrees decrease along order: the rest are all cold
+        else
+            while (hi < n && cdeg[order[hi]] == d) ++hi;
         if (hi - lo > 1) {
             std::vector<std::pair<int32_t, int32_t>> kv((size_t)(hi - lo));
             for (int32_t q = lo; q < hi; ++q) kv[(size_t)(q - lo)] = {first[order[q]], order[q]};
@@ -1166,7 +1171,8 @@ pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *r
             for (int32_t i = 0; i < m; ++i) rlen[i] = row_ptr[i + 1] - row_ptr[i];
             for (int64_t e = 0; e < nnz; ++e) cdeg[col[e]] += 1;
             // one round of co-clustering: columns by degree, rows by their hottest
-            // columns, columns within a degree by their first row, rows again
+            // columns, columns within a degree (the cold ones as one class) by
+            // their first row, rows again
             const bool ro = prm.reorder != 0;
             std::vector<int32_t> col_order = order_by_count(cdeg, ro);
             std::vector<int32_t> new_row(m), new_col(n), new_rp((size_t)m + 1);
