@@ -245,7 +245,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--m", type=int, default=20_000_000)
     ap.add_argument("--n", type=int, default=25_000_000)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-count", type=int, default=1024,
                     help="instances of the batched-solver measurement (0 skips it)")
