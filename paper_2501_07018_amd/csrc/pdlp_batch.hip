@@ -525,6 +525,11 @@ class BatchSolver {
         };
         const bool use_graphs = prm_.graphs && ++rounds_on_lists_ > 2;
         if (use_graphs && !graphs_.ready()) graphs_.capture(attempt);
+        // primal candidates of the first attempt (later ones come from the products)
+        HIPCHECK(pdlp::launch_b_primal(s(), P_->AT, v, W_.it, W_.ctrl_d, bm,
+                                       W_.part_ps));
+        long long tried = 0;
+        for (int i = 0; i < B(); ++i) tried += W_.ctrl_h[i].attempts;
         while (rem > 0) {
             long long n_att = rem + rem / 8 + 1;
             if (n_att > 4096) n_att = 4096;
@@ -535,10 +540,16 @@ class BatchSolver {
                 for (long long a = 0; a < n_att; ++a) attempt(s());
             pull_ctrl();
             rem = 0;
+            long long now = 0;
             for (int i = 0; i < B(); ++i) {
                 const Ctrl &c = W_.ctrl_h[i];
+                now += c.attempts;
                 if (inst_[i].status < 0 && !c.stop) rem = std::max(rem, c.block_target - c.block_acc);
             }
+            // every launched attempt decides each running instance once
+            if (rem > 0 && now == tried)
+                throw LibError(PDLP_ERR_STATE, "batched step attempts made no decision");
+            tried = now;
             if (rem == 0) {
                 // instances still running with nothing left cannot exist: stop is set
                 // exactly when block_acc reaches the target

@@ -24,6 +24,33 @@ __device__ __forceinline__ int cb_inst(const BatchMaps &bm, int cb) {
 }
 
 // ---------------------------------------------------------- step attempt
+//
+// An attempt is three launches: the dual product, the Algorithm 2 decision
+// (kb_decide), and the primal product, which for an instance whose attempt
+// was rejected recomputes the primal candidate with the reduced step
+// instead.  The primal candidate of the first attempt of a round comes from
+// kb_primal.
+
+// Primal candidate x' = proj_X(x - tau (c - A^T y)) on the columns of A^T
+// block b, with the block's partial sum of |x' - x|^2.
+__device__ __forceinline__ void primal_block(const DCsr &AT, const Vecs &v, const Iter &it,
+                                             const Ctrl &c, int b, double *red, double *part) {
+    // buffers chosen by select, not by indexing (keeps Iter out of scratch)
+    const bool one = c.cur != 0;
+    const double tau = c.eta / c.omega;
+    const double *x = one ? it.X[1] : it.X[0], *aty = one ? it.ATY[1] : it.ATY[0];
+    double *xn = one ? it.X[0] : it.X[1];
+    double acc[1] = {0.0};
+    for (int j = AT.blk[b] + threadIdx.x; j < AT.blk[b + 1]; j += kThreads) {
+        const double xj = x[j];
+        const double xv = clampd(xj - tau * (v.c[j] - aty[j]), v.lv[j], v.uv[j]);
+        xn[j] = xv;
+        const double d = xv - xj;
+        acc[0] += d * d;
+    }
+    block_reduce<1>(acc, red);
+    if (threadIdx.x == 0) part[b] = acc[0];
+}
 
 __global__ __launch_bounds__(kThreads) void kb_primal(DCsr AT, Vecs v, Iter it, const Ctrl *ctrl,
                                                       BatchMaps bm, double *part) {
@@ -33,21 +60,73 @@ __global__ __launch_bounds__(kThreads) void kb_primal(DCsr AT, Vecs v, Iter it, 
         if (b < 0) continue;  // padding of the per-XCD interleave
         const Ctrl &c = ctrl[bm.tblk_inst[b]];
         if (c.stop || !c.need_primal) continue;
-        const int cur = c.cur;
-        const double tau = c.eta / c.omega;
-        const double *x = it.X[cur], *aty = it.ATY[cur];
-        double *xn = it.X[cur ^ 1];
-        double acc[1] = {0.0};
-        for (int j = AT.blk[b] + threadIdx.x; j < AT.blk[b + 1]; j += kThreads) {
-            const double xj = x[j];
-            const double xv = clampd(xj - tau * (v.c[j] - aty[j]), v.lv[j], v.uv[j]);
-            xn[j] = xv;
-            const double d = xv - xj;
-            acc[0] += d * d;
-        }
-        block_reduce<1>(acc, red);
-        if (threadIdx.x == 0) part[b] = acc[0];
+        primal_block(AT, v, it, c, b, red, part);
     }
+}
+
+// Algorithm 2 decision of running instance i by one wave: the step norms
+// and the interaction term are summed from the per-block partials in a
+// fixed order (lane-strided, then the wave butterfly); lane 0 updates the
+// control block.
+__device__ __forceinline__ void decide_instance(Ctrl *ctrl, const BatchMaps &bm, int i,
+                                                const double *pd, const double *pps,
+                                                const double *ppf) {
+    const int lane = threadIdx.x & 63;
+    const Ctrl c0 = ctrl[i];
+    const double *pp = c0.need_primal ? pps : ppf;
+    double dx2 = 0.0, dy2 = 0.0, cr = 0.0;
+    for (int b = bm.tblk_off[i] + lane; b < bm.tblk_off[i + 1]; b += 64) dx2 += pp[b];
+    for (int b = bm.ablk_off[i] + lane; b < bm.ablk_off[i + 1]; b += 64) {
+        dy2 += pd[2 * b];
+        cr += pd[2 * b + 1];
+    }
+    dx2 = wave_sum(dx2);
+    dy2 = wave_sum(dy2);
+    cr = wave_sum(cr);
+    if (lane != 0) return;
+    Ctrl c = c0;
+    const double eta = c.eta, omega = c.omega;
+    const double num = omega * dx2 + dy2 / omega;
+    const double den = 2.0 * fabs(cr);
+    c.attempts += 1;
+    if (!isfinite(num) || !isfinite(den)) {
+        c.numerr = 1;
+        c.stop = 1;
+        c.run_at = 0;
+        ctrl[i] = c;
+        return;
+    }
+    const double eta_bar = den > 0.0 ? num / den : INFINITY;
+    const double jj = (double)(c.attempts + 1);
+    const double e1 = (1.0 - pow(jj, -c.red_exp)) * eta_bar;
+    const double e2 = (1.0 + pow(jj, -c.grow_exp)) * eta;
+    const double eta_next = e1 < e2 ? e1 : e2;
+    c.last_eta_bar = eta_bar;
+    if (c.fixed_step || eta <= eta_bar) {
+        if (bm.tape_eta && c.k < bm.tape_K) {
+            bm.tape_eta[(size_t)i * bm.tape_K + c.k] = eta;
+            bm.tape_omega[(size_t)i * bm.tape_K + c.k] = omega;
+        }
+        c.cur ^= 1;
+        c.k += 1;
+        c.t += 1;
+        c.block_acc += 1;
+        c.seta += eta;
+        c.eta_used = eta;
+        c.eta_avg_y = eta;
+        c.pending_sy = 1;
+        c.eta_hat = c.fixed_step ? c.fixed_eta : eta_next;
+        c.eta = c.eta_hat;
+        c.stop = c.block_acc >= c.block_target;
+        c.need_primal = c.stop;
+        c.run_at = 1;
+    } else {
+        c.eta = eta_next;
+        c.need_primal = 1;
+        c.run_at = 0;
+        c.pending_sy = 0;
+    }
+    ctrl[i] = c;
 }
 
 struct BatchDualEpi : NoPrefetch {
@@ -104,9 +183,11 @@ PDLP_STREAM_KERNEL void kb_spmv_dual(DCsr A, Vecs v, Iter it, const Ctrl *ctrl,
 struct BatchPrimalEpi : NoPrefetch {
     const Ctrl *ctrl;
     BatchMaps bm;
+    DCsr AT;
     Iter it;
     Vecs v;
-    double *part;
+    double *part, *pps;
+    double *red;
     const double *gsrc;
     PrimalRow row;
     __device__ __forceinline__ int count(const DCsr &) const { return bm.nt; }
@@ -114,7 +195,11 @@ struct BatchPrimalEpi : NoPrefetch {
     __device__ __forceinline__ bool begin(int b) {
         if (b < 0) return false;
         const Ctrl &c = ctrl[bm.tblk_inst[b]];
-        if (!c.run_at) return false;
+        if (!c.run_at) {
+            // rejected attempt: the next candidate with the reduced step
+            if (!c.stop && c.need_primal) primal_block(AT, v, it, c, b, red, pps);
+            return false;
+        }
         const bool one = c.cur != 0;
         gsrc = one ? it.Y[1] : it.Y[0];
         row = PrimalRow{one ? it.X[1] : it.X[0], v.c, v.lv, v.uv, one ? it.ATY[1] : it.ATY[0],
@@ -134,87 +219,35 @@ struct BatchPrimalEpi : NoPrefetch {
     }
 };
 
-PDLP_STREAM_KERNEL void kb_spmv_primal(DCsr AT, Vecs v, Iter it,
-                                                           const Ctrl *ctrl, BatchMaps bm,
-                                                           double *part) {
+PDLP_STREAM_KERNEL void kb_spmv_primal(DCsr AT, Vecs v, Iter it, const Ctrl *ctrl,
+                                       BatchMaps bm, double *part, double *pps) {
     __shared__ double prod[kStage];
     __shared__ double red[kThreads / 64];
     BatchPrimalEpi epi;
     epi.ctrl = ctrl;
     epi.bm = bm;
+    epi.AT = AT;
     epi.it = it;
     epi.v = v;
     epi.part = part;
+    epi.pps = pps;
+    epi.red = red;
     double acc[1] = {0.0};
     stream_spmv<1>(AT, epi, acc, prod, red);
 }
 
-// Algorithm 2 decision, one wave per instance.
+// Algorithm 2 decision, one wave per listed instance.
 __global__ __launch_bounds__(kThreads) void kb_decide(Ctrl *ctrl, BatchMaps bm, const double *pd,
                                                       const double *pps, const double *ppf) {
     const int lane = threadIdx.x & 63;
     const int ii = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
     if (ii >= bm.ni) return;
     const int i = bm.ilist[ii];
-    const Ctrl c0 = ctrl[i];
-    if (c0.stop) {
+    if (ctrl[i].stop) {
         if (lane == 0) ctrl[i].run_at = 0;
         return;
     }
-    const double *pp = c0.need_primal ? pps : ppf;
-    double dx2 = 0.0, dy2 = 0.0, cr = 0.0;
-    for (int b = bm.tblk_off[i] + lane; b < bm.tblk_off[i + 1]; b += 64) dx2 += pp[b];
-    for (int b = bm.ablk_off[i] + lane; b < bm.ablk_off[i + 1]; b += 64) {
-        dy2 += pd[2 * b];
-        cr += pd[2 * b + 1];
-    }
-    dx2 = wave_sum(dx2);
-    dy2 = wave_sum(dy2);
-    cr = wave_sum(cr);
-    if (lane != 0) return;
-    Ctrl c = c0;
-    const double eta = c.eta, omega = c.omega;
-    const double num = omega * dx2 + dy2 / omega;
-    const double den = 2.0 * fabs(cr);
-    c.attempts += 1;
-    if (!isfinite(num) || !isfinite(den)) {
-        c.numerr = 1;
-        c.stop = 1;
-        c.run_at = 0;
-        ctrl[i] = c;
-        return;
-    }
-    const double eta_bar = den > 0.0 ? num / den : INFINITY;
-    const double jj = (double)(c.attempts + 1);
-    const double e1 = (1.0 - pow(jj, -c.red_exp)) * eta_bar;
-    const double e2 = (1.0 + pow(jj, -c.grow_exp)) * eta;
-    const double eta_next = e1 < e2 ? e1 : e2;
-    c.last_eta_bar = eta_bar;
-    if (c.fixed_step || eta <= eta_bar) {
-        if (bm.tape_eta && c.k < bm.tape_K) {
-            bm.tape_eta[(size_t)i * bm.tape_K + c.k] = eta;
-            bm.tape_omega[(size_t)i * bm.tape_K + c.k] = omega;
-        }
-        c.cur ^= 1;
-        c.k += 1;
-        c.t += 1;
-        c.block_acc += 1;
-        c.seta += eta;
-        c.eta_used = eta;
-        c.eta_avg_y = eta;
-        c.pending_sy = 1;
-        c.eta_hat = c.fixed_step ? c.fixed_eta : eta_next;
-        c.eta = c.eta_hat;
-        c.stop = c.block_acc >= c.block_target;
-        c.need_primal = c.stop;
-        c.run_at = 1;
-    } else {
-        c.eta = eta_next;
-        c.need_primal = 1;
-        c.run_at = 0;
-        c.pending_sy = 0;
-    }
-    ctrl[i] = c;
+    decide_instance(ctrl, bm, i, pd, pps, ppf);
 }
 
 // Dual average owed by the last accepted step, then the current iterate is
@@ -807,13 +840,18 @@ static inline int list_grid(int n, int cap) { return n < cap ? (n > 0 ? n : 1) :
 constexpr int kBatchGridCap = 4096;   // elementwise / check kernels
 constexpr int kBatchSpmvCap = 2048;   // persistent CSR stream kernels (8 per CU)
 
+hipError_t launch_b_primal(hipStream_t s, const DCsr &AT, Vecs v, Iter it, const Ctrl *ctrl,
+                           const BatchMaps &bm, double *pps) {
+    if (bm.nt > 0)
+        hipLaunchKernelGGL(kb_primal, dim3(list_grid(bm.nt, kBatchGridCap)), dim3(kThreads), 0, s,
+                           AT, v, it, ctrl, bm, pps);
+    return hipGetLastError();
+}
+
 hipError_t launch_b_attempt(hipStream_t s, const DCsr &A, const DCsr &AT, Vecs v, Iter it,
                             Ctrl *ctrl, const BatchMaps &bm, double *pd, double *pps,
                             double *ppf) {
     if (bm.ni == 0) return hipSuccess;
-    if (bm.nt > 0)
-        hipLaunchKernelGGL(kb_primal, dim3(list_grid(bm.nt, kBatchGridCap)), dim3(kThreads), 0, s,
-                           AT, v, it, ctrl, bm, pps);
     if (bm.na > 0)
         hipLaunchKernelGGL(kb_spmv_dual, dim3(list_grid(bm.na, kBatchSpmvCap)), dim3(kThreads), 0,
                            s, A, v, it, ctrl, bm, pd);
@@ -821,7 +859,7 @@ hipError_t launch_b_attempt(hipStream_t s, const DCsr &A, const DCsr &AT, Vecs v
                        ppf);
     if (bm.nt > 0)
         hipLaunchKernelGGL(kb_spmv_primal, dim3(list_grid(bm.nt, kBatchSpmvCap)), dim3(kThreads), 0,
-                           s, AT, v, it, ctrl, bm, ppf);
+                           s, AT, v, it, ctrl, bm, ppf, pps);
     return hipGetLastError();
 }
 

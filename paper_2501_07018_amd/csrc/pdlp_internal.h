@@ -243,6 +243,12 @@ hipError_t launch_rate_gather(hipStream_t s, int64_t n, const uint32_t *idx, con
                               double *out, int grid);
 
 // batched solver (one control block per instance; per-block partial sums)
+// primal candidates of the first attempt of a round (instances with need_primal)
+hipError_t launch_b_primal(hipStream_t s, const DCsr &AT, Vecs v, Iter it, const Ctrl *ctrl,
+                           const BatchMaps &bm, double *pps);
+// one step attempt of every listed running instance: dual product, step
+// decision, then the primal product (or the primal candidate again after a
+// rejection)
 hipError_t launch_b_attempt(hipStream_t s, const DCsr &A, const DCsr &AT, Vecs v, Iter it,
                             Ctrl *ctrl, const BatchMaps &bm, double *pd, double *pps,
                             double *ppf);
