@@ -164,3 +164,37 @@ def test_batch_limits_and_rejections():
     with pytest.raises(pd.PdlpError) as ei:
         b.solve(pd.pdlp_params_default(polish=1))
     assert ei.value.code == pd.PDLP_ERR_INVALID_ARGUMENT
+
+
+def _box_lp(seed, n):
+    """No rows: min c^T x over the box [-1, 2]^n, solved by the bound that
+    the sign of each c_j picks (any point of the box where c_j = 0)."""
+    rng = np.random.default_rng(seed)
+    c = np.round(rng.standard_normal(n), 3)
+    c[0] = 0.0
+    return lpgen.LP(0, n, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0), c,
+                    np.zeros(0), np.zeros(0), -np.ones(n), 2 * np.ones(n))
+
+
+def test_batch_with_rowless_instances():
+    """Instances without rows have no dual product in a step attempt; they
+    share the batch with ordinary instances and every one reaches its
+    optimum (closed form for the boxes, planted for the others)."""
+    say("batch with rowless instances")
+    lps = [_box_lp(1, 30), lpgen.planted_uniform(150, 225, 8, seed=101), _box_lp(2, 5),
+           lpgen.planted_uniform(433, 650, 8, seed=105)]
+    res = pd.Batch(lps).solve(pd.pdlp_params_default(eps_feas=1e-8, eps_gap=1e-8,
+                                                     max_iters=20000))
+    for i, (lp, r) in enumerate(zip(lps, res)):
+        assert r["status_name"] == "OPTIMAL", i
+        assert np.all(r["x"] >= lp.lv) and np.all(r["x"] <= lp.uv), i
+        if lp.m == 0:
+            star = np.where(lp.c > 0, lp.lv, np.where(lp.c < 0, lp.uv, 0.0))
+            assert r["primal_obj"] == pytest.approx(lp.c @ star, rel=1e-9, abs=1e-12), i
+            assert r["y"].size == 0
+        else:
+            assert r["primal_obj"] == pytest.approx(lp.p_star, rel=1e-6), i
+    # an all-rowless batch has no dual product at all
+    res = pd.Batch([_box_lp(3, 7), _box_lp(4, 11)]).solve(pd.pdlp_params_default())
+    for r in res:
+        assert r["status_name"] == "OPTIMAL"
