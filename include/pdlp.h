@@ -178,6 +178,21 @@ int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
                         const double *uv_host, double obj_offset, const pdlp_params *params,
                         void *hip_stream, pdlp_problem **out);
 
+/*
+ * Same as pdlp_problem_create, with every array in GPU memory (for instance
+ * the storage of torch tensors on the device; host memory is accepted too).
+ * Validation and the internal row/column labelling run on the host, so the
+ * arrays are first copied to the host on hip_stream, after the work already
+ * queued there; the caller keeps ownership and may free them when the call
+ * returns.  Errors as for pdlp_problem_create; HIP_ERROR for a pointer the
+ * runtime cannot copy from.
+ */
+int pdlp_problem_create_device(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr_dev,
+                               const int32_t *col_dev, const double *val_dev, const double *c_dev,
+                               const double *lc_dev, const double *uc_dev, const double *lv_dev,
+                               const double *uv_dev, double obj_offset, const pdlp_params *params,
+                               void *hip_stream, pdlp_problem **out);
+
 void pdlp_problem_destroy(pdlp_problem *p);
 
 /* Sizes of a created problem. */

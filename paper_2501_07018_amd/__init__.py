@@ -112,7 +112,8 @@ class StateBlob(C.Structure):
 
 _lib = None
 
-EXPORTS = ("pdlp_problem_create", "pdlp_problem_destroy", "pdlp_problem_dims",
+EXPORTS = ("pdlp_problem_create", "pdlp_problem_create_device", "pdlp_problem_destroy",
+           "pdlp_problem_dims",
            "pdlp_problem_get_scaled", "pdlp_spmv", "pdlp_params_default", "pdlp_solve",
            "pdlp_state_create", "pdlp_state_destroy", "pdlp_iterate_k", "pdlp_state_get",
            "pdlp_state_set", "pdlp_norm_gap", "pdlp_last_error", "pdlp_state_solve",
@@ -135,6 +136,8 @@ def lib() -> C.CDLL:
     vp = C.c_void_p
     L.pdlp_problem_create.argtypes = [C.c_int32, C.c_int32, C.c_int64, I32, I32, D, D, D, D, D, D,
                                       C.c_double, C.POINTER(Params), vp, C.POINTER(vp)]
+    L.pdlp_problem_create_device.argtypes = [C.c_int32, C.c_int32, C.c_int64] + [vp] * 8 + \
+        [C.c_double, C.POINTER(Params), vp, C.POINTER(vp)]
     L.pdlp_problem_destroy.argtypes = [vp]
     L.pdlp_problem_destroy.restype = None
     L.pdlp_problem_dims.argtypes = [vp, I32, I32, C.POINTER(C.c_int64)]
@@ -214,6 +217,19 @@ def pdlp_problem_create(m, n, row_ptr, col, val, c, lc, uc, lv, uv, obj_offset=0
                                    *[_d(a) for a in arrs], float(obj_offset),
                                    C.byref(params) if params is not None else None,
                                    stream, C.byref(h))
+    _check(rc)
+    return h
+
+
+def pdlp_problem_create_device(m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, obj_offset=0.0,
+                               params: Params | None = None, stream=None):
+    """Device-memory variant: each array argument is the integer address of
+    int32 (row_ptr, col) or float64 (the others) storage in GPU memory."""
+    h = C.c_void_p()
+    ptrs = [C.c_void_p(int(a)) for a in (row_ptr, col, val, c, lc, uc, lv, uv)]
+    rc = lib().pdlp_problem_create_device(int(m), int(n), int(nnz), *ptrs, float(obj_offset),
+                                          C.byref(params) if params is not None else None,
+                                          stream, C.byref(h))
     _check(rc)
     return h
 
@@ -521,6 +537,26 @@ class Problem:
         self.m, self.n = int(lp.m), int(lp.n)
         self.h = pdlp_problem_create(lp.m, lp.n, lp.row_ptr, lp.col, lp.val, lp.c, lp.lc, lp.uc,
                                      lp.lv, lp.uv, getattr(lp, "obj_offset", 0.0), params, stream)
+
+    @classmethod
+    def from_tensors(cls, m, n, row_ptr, col, val, c, lc, uc, lv, uv, obj_offset=0.0,
+                     params: Params | None = None) -> "Problem":
+        """Create from torch tensors in GPU memory (int32 row_ptr/col, float64
+        others, contiguous), read on the current torch stream."""
+        import torch
+        ts = (row_ptr, col, val, c, lc, uc, lv, uv)
+        for i, t in enumerate(ts):
+            want = torch.int32 if i < 2 else torch.float64
+            if t.dtype != want or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("tensors must be contiguous CUDA tensors: int32 row_ptr and "
+                                 "col, float64 val, c, lc, uc, lv, uv")
+        self = cls.__new__(cls)
+        self.m, self.n = int(m), int(n)
+        self.h = None
+        self.h = pdlp_problem_create_device(
+            m, n, col.numel(), *[t.data_ptr() for t in ts], obj_offset, params,
+            C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        return self
 
     def close(self):
         if self.h:

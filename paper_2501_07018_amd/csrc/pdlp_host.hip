@@ -1283,6 +1283,42 @@ int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
     });
 }
 
+int pdlp_problem_create_device(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                               const int32_t *col, const double *val, const double *c,
+                               const double *lc, const double *uc, const double *lv,
+                               const double *uv, double obj_offset, const pdlp_params *params,
+                               void *hip_stream, pdlp_problem **out) {
+    return guarded([&] {
+        if (!out) invalid("out is NULL");
+        *out = nullptr;
+        if (m < 0 || n < 1) invalid("need m >= 0 and n >= 1");
+        if (nnz < 0 || nnz > (int64_t)std::numeric_limits<int32_t>::max())
+            invalid("nnz must lie in [0, 2^31)");
+        if (!row_ptr || (nnz > 0 && (!col || !val)) || !c || (m > 0 && (!lc || !uc)) || !lv || !uv)
+            invalid("NULL input array");
+        // validation and the labelling sorts run on the host: stage the
+        // arrays there, after the work the caller queued on its stream
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        std::vector<int32_t> rp((size_t)m + 1), cl((size_t)nnz);
+        std::vector<double> vl((size_t)nnz), cv(n), lcv(m), ucv(m), lvv(n), uvv(n);
+        auto get = [&](void *dst, const void *src, size_t bytes) {
+            if (bytes) HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, s));
+        };
+        get(rp.data(), row_ptr, sizeof(int32_t) * rp.size());
+        get(cl.data(), col, sizeof(int32_t) * cl.size());
+        get(vl.data(), val, sizeof(double) * vl.size());
+        get(cv.data(), c, sizeof(double) * cv.size());
+        get(lcv.data(), lc, sizeof(double) * lcv.size());
+        get(ucv.data(), uc, sizeof(double) * ucv.size());
+        get(lvv.data(), lv, sizeof(double) * lvv.size());
+        get(uvv.data(), uv, sizeof(double) * uvv.size());
+        HIPCHECK(hipStreamSynchronize(s));
+        *out = create_problem(m, n, nnz, rp.data(), cl.data(), vl.data(), cv.data(), lcv.data(),
+                              ucv.data(), lvv.data(), uvv.data(), obj_offset, params, hip_stream,
+                              nullptr, nullptr);
+    });
+}
+
 void pdlp_problem_destroy(pdlp_problem *p) { delete p; }
 
 int pdlp_problem_dims(const pdlp_problem *p, int32_t *m, int32_t *n, int64_t *nnz) {

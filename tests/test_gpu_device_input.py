@@ -1,0 +1,121 @@
+"""pdlp_problem_create_device: the same problem as pdlp_problem_create when
+the arrays live in GPU memory.
+
+The arrays are placed on the device with the HIP runtime the library itself
+uses (hipMalloc/hipMemcpy through ctypes), and, in a child process, as torch
+tensors through Problem.from_tensors.  Both must give bitwise the same
+preconditioned problem and the same solve as the host-array call.
+"""
+import ctypes as C
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import lpgen
+import paper_2501_07018_amd as pd
+from tests.test_gpu_parity import gpu_params, say
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+class _DeviceArrays:
+    """Device copies of host arrays, freed on close."""
+
+    def __init__(self):
+        pd.lib()  # the library's HIP runtime is the one already loaded
+        self.hip = C.CDLL("libamdhip64.so.7")
+        self.hip.hipMalloc.argtypes = [C.POINTER(C.c_void_p), C.c_size_t]
+        self.hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+        self.hip.hipFree.argtypes = [C.c_void_p]
+        self.ptrs = []
+
+    def put(self, a):
+        a = np.ascontiguousarray(a)
+        p = C.c_void_p()
+        assert self.hip.hipMalloc(C.byref(p), max(a.nbytes, 8)) == 0
+        self.ptrs.append(p)
+        if a.nbytes:
+            assert self.hip.hipMemcpy(p, a.ctypes.data, a.nbytes, 1) == 0  # host to device
+        return p.value
+
+    def close(self):
+        for p in self.ptrs:
+            self.hip.hipFree(p)
+        self.ptrs = []
+
+
+def _create_device(lp, dev, params=None):
+    arrs = [np.asarray(lp.row_ptr, np.int32), np.asarray(lp.col, np.int32)] + \
+           [np.asarray(getattr(lp, k), np.float64) for k in ("val", "c", "lc", "uc", "lv", "uv")]
+    h = pd.pdlp_problem_create_device(lp.m, lp.n, lp.nnz, *[dev.put(a) for a in arrs],
+                                      0.0, params, None)
+    p = pd.Problem.__new__(pd.Problem)
+    p.m, p.n, p.h = lp.m, lp.n, h
+    return p
+
+
+def test_device_arrays_give_the_host_problem():
+    say("create from device arrays")
+    dev = _DeviceArrays()
+    try:
+        for lp in (lpgen.small_lp(), lpgen.planted_skewed(3000, 5000, seed=103, n_dense=3)):
+            host = pd.Problem(lp)
+            devp = _create_device(lp, dev)
+            gh, gd = host.scaled(), devp.scaled()
+            for k in gh:
+                assert np.array_equal(gh[k], gd[k]), k
+            prm = gpu_params(eps_feas=1e-6, eps_gap=1e-6, max_iters=20000)
+            rh, rd = host.solve(prm), devp.solve(prm)
+            assert rh["status_name"] == rd["status_name"] and rh["iterations"] == rd["iterations"]
+            for k in ("x", "y", "r"):
+                assert np.array_equal(rh[k], rd[k]), k
+            host.close()
+            devp.close()
+        # validation applies to device input as to host input
+        bad = lpgen.small_lp()
+        bad.lc = bad.lc.copy()
+        bad.lc[0] = bad.uc[0] + 1.0
+        with pytest.raises(pd.PdlpError) as ei:
+            _create_device(bad, dev)
+        assert ei.value.code == pd.PDLP_ERR_INVALID_ARGUMENT
+    finally:
+        dev.close()
+
+
+_CHILD = r"""
+import json, sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import lpgen
+import paper_2501_07018_amd as pd
+lp = lpgen.small_lp()
+d = torch.device("cuda:0")
+t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dtype=dt, device=d)
+i32, f64 = torch.int32, torch.float64
+p = pd.Problem.from_tensors(lp.m, lp.n, t(lp.row_ptr, i32), t(lp.col, i32), t(lp.val, f64),
+                            t(lp.c, f64), t(lp.lc, f64), t(lp.uc, f64), t(lp.lv, f64),
+                            t(lp.uv, f64))
+r = p.solve(pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6, max_iters=20000))
+print(json.dumps({"status": r["status_name"], "iterations": r["iterations"],
+                  "x": r["x"].tolist()}))
+"""
+
+
+def test_torch_tensors_give_the_host_problem():
+    say("create from torch tensors (child process)")
+    pytest.importorskip("torch")
+    out = subprocess.run([sys.executable, "-c", _CHILD, ROOT], capture_output=True, text=True,
+                         timeout=240)
+    assert out.returncode == 0, out.stderr[-2000:]
+    got = json.loads(out.stdout.strip().splitlines()[-1])
+    r = pd.Problem(lpgen.small_lp()).solve(pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6,
+                                                                  max_iters=20000))
+    assert got["status"] == r["status_name"] and got["iterations"] == r["iterations"]
+    assert np.array_equal(np.array(got["x"]), r["x"])
