@@ -265,8 +265,8 @@ def main():
     global GRAPHS
     GRAPHS = 0 if args.no_graphs else 1
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding notes in DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path; use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import lpgen
