@@ -25,12 +25,14 @@ struct BatchRecord {
 };
 
 // Packs `count` instances (arrays concatenated in instance order, local
-// column labels) into a batch; validates every instance.
+// column labels) into a batch; validates every instance.  sort_gathers adds
+// the column-sorted block copies of the matrices (only for batches whose
+// matrix values never change after creation).
 pdlp_batch *make_batch(int32_t count, const int32_t *m, const int32_t *n, const int64_t *nnz,
                        const int32_t *row_ptr, const int32_t *col, const double *val,
                        const double *c, const double *lc, const double *uc, const double *lv,
                        const double *uv, const double *obj_offset, const pdlp_params *params,
-                       void *hip_stream);
+                       void *hip_stream, bool sort_gathers);
 
 // Runs K accepted steps of Algorithm 1 (restart checks, no termination) on
 // every instance from (proj_X(0), 0), filling `rec`; the final iterate is

@@ -930,7 +930,7 @@ pdlp_batch *pdlp::host::make_batch(int32_t count, const int32_t *m, const int32_
                                    const int32_t *col, const double *val, const double *c,
                                    const double *lc, const double *uc, const double *lv,
                                    const double *uv, const double *obj_offset,
-                                   const pdlp_params *params, void *hip_stream) {
+                                   const pdlp_params *params, void *hip_stream, bool sort_gathers) {
     if (count < 1) invalid("count must be >= 1");
     if (!m || !n || !nnz || !row_ptr) invalid("NULL size array");
     int64_t M = 0, N = 0, NZ = 0;
@@ -992,6 +992,7 @@ pdlp_batch *pdlp::host::make_batch(int32_t count, const int32_t *m, const int32_
             }
         b->P = create_problem((int32_t)M, (int32_t)N, NZ, rp.data(), cg.data(), val, c, lc, uc,
                               lv, uv, 0.0, params, hip_stream, &row_breaks, &col_breaks, true);
+        if (sort_gathers) sort_block_gathers(b->P);
         build_maps(b);
     } catch (...) {
         delete b;
@@ -1021,7 +1022,7 @@ int pdlp_batch_create(int32_t count, const int32_t *m, const int32_t *n, const i
         if (!out) invalid("out is NULL");
         *out = nullptr;
         *out = make_batch(count, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, obj_offset,
-                          params, hip_stream);
+                          params, hip_stream, true);
     });
 }
 

@@ -130,6 +130,7 @@ __device__ __forceinline__ void decide_instance(Ctrl *ctrl, const BatchMaps &bm,
 }
 
 struct BatchDualEpi : NoPrefetch {
+    static constexpr bool kSortable = true;
     const Ctrl *ctrl;
     BatchMaps bm;
     Iter it;
@@ -181,6 +182,7 @@ PDLP_STREAM_KERNEL void kb_spmv_dual(DCsr A, Vecs v, Iter it, const Ctrl *ctrl,
 }
 
 struct BatchPrimalEpi : NoPrefetch {
+    static constexpr bool kSortable = true;
     const Ctrl *ctrl;
     BatchMaps bm;
     DCsr AT;
@@ -318,6 +320,7 @@ __global__ __launch_bounds__(kThreads) void kb_elementwise(DCsr A, DCsr AT, Batc
 }
 
 struct BatchPlainEpi : NoPrefetch {
+    static constexpr bool kSortable = true;
     const int32_t *inst, *mask, *list;
     int nlist;
     const double *gsrc;

@@ -223,21 +223,44 @@ __device__ __forceinline__ void stream_spmv(const DCsr &A, Epi &epi, double (&ac
             }
             int ci[kPer];
             double vv[kPer];
+            bool sorted = false;
+            if constexpr (Epi::kSortable) sorted = A.sblk != nullptr && A.sblk[b] != 0;
+            if (sorted) {
+                // column-sorted copy: neighbouring lanes gather neighbouring
+                // words; each product goes to its entry's slot in the block
 #pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int q = i * kThreads + threadIdx.x;
-                if (q < len) {
-                    ci[i] = stream_load(A.col + e0 + q);
-                    vv[i] = stream_load(A.val + e0 + q);
-                } else {
-                    ci[i] = 0;
-                    vv[i] = 0.0;
+                for (int i = 0; i < kPer; ++i) {
+                    const int q = i * kThreads + threadIdx.x;
+                    if (q < len) {
+                        ci[i] = stream_load(A.scol + e0 + q);
+                        vv[i] = stream_load(A.sval + e0 + q);
+                    } else {
+                        ci[i] = 0;
+                        vv[i] = 0.0;
+                    }
                 }
-            }
 #pragma unroll
-            for (int i = 0; i < kPer; ++i) {
-                const int q = i * kThreads + threadIdx.x;
-                if (q < len) prod[q] = vv[i] * x[ci[i]];
+                for (int i = 0; i < kPer; ++i) {
+                    const int q = i * kThreads + threadIdx.x;
+                    if (q < len) prod[stream_load(A.slot + e0 + q)] = vv[i] * x[ci[i]];
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int q = i * kThreads + threadIdx.x;
+                    if (q < len) {
+                        ci[i] = stream_load(A.col + e0 + q);
+                        vv[i] = stream_load(A.val + e0 + q);
+                    } else {
+                        ci[i] = 0;
+                        vv[i] = 0.0;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < kPer; ++i) {
+                    const int q = i * kThreads + threadIdx.x;
+                    if (q < len) prod[q] = vv[i] * x[ci[i]];
+                }
             }
             __syncthreads();
             if (rr < r1) {
@@ -339,6 +362,7 @@ struct PrimalRow {
 struct NoPrefetch {
     struct Pre {};
     __device__ __forceinline__ Pre prefetch(int) const { return {}; }
+    static constexpr bool kSortable = false;  // reads DCsr's column-sorted copy when present
 };
 
 // Epilogue base for a single LP: one gathered vector, partial sums

@@ -226,6 +226,9 @@ struct pdlp_problem {
 // Problem creation shared by single problems and batches (row_breaks /
 // col_breaks: first rows / columns of the instances of a batch, which row
 // blocks may not straddle; a batch keeps the caller's labels).
+// Column-sorted copies of the short-row blocks (DCsr::scol/sval/slot) of a
+// created problem, from its current scaled values.
+void sort_block_gathers(pdlp_problem *P);
 pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
                              const int32_t *col, const double *val, const double *c,
                              const double *lc, const double *uc, const double *lv,

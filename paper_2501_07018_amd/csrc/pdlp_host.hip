@@ -1269,6 +1269,87 @@ pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *r
         return P;
 }
 
+// Column-sorted copies of the short-row blocks of A and A^T (DCsr::scol,
+// sval, slot, sblk) from the scaled values now on the device.  A block is
+// sorted when that cuts the cache lines its waves gather from (distinct
+// 128-byte lines per 64 consecutive entries, summed over the block) by at
+// least a third; sorting a block whose columns are spread too thinly only
+// adds the slot stream and scattered LDS stores.  The copies hold the
+// scaled values of this moment: a later change of the matrix values must
+// not use them.
+void sort_block_gathers(pdlp_problem *P) {
+    hipStream_t s = P->stream;
+    for (int t = 0; t < 2; ++t) {
+        DCsr &M = t == 0 ? P->A : P->AT;
+        const std::vector<int32_t> &blk = t == 0 ? P->blkA : P->blkT;
+        const int64_t nnz = M.nnz;
+        if (nnz == 0 || M.nblk == 0) continue;
+        std::vector<int32_t> rp((size_t)M.rows + 1), col((size_t)nnz);
+        HIPCHECK(hipMemcpyAsync(rp.data(), M.row_ptr, sizeof(int32_t) * rp.size(),
+                                hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(col.data(), M.col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        std::vector<int32_t> scol((size_t)nnz);
+        std::vector<uint16_t> slot((size_t)nnz);
+        std::vector<int64_t> perm((size_t)nnz);
+        std::vector<uint8_t> sblk((size_t)M.nblk, 0);
+        // distinct 16-word lines in each run of 64 consecutive entries
+        auto lines = [](const std::vector<std::pair<int32_t, int32_t>> &kv) {
+            int64_t total = 0;
+            std::vector<int32_t> g;
+            for (size_t a = 0; a < kv.size(); a += 64) {
+                g.clear();
+                for (size_t q = a; q < std::min(kv.size(), a + 64); ++q) g.push_back(kv[q].first >> 4);
+                std::sort(g.begin(), g.end());
+                total += std::unique(g.begin(), g.end()) - g.begin();
+            }
+            return total;
+        };
+        parallel_for(M.nblk, [&](int64_t b0, int64_t b1) {
+            std::vector<std::pair<int32_t, int32_t>> kv;
+            for (int64_t b = b0; b < b1; ++b) {
+                const int32_t r0 = blk[(size_t)b], r1 = blk[(size_t)b + 1];
+                const int64_t e0 = rp[(size_t)r0], e1 = rp[(size_t)r1];
+                const int64_t len = e1 - e0, len0 = rp[(size_t)r0 + 1] - e0;
+                const bool stream = len <= pdlp::kStage && len0 <= pdlp::kMedRow;
+                kv.resize((size_t)len);
+                for (int64_t q = 0; q < len; ++q) kv[(size_t)q] = {col[(size_t)(e0 + q)], (int32_t)q};
+                bool use = false;
+                if (stream && len > 64) {
+                    const int64_t before = lines(kv);
+                    std::sort(kv.begin(), kv.end());
+                    use = 3 * lines(kv) <= 2 * before;
+                }
+                if (!use)
+                    for (int64_t q = 0; q < len; ++q) kv[(size_t)q] = {col[(size_t)(e0 + q)], (int32_t)q};
+                sblk[(size_t)b] = use;
+                for (int64_t q = 0; q < len; ++q) {
+                    const int64_t src = e0 + kv[(size_t)q].second;
+                    scol[(size_t)(e0 + q)] = col[(size_t)src];
+                    slot[(size_t)(e0 + q)] = (uint16_t)kv[(size_t)q].second;
+                    perm[(size_t)(e0 + q)] = src;
+                }
+            }
+        });
+        Arena tmp;
+        int64_t *perm_d = tmp.dev<int64_t>(nnz);
+        int32_t *scol_d = P->arena.dev<int32_t>(nnz);
+        double *sval_d = P->arena.dev<double>(nnz);
+        uint16_t *slot_d = P->arena.dev<uint16_t>(nnz);
+        uint8_t *sblk_d = P->arena.dev<uint8_t>(M.nblk);
+        HIPCHECK(hipMemcpyAsync(sblk_d, sblk.data(), M.nblk, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(perm_d, perm.data(), sizeof(int64_t) * nnz, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(scol_d, scol.data(), sizeof(int32_t) * nnz, hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(slot_d, slot.data(), sizeof(uint16_t) * nnz, hipMemcpyHostToDevice, s));
+        HIPCHECK(pdlp::launch_take(s, nnz, perm_d, M.val, sval_d));
+        HIPCHECK(hipStreamSynchronize(s));
+        M.scol = scol_d;
+        M.sval = sval_d;
+        M.slot = slot_d;
+        M.sblk = sblk_d;
+    }
+}
+
 extern "C" {
 
 int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,

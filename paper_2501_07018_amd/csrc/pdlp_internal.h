@@ -44,6 +44,15 @@ struct DCsr {
     int32_t nblk = 0;
     int32_t *blk = nullptr;
     int32_t grid = 0;  // workgroups of the persistent stream kernels
+    // Optional copy of the entries of short-row blocks sorted by column
+    // (scol, sval) with each entry's position in the block (slot), so that
+    // the lanes of a wave gather neighbouring words; the products are staged
+    // at their slots, so row sums keep the stored order.  sblk[b] = 1 marks
+    // the blocks that use the copy.  Null when absent.
+    const int32_t *scol = nullptr;
+    const double *sval = nullptr;
+    const uint16_t *slot = nullptr;
+    const uint8_t *sblk = nullptr;
 };
 
 // Scaled problem vectors seen by the iteration.
@@ -243,6 +252,9 @@ hipError_t launch_rate_gather(hipStream_t s, int64_t n, const uint32_t *idx, con
                               double *out, int grid);
 
 // batched solver (one control block per instance; per-block partial sums)
+// dst[k] = src[perm[k]], k < len
+hipError_t launch_take(hipStream_t s, int64_t len, const int64_t *perm, const double *src,
+                       double *dst);
 // primal candidates of the first attempt of a round (instances with need_primal)
 hipError_t launch_b_primal(hipStream_t s, const DCsr &AT, Vecs v, Iter it, const Ctrl *ctrl,
                            const BatchMaps &bm, double *pps);

@@ -216,6 +216,13 @@ __global__ __launch_bounds__(kThreads) void k_fill(int64_t len, double *a, doubl
         a[i] = v;
 }
 
+__global__ __launch_bounds__(kThreads) void k_take(int64_t len, const int64_t *perm,
+                                                    const double *src, double *dst) {
+    for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * kThreads)
+        dst[i] = src[perm[i]];
+}
+
 __global__ __launch_bounds__(kThreads) void k_copy(int64_t len, const double *a, double *out) {
     for (int64_t i = blockIdx.x * (int64_t)kThreads + threadIdx.x; i < len;
          i += (int64_t)gridDim.x * kThreads)
@@ -1077,6 +1084,13 @@ hipError_t launch_average(hipStream_t s, int64_t len, const double *sum, double 
 
 hipError_t launch_fill(hipStream_t s, int64_t len, double *a, double v) {
     if (len > 0) hipLaunchKernelGGL(k_fill, dim3(grid_for(len)), dim3(kThreads), 0, s, len, a, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_take(hipStream_t s, int64_t len, const int64_t *perm, const double *src,
+                       double *dst) {
+    if (len > 0)
+        hipLaunchKernelGGL(k_take, dim3(grid_for(len)), dim3(kThreads), 0, s, len, perm, src, dst);
     return hipGetLastError();
 }
 

@@ -243,7 +243,7 @@ int pdlp_unroll_create(int32_t count, const int32_t *m, const int32_t *n, const 
         auto *u = new pdlp_unroll();
         try {
             u->b = make_batch(count, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, nullptr,
-                              params, hip_stream);
+                              params, hip_stream, false);
             u->arena = new Arena();
             pdlp_problem *P = u->b->P;
             u->N = P->n;
