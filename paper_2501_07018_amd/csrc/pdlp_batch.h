@@ -26,8 +26,8 @@ struct BatchRecord {
 
 // Packs `count` instances (arrays concatenated in instance order, local
 // column labels) into a batch; validates every instance.  sort_gathers adds
-// the column-sorted block copies of the matrices (only for batches whose
-// matrix values never change after creation).
+// the column-sorted block copies of the matrices (refresh_block_gathers
+// after any later change of the matrix values).
 pdlp_batch *make_batch(int32_t count, const int32_t *m, const int32_t *n, const int64_t *nnz,
                        const int32_t *row_ptr, const int32_t *col, const double *val,
                        const double *c, const double *lc, const double *uc, const double *lv,

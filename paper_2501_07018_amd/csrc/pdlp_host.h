@@ -217,6 +217,7 @@ struct pdlp_problem {
     // orig_pos[new entry] = caller's entry index
     int32_t *row_order = nullptr, *col_order = nullptr, *orig_pos = nullptr;
     std::vector<int32_t> blkA, blkT;  // host copies of the row-block partitions
+    int64_t *sperm[2] = {nullptr, nullptr};  // A, A^T: source entry of each sorted-copy entry
     double *res_d = nullptr, *res_h = nullptr;  // small reduction results
     pdlp_params scale_params;
 
@@ -229,6 +230,9 @@ struct pdlp_problem {
 // Column-sorted copies of the short-row blocks (DCsr::scol/sval/slot) of a
 // created problem, from its current scaled values.
 void sort_block_gathers(pdlp_problem *P);
+// Copy the current values of A and A^T into their sorted copies (after the
+// values changed), on stream s.
+void refresh_block_gathers(pdlp_problem *P, hipStream_t s);
 pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
                              const int32_t *col, const double *val, const double *c,
                              const double *lc, const double *uc, const double *lv,

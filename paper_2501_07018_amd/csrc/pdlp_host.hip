@@ -1275,8 +1275,8 @@ pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *r
 // 128-byte lines per 64 consecutive entries, summed over the block) by at
 // least a third; sorting a block whose columns are spread too thinly only
 // adds the slot stream and scattered LDS stores.  The copies hold the
-// scaled values of this moment: a later change of the matrix values must
-// not use them.
+// scaled values of this moment: after a change of the matrix values,
+// refresh_block_gathers copies them again.
 void sort_block_gathers(pdlp_problem *P) {
     hipStream_t s = P->stream;
     for (int t = 0; t < 2; ++t) {
@@ -1331,8 +1331,7 @@ void sort_block_gathers(pdlp_problem *P) {
                 }
             }
         });
-        Arena tmp;
-        int64_t *perm_d = tmp.dev<int64_t>(nnz);
+        int64_t *perm_d = P->arena.dev<int64_t>(nnz);
         int32_t *scol_d = P->arena.dev<int32_t>(nnz);
         double *sval_d = P->arena.dev<double>(nnz);
         uint16_t *slot_d = P->arena.dev<uint16_t>(nnz);
@@ -1347,6 +1346,15 @@ void sort_block_gathers(pdlp_problem *P) {
         M.sval = sval_d;
         M.slot = slot_d;
         M.sblk = sblk_d;
+        P->sperm[t] = perm_d;
+    }
+}
+
+void refresh_block_gathers(pdlp_problem *P, hipStream_t s) {
+    for (int t = 0; t < 2; ++t) {
+        DCsr &M = t == 0 ? P->A : P->AT;
+        if (M.sval && P->sperm[t])
+            HIPCHECK(pdlp::launch_take(s, M.nnz, P->sperm[t], M.val, const_cast<double *>(M.sval)));
     }
 }
 

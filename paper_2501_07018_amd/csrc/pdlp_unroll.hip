@@ -224,6 +224,7 @@ void set_data(pdlp_unroll *u, const double *c, const double *lc, const double *u
                                 st));
         HIPCHECK(pdlp::launch_u_scale_values(st, P->A, u->val_orig, P->d1, P->d2, u->a2t,
                                              P->A.val, P->AT.val));
+        refresh_block_gathers(P, st);
     }
     sync(u);
 }
@@ -243,7 +244,7 @@ int pdlp_unroll_create(int32_t count, const int32_t *m, const int32_t *n, const 
         auto *u = new pdlp_unroll();
         try {
             u->b = make_batch(count, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, nullptr,
-                              params, hip_stream, false);
+                              params, hip_stream, true);
             u->arena = new Arena();
             pdlp_problem *P = u->b->P;
             u->N = P->n;
@@ -273,6 +274,7 @@ int pdlp_unroll_create(int32_t count, const int32_t *m, const int32_t *n, const 
                                         hipMemcpyHostToDevice, st));
                 HIPCHECK(pdlp::launch_u_scale_values(st, P->A, u->val_orig, P->d1, P->d2, u->a2t,
                                                      P->A.val, P->AT.val));
+                refresh_block_gathers(P, st);
             }
             // identity lists: every instance and block in order
             const BatchMaps &bm = u->b->bm;

@@ -65,6 +65,7 @@ __global__ __launch_bounds__(kThreads) void ku_primal(DCsr AT, Vecs v, UStep us,
 }
 
 struct UDualEpi : NoPrefetch {
+    static constexpr bool kSortable = true;
     UStep us;
     Vecs v;
     const double *gsrc, *y, *ax;
@@ -108,6 +109,7 @@ PDLP_STREAM_KERNEL void ku_dual(DCsr A, UDualEpi epi) {
 }
 
 struct UPrimalEpi : NoPrefetch {
+    static constexpr bool kSortable = true;
     UStep us;
     const double *gsrc, *x, *xn;
     double *atyn, *sx, *seg_w;
@@ -184,6 +186,7 @@ __global__ __launch_bounds__(kThreads) void ku_rrow(DCsr A, UStep us, const doub
 
 // Columns: wb = -sigma A~^T yhb, through w = 2 x+ - x, the projection and v.
 struct URColEpi : NoPrefetch {
+    static constexpr bool kSortable = true;
     UStep us;
     const double *gsrc, *sxb;
     const uint8_t *pm;
