@@ -100,6 +100,10 @@ typedef struct pdlp_params {
                                  separately; else a value in [64, 2048].  Row sums are the same
                                  whatever the blocks; only the order in which the step norms'
                                  partial sums combine changes. */
+    int32_t sorted_gathers;   /* batch and unroll creation: 1 (default) keeps a copy of the
+                                 short-row blocks of A and A^T sorted by column (22 bytes per
+                                 nonzero) where that cuts the cache lines a wave gathers from;
+                                 0 leaves it out.  Results are identical either way. */
 } pdlp_params;
 
 /* Result of a solve.  x, y, r are caller buffers of length n, m, n (or NULL);

@@ -48,7 +48,7 @@ class Params(C.Structure):
                 ("detect_infeasibility", C.c_int32), ("eps_infeasible", C.c_double),
                 ("restart_period", C.c_int64), ("fixed_step_size", C.c_double),
                 ("fixed_primal_weight", C.c_double), ("graphs", C.c_int32),
-                ("stream_block", C.c_int32)]
+                ("stream_block", C.c_int32), ("sorted_gathers", C.c_int32)]
 
 
 class Result(C.Structure):

@@ -992,7 +992,7 @@ pdlp_batch *pdlp::host::make_batch(int32_t count, const int32_t *m, const int32_
             }
         b->P = create_problem((int32_t)M, (int32_t)N, NZ, rp.data(), cg.data(), val, c, lc, uc,
                               lv, uv, 0.0, params, hip_stream, &row_breaks, &col_breaks, true);
-        if (sort_gathers) sort_block_gathers(b->P);
+        if (sort_gathers && (!params || params->sorted_gathers)) sort_block_gathers(b->P);
         build_maps(b);
     } catch (...) {
         delete b;

@@ -175,6 +175,7 @@ inline void check_params(const pdlp_params &p) {
     if (p.stream_block != 0 && p.stream_block != -1 &&
         !(p.stream_block >= 64 && p.stream_block <= pdlp::kStage))
         invalid("stream_block must be 0, -1 or in [64, 2048]");
+    if (p.sorted_gathers != 0 && p.sorted_gathers != 1) invalid("sorted_gathers must be 0 or 1");
     if (p.restart_period > 0) {
         if (!(p.fixed_step_size > 0.0) || !std::isfinite(p.fixed_step_size))
             invalid("restart_period > 0 needs a finite fixed_step_size > 0");

@@ -1139,6 +1139,7 @@ void pdlp_params_default(pdlp_params *p) {
     p->fixed_step_size = 0.0;
     p->fixed_primal_weight = 1.0;
     p->graphs = 1;
+    p->sorted_gathers = 1;
 }
 
 }  // extern "C"

@@ -198,3 +198,41 @@ def test_batch_with_rowless_instances():
     res = pd.Batch([_box_lp(3, 7), _box_lp(4, 11)]).solve(pd.pdlp_params_default())
     for r in res:
         assert r["status_name"] == "OPTIMAL"
+
+
+def test_sorted_gathers_change_nothing():
+    """The column-sorted block copies only reorder which lane gathers which
+    word; every product is staged at its entry's slot and summed in stored
+    order, so solves, the unrolled forward map, its tape and its gradients
+    are bitwise the same with and without them."""
+    say("sorted gathers on/off")
+    lps = _mixed_batch()[:6] + [lpgen.batch_lp(i, m, n) for i, (m, n)
+                                in enumerate(lpgen.batch_sizes()[:6])]
+    prm = dict(eps_feas=1e-7, eps_gap=1e-7, max_iters=6000)
+    runs = []
+    for sg in (1, 0):
+        b = pd.Batch(lps, pd.pdlp_params_default(sorted_gathers=sg))
+        runs.append(b.solve(pd.pdlp_params_default(**prm)))
+        b.close()
+    for r0, r1 in zip(*runs):
+        assert r0["status_name"] == r1["status_name"]
+        for key in ("iterations", "attempts", "kkt_passes", "restarts"):
+            assert r0[key] == r1[key], key
+        for key in ("x", "y", "r"):
+            assert np.array_equal(r0[key], r1[key]), key
+    layer = [lpgen.layer_lp(i) for i in range(4)]
+    g = np.random.default_rng(8).standard_normal(sum(lp.n for lp in layer))
+    outs = []
+    for sg in (1, 0):
+        u = pd.Unroll(layer, pd.pdlp_params_default(sorted_gathers=sg))
+        x = u.forward(120, 25)
+        outs.append((x, u.tape(), u.backward(g)))
+        u.set_data(val=np.concatenate([lp.val for lp in layer]) * 0.98)
+        outs[-1] += (u.forward(120, 25),)
+        u.close()
+    (xa, ta, ga, x2a), (xb, tb, gb, x2b) = outs
+    assert np.array_equal(xa, xb) and np.array_equal(x2a, x2b)
+    for p, q in zip(ta, tb):
+        assert np.array_equal(p, q)
+    for key in ga:
+        assert np.array_equal(ga[key], gb[key]), key
