@@ -54,7 +54,8 @@ class _Params(C.Structure):
                 ("polish_first", C.c_int64), ("fixed_step", C.c_int32),
                 ("fixed_eta", C.c_double), ("adaptive_restarts", C.c_int32),
                 ("detect_infeas", C.c_int32), ("eps_infeas", C.c_double),
-                ("restart_period", C.c_int64), ("fixed_omega", C.c_double)]
+                ("restart_period", C.c_int64), ("fixed_omega", C.c_double),
+                ("signed_step_rule", C.c_int32)]
 
 
 class _State(C.Structure):
@@ -91,6 +92,17 @@ class _Result(C.Structure):
 
 class _Tape(C.Structure):
     _fields_ = [("cap", C.c_int64), ("eta", D), ("omega", D), ("restart", I32)]
+
+
+I64 = C.POINTER(C.c_int64)
+
+
+class _Trace(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("count", C.c_int64), ("attempt", I64), ("k", I64),
+                ("eta", D), ("eta_bar", D), ("eta_next", D), ("num", D), ("cross", D),
+                ("accepted", I32), ("phase", I32), ("pcap", C.c_int64), ("pcount", C.c_int64),
+                ("pol_k", I64), ("pol_cap", I64), ("pol_primal", I64), ("pol_dual", I64),
+                ("pol_gap", D)]
 
 
 class _Cert(C.Structure):
@@ -146,12 +158,19 @@ def lib():
                                       C.POINTER(_State), C.POINTER(_Scratch), D, D,
                                       C.POINTER(_Result), C.POINTER(_Tape)]
         L.orc_pdlp_record.restype = C.c_int32
+        L.orc_pdlp_trace.argtypes = [C.POINTER(_LP), C.POINTER(_Unscale), C.POINTER(_Params),
+                                     C.POINTER(_State), C.POINTER(_Scratch), D, D,
+                                     C.POINTER(_Result), C.POINTER(_Tape), C.POINTER(_Trace)]
+        L.orc_pdlp_trace.restype = C.c_int32
         L.orc_unroll_replay.argtypes = [C.POINTER(_LP), C.POINTER(_Tape), C.c_int64, D, D, D, D,
                                         C.POINTER(C.c_int64)]
         L.orc_unroll_replay.restype = None
         L.orc_unroll_adjoint.argtypes = [C.POINTER(_LP), C.POINTER(_Tape), C.c_int64, D, D, D, D,
                                          D]
         L.orc_unroll_adjoint.restype = C.c_int32
+        L.orc_unroll_tangent.argtypes = [C.POINTER(_LP), C.POINTER(_Tape), C.c_int64, D, D, D, D,
+                                         D]
+        L.orc_unroll_tangent.restype = C.c_int32
         _lib = L
     return _lib
 
@@ -254,6 +273,7 @@ class Params:
     eps_infeas: float = 1e-9
     restart_period: int = 0        # > 0: Algorithm 5 mode (needs fixed_step, fixed_eta)
     fixed_omega: float = 1.0
+    signed_step_rule: bool = False  # the printed signed step test (tests only)
 
     def cstruct(self) -> _Params:
         rc = self.reduced_cost_mode
@@ -265,7 +285,8 @@ class Params:
                        int(bool(self.polish)), int(self.polish_first), int(bool(self.fixed_step)),
                        float(self.fixed_eta), int(bool(self.adaptive_restarts)),
                        int(bool(self.detect_infeasibility)), float(self.eps_infeas),
-                       int(self.restart_period), float(self.fixed_omega))
+                       int(self.restart_period), float(self.fixed_omega),
+                       int(bool(self.signed_step_rule)))
 
 
 STATUS = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 3: "NUMERICAL_ERROR", 4: "PRIMAL_INFEASIBLE",
@@ -370,6 +391,39 @@ class Solver:
                        C.byref(self.scr), _d(self.out_x), _d(self.out_y), C.byref(res))
         d = {f: getattr(res, f) for f, _ in _Result._fields_}
         d["status_name"] = STATUS.get(d["status"], str(d["status"]))
+        self.result = d
+        return d
+
+    def traced(self, params: Params | None = None, cap: int = 1 << 16,
+               pcap: int = 64) -> dict:
+        """Run with `params` (default: this solver's) recording every step
+        attempt and polishing point (see orc_trace).  Returns the result dict
+        with the trace arrays under "trace" (first min(count, cap) entries)."""
+        params = params or self.params
+        a = {k: np.zeros(cap, dtype=np.int64) for k in ("attempt", "k")}
+        a.update({k: np.zeros(cap) for k in ("eta", "eta_bar", "eta_next", "num", "cross")})
+        a.update({k: np.zeros(cap, dtype=np.int32) for k in ("accepted", "phase")})
+        pa = {k: np.zeros(pcap, dtype=np.int64) for k in ("pol_k", "pol_cap", "pol_primal",
+                                                          "pol_dual")}
+        pa["pol_gap"] = np.zeros(pcap)
+        ptr = lambda v: v.ctypes.data_as(I64 if v.dtype == np.int64 else
+                                         (I32 if v.dtype == np.int32 else D))
+        tr = _Trace(cap, 0, *[ptr(a[k]) for k in ("attempt", "k", "eta", "eta_bar", "eta_next",
+                                                  "num", "cross", "accepted", "phase")],
+                    pcap, 0, *[ptr(pa[k]) for k in ("pol_k", "pol_cap", "pol_primal",
+                                                    "pol_dual", "pol_gap")])
+        res = _Result()
+        cp = params.cstruct()
+        lib().orc_pdlp_trace(self.scaled.ref(), C.byref(self.uns), C.byref(cp),
+                             C.byref(self.st), C.byref(self.scr), _d(self.out_x),
+                             _d(self.out_y), C.byref(res), None, C.byref(tr))
+        d = {f: getattr(res, f) for f, _ in _Result._fields_}
+        d["status_name"] = STATUS.get(d["status"], str(d["status"]))
+        nt, npol = min(tr.count, cap), min(tr.pcount, pcap)
+        t = {k: v[:nt].copy() for k, v in a.items()}
+        t.update({k: v[:npol].copy() for k, v in pa.items()})
+        t["count"], t["pcount"] = tr.count, tr.pcount
+        d["trace"] = t
         self.result = d
         return d
 
@@ -506,6 +560,32 @@ class Unroll:
         lib().orc_unroll_replay(view.ref(), C.byref(self.tape), self.K, _d(x), None, None, None,
                                 C.byref(sig))
         return self.d2 * x, sig.value
+
+    def tangent(self, dc=None, dlc=None, duc=None, dval=None) -> np.ndarray:
+        """Directional derivative of x_K (original units) along a direction of
+        the data in original units (None = zero): the scaled direction is
+        dc~ = D2 dc, dlc~ = D1 dlc, duc~ = D1 duc (0 where the bound is
+        infinite), dA~_ij = D1_i D2_j dA_ij; the result is D2 dx~_K."""
+        lp = self.lp
+        m, n = lp.m, lp.n
+        nnz = int(np.asarray(lp.row_ptr)[-1]) if m else 0
+        z = lambda k, a: np.zeros(k) if a is None else _f64(a)
+        dc, dlc, duc, dval = z(n, dc), z(m, dlc), z(m, duc), z(nnz, dval)
+        fin_l = np.isfinite(np.asarray(lp.lc, dtype=np.float64))
+        fin_u = np.isfinite(np.asarray(lp.uc, dtype=np.float64))
+        rp = np.asarray(lp.row_ptr, dtype=np.int64)
+        rows = np.repeat(np.arange(m), np.diff(rp))
+        cols = np.asarray(lp.col, dtype=np.int64)
+        sdc = _f64(self.d2 * dc)
+        sdl = _f64(np.where(fin_l, self.d1 * dlc, 0.0))
+        sdu = _f64(np.where(fin_u, self.d1 * duc, 0.0))
+        sdv = _f64(self.d1[rows] * self.d2[cols] * dval)
+        dx = np.zeros(n)
+        rc = lib().orc_unroll_tangent(self.view.ref(), C.byref(self.tape), self.K, _d(sdc),
+                                      _d(sdl), _d(sdu), _d(sdv) if sdv.size else None, _d(dx))
+        if rc != 0:
+            raise MemoryError("oracle tangent out of memory")
+        return self.d2 * dx
 
     def backward(self, gx) -> dict:
         """Gradients of <gx, x_K> in original units (dc, dlc, duc, dval)."""

@@ -241,15 +241,10 @@ double orc_dual_case(double yhat, double sigma, double lc, double uc) {
 /*
  * One primal-dual candidate for step size eta (eq. "specialized-pdhg" with
  * tau = eta/omega, sigma = eta*omega).  Writes x', A x', y'; returns
- * num = ||z'-z||_omega^2 and den = 2 |(y'-y)^T A (x'-x)|.
- * Reading: Algorithm 2 splits on the sign of 2 (y'-y)^T A (x'-x).  With the
- * paper's own conventions (K = -A in Appendix B) the PDHG metric is
- * threatened when that product is negative, so the signed rule would accept
- * exactly the unsafe steps (the method then diverges); its magnitude is used,
- * which keeps the stated bound eta_bar >= 1/||A||_2.
+ * num = ||z'-z||_omega^2 and the signed interaction cross = (y'-y)^T A (x'-x).
  */
 static void pdhg_candidate(const orc_lp *lp, const orc_state *st, double eta,
-                           double *xn, double *axn, double *yn, double *num, double *den) {
+                           double *xn, double *axn, double *yn, double *num, double *cross) {
     double tau = eta / st->omega, sigma = eta * st->omega;
     for (int32_t j = 0; j < lp->n; ++j) {
         double g = lp->c[j] - st->aty[j];
@@ -262,36 +257,73 @@ static void pdhg_candidate(const orc_lp *lp, const orc_state *st, double eta,
     }
     double dx2 = dist2(xn, st->x, lp->n);
     double dy2 = dist2(yn, st->y, lp->m);
-    double cross = 0.0;
-    for (int32_t i = 0; i < lp->m; ++i) cross += (yn[i] - st->y[i]) * (axn[i] - st->ax[i]);
+    double cr = 0.0;
+    for (int32_t i = 0; i < lp->m; ++i) cr += (yn[i] - st->y[i]) * (axn[i] - st->ax[i]);
     *num = st->omega * dx2 + dy2 / st->omega;
-    *den = 2.0 * fabs(cross);
+    *cross = cr;
+}
+
+static void trace_attempt(orc_trace *tr, int phase, const orc_state *st, double eta,
+                          double eta_bar, double eta_next, double num, double cross, int acc) {
+    if (!tr) return;
+    int64_t q = tr->count++;
+    if (q >= tr->cap) return;
+    if (tr->attempt) tr->attempt[q] = st->attempts;
+    if (tr->k) tr->k[q] = st->k;
+    if (tr->eta) tr->eta[q] = eta;
+    if (tr->eta_bar) tr->eta_bar[q] = eta_bar;
+    if (tr->eta_next) tr->eta_next[q] = eta_next;
+    if (tr->num) tr->num[q] = num;
+    if (tr->cross) tr->cross[q] = cross;
+    if (tr->accepted) tr->accepted[q] = acc;
+    if (tr->phase) tr->phase[q] = phase;
 }
 
 /*
- * AdaptiveStepOfPDHG (Algorithm 2).  Reading: the counter in the factors
- * (1 - (k+1)^-0.3) and (1 + (k+1)^-0.6) is the number of step attempts made
- * so far, incremented before use (the literal first-iteration factor 1 - 1^-0.3
- * is 0 and would stall the method).  Returns 0, or ORC_NUMERR when the step
- * produced a non-finite value.  On return the accepted candidate is the new
- * iterate, and st->last_eta holds the eta that was used.
+ * AdaptiveStepOfPDHG (Algorithm 2).
+ *
+ * Reading of the step test: the algorithm splits on the sign of
+ * 2 (y'-y)^T A (x'-x).  With the paper's own conventions (Appendix B: the
+ * saddle form with K = -A) PDHG is a proximal-point method in the metric
+ * M = [[I/tau, A^T], [A, I/sigma]], and a step is safe when
+ * ||z'-z||_M^2 = ||z'-z||_omega^2 / eta + 2 (y'-y)^T A (x'-x) >= 0; that
+ * quantity is threatened when the interaction is negative, exactly the case
+ * the printed rule accepts unconditionally.  The magnitude
+ * |2 (y'-y)^T A (x'-x)| is used instead, so every accepted step keeps the
+ * metric nonnegative and the stated bound eta_bar >= 1/||A||_2 holds.
+ * (signed_step_rule = 1 follows the printed rule; the tests use it to show a
+ * step it accepts with a negative metric.)
+ *
+ * Reading of the counter: the k in (1 - (k+1)^-0.3), (1 + (k+1)^-0.6) is the
+ * number of step attempts made so far, incremented before use (the literal
+ * first-iteration factor 1 - 1^-0.3 is 0 and would stall the method).
+ *
+ * Returns 0, or ORC_NUMERR when the step produced a non-finite value.  On
+ * return the accepted candidate is the new iterate, and st->last_eta holds
+ * the eta that was used.
  */
-int orc_adaptive_step(const orc_lp *lp, const orc_params *prm, orc_state *st,
-                      orc_scratch *scr) {
+static int adaptive_step(const orc_lp *lp, const orc_params *prm, orc_state *st,
+                         orc_scratch *scr, orc_trace *tr, int phase) {
     double eta = prm->fixed_step ? prm->fixed_eta : st->eta_hat;
     double *xn = scr->n0, *atyn = scr->n1, *yn = scr->m0, *axn = scr->m1;
     for (;;) {
         st->attempts += 1;
-        double num, den;
-        pdhg_candidate(lp, st, eta, xn, axn, yn, &num, &den);
-        if (!is_fin(num) || !is_fin(den)) return ORC_NUMERR;
+        double num, cross;
+        pdhg_candidate(lp, st, eta, xn, axn, yn, &num, &cross);
+        double den = prm->signed_step_rule ? 2.0 * cross : 2.0 * fabs(cross);
+        if (!is_fin(num) || !is_fin(den)) {
+            trace_attempt(tr, phase, st, eta, NAN, NAN, num, cross, 0);
+            return ORC_NUMERR;
+        }
         double eta_bar = den > 0.0 ? num / den : INFINITY;
         st->last_eta_bar = eta_bar;
         double jj = (double)(st->attempts + 1);
         double e1 = (1.0 - pow(jj, -prm->red_exp)) * eta_bar;
         double e2 = (1.0 + pow(jj, -prm->grow_exp)) * eta;
         double eta_next = e1 < e2 ? e1 : e2;
-        if (prm->fixed_step || eta <= eta_bar) {
+        int acc = prm->fixed_step || eta <= eta_bar;
+        trace_attempt(tr, phase, st, eta, eta_bar, eta_next, num, cross, acc);
+        if (acc) {
             orc_spmv_t(lp, yn, atyn);
             st->kkt_passes += 1;
             memcpy(st->x, xn, sizeof(double) * lp->n);
@@ -304,6 +336,11 @@ int orc_adaptive_step(const orc_lp *lp, const orc_params *prm, orc_state *st,
         }
         eta = eta_next;
     }
+}
+
+int orc_adaptive_step(const orc_lp *lp, const orc_params *prm, orc_state *st,
+                      orc_scratch *scr) {
+    return adaptive_step(lp, prm, st, scr, NULL, 0);
 }
 
 /* ------------------------------------------------ normalized duality gap */
@@ -710,6 +747,8 @@ typedef struct {
     orc_state *st;
     orc_scratch *scr;
     orc_tape *tape;                    /* optional record of the decisions */
+    orc_trace *trace;                  /* optional trace of attempts and polishing */
+    int phase;                         /* 0 main run, 1 primal / 2 dual feasibility sub-run */
     /* extra buffers */
     double *xb, *yb, *axb, *atyb;      /* average and its products */
     double *xp, *yp;                   /* previous restart point */
@@ -803,6 +842,19 @@ static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish
 static int alloc_ctx(loop_ctx *L, int32_t m, int32_t n);
 static void free_ctx(loop_ctx *L);
 
+/* Appends a polishing entry; returns its index or -1. */
+static int64_t trace_polish(orc_trace *tr, int64_t k, double gap, int64_t cap) {
+    if (!tr) return -1;
+    int64_t q = tr->pcount++;
+    if (q >= tr->pcap) return -1;
+    if (tr->pol_k) tr->pol_k[q] = k;
+    if (tr->pol_gap) tr->pol_gap[q] = gap;
+    if (tr->pol_cap) tr->pol_cap[q] = cap;
+    if (tr->pol_primal) tr->pol_primal[q] = -1;
+    if (tr->pol_dual) tr->pol_dual[q] = -1;
+    return q;
+}
+
 /*
  * Feasibility polishing (Algorithm 4), called after the k-th accepted step
  * for k = polish_first * 2^i once the relative gap of the average is below
@@ -814,7 +866,7 @@ static void free_ctx(loop_ctx *L);
  * pair is accepted when it meets the full termination criteria.
  */
 static int feasibility_polish(loop_ctx *L, double *out_x, double *out_y, orc_kkt *out_kkt,
-                              orc_result *res) {
+                              orc_result *res, int64_t pe) {
     const orc_lp *lp = L->lp;
     orc_state *st = L->st;
     int32_t m = lp->m, n = lp->n;
@@ -861,6 +913,7 @@ static int feasibility_polish(loop_ctx *L, double *out_x, double *out_y, orc_kkt
         L2.lp = &lpP;
         L2.prm = &p2;
         L2.st = &s2;
+        L2.phase = 1;
         orc_spmv(&lpP, s2.x, s2.ax);
         orc_spmv_t(&lpP, s2.y, s2.aty);
         memcpy(s2.x0, s2.x, bn - sizeof(double));
@@ -871,6 +924,7 @@ static int feasibility_polish(loop_ctx *L, double *out_x, double *out_y, orc_kkt
         s2.mu_ref = s2.mu_c_prev = INFINITY; s2.last_eta = 0.0;
         int rc = pdlp_loop(&L2, cap, TERM_PRIMAL, 0, px, py, &kk, &r2);
         res->polish_iters += s2.k;
+        if (pe >= 0 && L->trace->pol_primal) L->trace->pol_primal[pe] = s2.k;
         base_passes += s2.kkt_passes;
         ok = (rc == ORC_OK);
     }
@@ -883,6 +937,7 @@ static int feasibility_polish(loop_ctx *L, double *out_x, double *out_y, orc_kkt
         L2.lp = &lpD;
         L2.prm = &p2;
         L2.st = &s2;
+        L2.phase = 2;
         orc_spmv(&lpD, s2.x, s2.ax);
         orc_spmv_t(&lpD, s2.y, s2.aty);
         memcpy(s2.x0, s2.x, bn - sizeof(double));
@@ -893,6 +948,7 @@ static int feasibility_polish(loop_ctx *L, double *out_x, double *out_y, orc_kkt
         s2.mu_ref = s2.mu_c_prev = INFINITY; s2.last_eta = 0.0;
         int rc = pdlp_loop(&L2, cap, TERM_DUAL, 0, dx, dy, &kk, &r2);
         res->polish_iters += s2.k;
+        if (pe >= 0 && L->trace->pol_dual) L->trace->pol_dual[pe] = s2.k;
         base_passes += s2.kkt_passes;
         ok = (rc == ORC_OK);
     }
@@ -1004,7 +1060,7 @@ static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish
             memcpy(L->xprev, st->x, sizeof(double) * n);
             memcpy(L->yprev, st->y, sizeof(double) * m);
         }
-        int rc = orc_adaptive_step(lp, prm, st, L->scr);
+        int rc = adaptive_step(lp, prm, st, L->scr, L->trace, L->phase);
         if (rc != ORC_OK) return ORC_NUMERR;
         double eta = st->last_eta;
         if (L->tape && st->k < L->tape->cap) {
@@ -1037,8 +1093,9 @@ static int pdlp_loop(loop_ctx *L, int64_t max_k, int term_mode, int allow_polish
         if (pol) {
             next_polish *= 2;
             orc_kkt_eval(L->u, L->xb, L->yb, 0, L->kx, L->kr, L->katy, L->ky, L->kax, &kk);
+            int64_t pe = trace_polish(L->trace, st->k, kk.rel_gap, st->k / 8);
             if (kk.rel_gap < prm->eps_gap) {
-                if (feasibility_polish(L, out_x, out_y, out_kkt, res)) {
+                if (feasibility_polish(L, out_x, out_y, out_kkt, res, pe)) {
                     res->polished = 1;
                     return ORC_POLISHED;
                 }
@@ -1141,14 +1198,15 @@ static void free_ctx(loop_ctx *L) {
  * iterate in the no-termination mode; the certificate on an infeasible
  * status).  Returns the status code.  When
  * `tape` is not NULL the decisions of every accepted step are recorded in it
- * (see orc_tape).
+ * (see orc_tape); when `trace` is not NULL every step attempt and every
+ * polishing point are appended to it (see orc_trace).
  */
-int32_t orc_pdlp_record(const orc_lp *lp, const orc_unscale *u, const orc_params *prm,
-                        orc_state *st, orc_scratch *scr, double *out_x, double *out_y,
-                        orc_result *res, orc_tape *tape) {
+int32_t orc_pdlp_trace(const orc_lp *lp, const orc_unscale *u, const orc_params *prm,
+                       orc_state *st, orc_scratch *scr, double *out_x, double *out_y,
+                       orc_result *res, orc_tape *tape, orc_trace *trace) {
     loop_ctx L;
     memset(&L, 0, sizeof L);
-    L.lp = lp; L.u = u; L.prm = prm; L.st = st; L.scr = scr; L.tape = tape;
+    L.lp = lp; L.u = u; L.prm = prm; L.st = st; L.scr = scr; L.tape = tape; L.trace = trace;
     if (!alloc_ctx(&L, lp->m, lp->n)) { free_ctx(&L); return -3; }
     orc_kkt kk;
     memset(&kk, 0, sizeof kk);
@@ -1181,6 +1239,13 @@ int32_t orc_pdlp_record(const orc_lp *lp, const orc_unscale *u, const orc_params
     res->eta = st->eta_hat;
     free_ctx(&L);
     return res->status;
+}
+
+/* orc_pdlp_trace without a trace. */
+int32_t orc_pdlp_record(const orc_lp *lp, const orc_unscale *u, const orc_params *prm,
+                        orc_state *st, orc_scratch *scr, double *out_x, double *out_y,
+                        orc_result *res, orc_tape *tape) {
+    return orc_pdlp_trace(lp, u, prm, st, scr, out_x, out_y, res, tape, NULL);
 }
 
 /* orc_pdlp_record without a record. */

@@ -47,6 +47,10 @@ typedef struct {
     int64_t restart_period;        /* > 0: Algorithm 5 (Appendix C) restarts every that
                                       many steps; needs fixed_step */
     double fixed_omega;            /* primal weight held in that mode */
+    int32_t signed_step_rule;      /* 0 (default): eta_bar from |2 (y'-y)^T A (x'-x)|;
+                                      1: the printed signed rule (eta_bar = inf when that
+                                      product is <= 0), kept only so that the tests can show
+                                      which steps it accepts (see orc_adaptive_step) */
 } orc_params;
 
 /* Iterate state; every array is owned by the caller. */
@@ -107,6 +111,33 @@ typedef struct {
     double *eta, *omega;
     int32_t *restart;
 } orc_tape;
+
+/*
+ * Optional trace of a run (caller-owned arrays, NULL pointers allowed).
+ *
+ * Every step attempt of Algorithm 2, main run and polishing sub-runs alike,
+ * appends one entry while count < cap: the attempt counter j that entered
+ * the factors (1 - (j+1)^-red_exp), (1 + (j+1)^-grow_exp), the trial step
+ * eta, the test value eta_bar, the next step eta', the movement
+ * num = ||z'-z||_omega^2, the signed interaction cross = (y'-y)^T A (x'-x),
+ * whether the attempt was accepted, the phase (0 main run, 1 primal
+ * feasibility sub-run, 2 dual feasibility sub-run) and the phase's accepted
+ * count k before the attempt.  `count` keeps counting past cap.
+ *
+ * Every feasibility-polishing point of Algorithm 4 (main-run k = polish_first
+ * * 2^i) appends one polishing entry while pcount < pcap: that k, the
+ * relative gap of the average tested against eps_gap, the sub-run cap, and
+ * the accepted steps of the primal and dual sub-runs (-1 when not run).
+ */
+typedef struct {
+    int64_t cap, count;
+    int64_t *attempt, *k;
+    double *eta, *eta_bar, *eta_next, *num, *cross;
+    int32_t *accepted, *phase;
+    int64_t pcap, pcount;
+    int64_t *pol_k, *pol_cap, *pol_primal, *pol_dual;
+    double *pol_gap;
+} orc_trace;
 
 /*
  * Outcome of one Appendix D test: `obj` is the certificate's objective

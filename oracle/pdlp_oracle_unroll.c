@@ -24,10 +24,13 @@
  * 0 on it for x+, and for y+ derivative 1 in yhat in the two moving cases
  * (plus sigma in the bound that moves it), 0 in the case that sets y+ = 0.
  *
+ * The tangent-linear map (orc_unroll_tangent) is the same derivative in
+ * forward mode.
+ *
  * Parity: pinned by central finite differences of orc_unroll_replay (the
  * replay itself is pinned by reproducing the recorded run bitwise), by a
- * one-step closed form and by exact linearity when no bound is ever met
- * (tests/test_oracle.py).
+ * one-step closed form, by exact linearity when no bound is ever met and by
+ * the dot-product test between the two modes (tests/test_oracle.py).
  */
 #include "pdlp_oracle.h"
 
@@ -204,5 +207,108 @@ int32_t orc_unroll_adjoint(const orc_lp *lp, const orc_tape *tp, int64_t K, cons
     free(xs); free(ys); free(seta); free(xb); free(yb); free(sxb); free(syb); free(aty);
     free(xp); free(w); free(vb); free(wb); free(xpb); free(ax); free(axp); free(yhb);
     free(ypb); free(av); free(xfin); free(p); free(q);
+    return 0;
+}
+
+/*
+ * Tangent-linear (forward-mode) derivative of the replayed map: given a
+ * direction (dc~ (n), dlc~, duc~ (m), dA~ per stored nonzero (nnz, CSR
+ * order)) in the scaled data, returns dx_K (n), the directional derivative
+ * of x_K, with the same fixed selections as orc_unroll_adjoint.  Per step,
+ * with d(.) the tangent of each quantity:
+ *   d(A~^T y) = dA~^T y + A~^T dy,  d(A~ x) = dA~ x + A~ dx
+ *   dv   = dx - tau (dc~ - d(A~^T y)),          dx+ = dv inside the box, else 0
+ *   dyhat = dy - sigma (2 d(A~ x+) - d(A~ x)),  dy+ = dyhat + sigma duc~ (case 1),
+ *                                               dyhat + sigma dlc~ (case 2), 0 (case 0)
+ *   dSx += eta dx+, dSy += eta dy+;  a restart to the average sets (dx, dy) =
+ *   (dSx, dSy) / S and recomputes the product tangents; any restart clears dS.
+ * The pairing <dx_K, gx> equals <(dc~, dlc~, duc~, dA~), adjoint of gx> up to
+ * rounding (the dot-product test).  Returns 0, or -3 when memory runs out.
+ */
+int32_t orc_unroll_tangent(const orc_lp *lp, const orc_tape *tp, int64_t K, const double *dc,
+                           const double *dlc, const double *duc, const double *dval,
+                           double *dx_out) {
+    const int32_t m = lp->m, n = lp->n;
+    orc_lp dl = *lp;          /* the direction as a matrix with A's pattern */
+    dl.val = dval;
+    double *x = calloc(n + 1, sizeof(double)), *aty = malloc(sizeof(double) * (n + 1));
+    double *xn = malloc(sizeof(double) * (n + 1)), *sx = calloc(n + 1, sizeof(double));
+    double *y = calloc(m + 1, sizeof(double)), *ax = malloc(sizeof(double) * (m + 1));
+    double *axn = malloc(sizeof(double) * (m + 1)), *sy = calloc(m + 1, sizeof(double));
+    double *dx = calloc(n + 1, sizeof(double)), *daty = malloc(sizeof(double) * (n + 1));
+    double *dxn = malloc(sizeof(double) * (n + 1)), *dsx = calloc(n + 1, sizeof(double));
+    double *dy = calloc(m + 1, sizeof(double)), *dax = malloc(sizeof(double) * (m + 1));
+    double *daxn = malloc(sizeof(double) * (m + 1)), *dsy = calloc(m + 1, sizeof(double));
+    double *tn = malloc(sizeof(double) * (n + 1)), *tm = malloc(sizeof(double) * (m + 1));
+    if (!x || !aty || !xn || !sx || !y || !ax || !axn || !sy || !dx || !daty || !dxn || !dsx ||
+        !dy || !dax || !daxn || !dsy || !tn || !tm) {
+        free(x); free(aty); free(xn); free(sx); free(y); free(ax); free(axn); free(sy);
+        free(dx); free(daty); free(dxn); free(dsx); free(dy); free(dax); free(daxn); free(dsy);
+        free(tn); free(tm);
+        return -3;
+    }
+    double seta = 0.0;
+    for (int32_t j = 0; j < n; ++j) x[j] = clampv(0.0, lp->lv[j], lp->uv[j]);
+    /* x_0 = proj_X(0) does not depend on the data; y_0 = 0 */
+    orc_spmv(lp, x, ax);
+    orc_spmv_t(lp, y, aty);
+    orc_spmv(&dl, x, dax);             /* d(A~ x_0) = dA~ x_0 */
+    for (int32_t j = 0; j < n; ++j) daty[j] = 0.0;
+    for (int64_t k = 0; k < K; ++k) {
+        const double eta = tp->eta[k], tau = eta / tp->omega[k], sigma = eta * tp->omega[k];
+        for (int32_t j = 0; j < n; ++j) {
+            const double g = lp->c[j] - aty[j];
+            const double v = x[j] - tau * g;
+            const int inside = v > lp->lv[j] && v < lp->uv[j];
+            xn[j] = clampv(v, lp->lv[j], lp->uv[j]);
+            dxn[j] = inside ? dx[j] - tau * (dc[j] - daty[j]) : 0.0;
+        }
+        orc_spmv(lp, xn, axn);
+        orc_spmv(&dl, xn, daxn);
+        orc_spmv(lp, dxn, tm);
+        for (int32_t i = 0; i < m; ++i) daxn[i] += tm[i];
+        for (int32_t i = 0; i < m; ++i) {
+            const double yhat = y[i] - sigma * (2.0 * axn[i] - ax[i]);
+            const double dyhat = dy[i] - sigma * (2.0 * daxn[i] - dax[i]);
+            const int br = dual_branch(yhat, sigma, lp->lc[i], lp->uc[i]);
+            dy[i] = br == 1 ? dyhat + sigma * duc[i] : br == 2 ? dyhat + sigma * dlc[i] : 0.0;
+            y[i] = orc_dual_case(yhat, sigma, lp->lc[i], lp->uc[i]);
+        }
+        memcpy(x, xn, sizeof(double) * n);
+        memcpy(dx, dxn, sizeof(double) * n);
+        memcpy(ax, axn, sizeof(double) * m);
+        memcpy(dax, daxn, sizeof(double) * m);
+        orc_spmv_t(lp, y, aty);
+        orc_spmv_t(&dl, y, daty);
+        orc_spmv_t(lp, dy, tn);
+        for (int32_t j = 0; j < n; ++j) daty[j] += tn[j];
+        seta += eta;
+        for (int32_t j = 0; j < n; ++j) { sx[j] += eta * x[j]; dsx[j] += eta * dx[j]; }
+        for (int32_t i = 0; i < m; ++i) { sy[i] += eta * y[i]; dsy[i] += eta * dy[i]; }
+        const int32_t r = tp->restart[k];
+        if (r == 2) {
+            for (int32_t j = 0; j < n; ++j) { x[j] = sx[j] / seta; dx[j] = dsx[j] / seta; }
+            for (int32_t i = 0; i < m; ++i) { y[i] = sy[i] / seta; dy[i] = dsy[i] / seta; }
+            orc_spmv(lp, x, ax);
+            orc_spmv_t(lp, y, aty);
+            orc_spmv(&dl, x, dax);
+            orc_spmv(lp, dx, tm);
+            for (int32_t i = 0; i < m; ++i) dax[i] += tm[i];
+            orc_spmv_t(&dl, y, daty);
+            orc_spmv_t(lp, dy, tn);
+            for (int32_t j = 0; j < n; ++j) daty[j] += tn[j];
+        }
+        if (r != 0) {
+            seta = 0.0;
+            memset(sx, 0, sizeof(double) * n);
+            memset(sy, 0, sizeof(double) * m);
+            memset(dsx, 0, sizeof(double) * n);
+            memset(dsy, 0, sizeof(double) * m);
+        }
+    }
+    memcpy(dx_out, dx, sizeof(double) * n);
+    free(x); free(aty); free(xn); free(sx); free(y); free(ax); free(axn); free(sy);
+    free(dx); free(daty); free(dxn); free(dsx); free(dy); free(dax); free(daxn); free(dsy);
+    free(tn); free(tm);
     return 0;
 }

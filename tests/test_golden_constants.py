@@ -12,9 +12,15 @@ import oracle
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")
 
 
-def _constants():
+def _constants(params_only=True):
     with open(GOLDEN) as f:
-        return json.load(f)["constants"]
+        cs = json.load(f)["constants"]
+    return [c for c in cs if c.get("param", True)] if params_only else cs
+
+
+def constant(key):
+    """Value of a constant of the golden file by key."""
+    return next(c["value"] for c in _constants(False) if c["key"] == key)
 
 
 @pytest.mark.parametrize("c", _constants(), ids=lambda c: c["key"])

@@ -543,3 +543,77 @@ def test_unroll_one_step_closed_form():
     expect = -tau * p * U.d2 ** 2 * gx
     np.testing.assert_allclose(g["c"], expect, rtol=1e-15, atol=0)
     assert not g["lc"].any() and not g["uc"].any() and not g["val"].any()
+
+
+# ------------------------------------------------- tangent-linear (forward mode)
+#
+# The tangent is pinned by central differences of the replay, by the one-step
+# closed form, by linearity in the direction, and by the dot-product test
+# against the reverse sweep, <J v, w> = <v, J^T w>: the two modes share no
+# derivative code, so a dropped or mis-signed term in either breaks the
+# equality.  The test keeps its meaning where the map is ill-conditioned
+# (large K), unlike finite differences.
+
+def _full_direction(rng, lp):
+    return dict(dc=_direction(rng, lp.c), dlc=_direction(rng, lp.lc), duc=_direction(rng, lp.uc),
+                dval=_direction(rng, lp.val))
+
+
+def test_unroll_tangent_one_step_closed_form():
+    lp = lpgen.planted_uniform(40, 70, 5, seed=9)
+    U = oracle.Unroll(lp, 1)
+    rng = np.random.default_rng(4)
+    d = _full_direction(rng, lp)
+    dx = U.tangent(**d)
+    tau = U.eta[0] / U.omega[0]
+    x0 = np.clip(0.0, U.view.lv, U.view.uv)
+    v = x0 - tau * U.view.c
+    p = (v > U.view.lv) & (v < U.view.uv)
+    np.testing.assert_allclose(dx, U.d2 * (-tau * p * (U.d2 * d["dc"])), rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("which", ["dc", "dlc", "duc", "dval", "all"])
+def test_unroll_tangent_matches_central_differences(which):
+    lp, U = _unroll_case()
+    rng = np.random.default_rng(5)
+    _, sig = U.replay()
+    names = {"dc": "c", "dlc": "lc", "duc": "uc", "dval": "val"}
+    for trial in range(3):
+        full = _full_direction(rng, lp)
+        d = full if which == "all" else {which: full[which]}
+        dx = U.tangent(**d)
+        h = 1e-6
+        plus = {names[k]: np.asarray(getattr(lp, names[k]), float) + h * v for k, v in d.items()}
+        minus = {names[k]: np.asarray(getattr(lp, names[k]), float) - h * v for k, v in d.items()}
+        xp, sp = U.replay(**plus)
+        xm, sm = U.replay(**minus)
+        assert sp == sig and sm == sig
+        fd = (xp - xm) / (2 * h)
+        assert np.linalg.norm(fd - dx) <= 1e-6 * np.linalg.norm(dx), (which, trial)
+
+
+def test_unroll_tangent_is_linear_in_the_direction():
+    lp, U = _unroll_case()
+    rng = np.random.default_rng(6)
+    a, b = _full_direction(rng, lp), _full_direction(rng, lp)
+    ta, tb = U.tangent(**a), U.tangent(**b)
+    tab = U.tangent(**{k: 2.5 * a[k] - b[k] for k in a})
+    np.testing.assert_allclose(tab, 2.5 * ta - tb, rtol=1e-12, atol=1e-12 * np.abs(ta).max())
+
+
+@pytest.mark.parametrize("m,n,k,K", [(60, 100, 5, 120), (200, 400, 6, 300), (2000, 4000, 10, 500)])
+def test_unroll_dot_product_tangent_vs_adjoint(m, n, k, K):
+    lp = lpgen.planted_uniform(m, n, k, seed=17)
+    U = oracle.Unroll(lp, K)
+    rng = np.random.default_rng(7)
+    d = _full_direction(rng, lp)
+    w = rng.standard_normal(lp.n)
+    jv = U.tangent(**d)
+    g = U.backward(w)
+    lhs = jv @ w
+    rhs = d["dc"] @ g["c"] + d["dlc"] @ g["lc"] + d["duc"] @ g["uc"] + d["dval"] @ g["val"]
+    vnorm = np.sqrt(sum(np.linalg.norm(v) ** 2 for v in d.values()))
+    gnorm = np.sqrt(sum(np.linalg.norm(v) ** 2 for v in g.values()))
+    scale = np.linalg.norm(jv) * np.linalg.norm(w) + vnorm * gnorm
+    assert abs(lhs - rhs) <= 1e-12 * scale, (lhs, rhs, scale)
+    assert abs(lhs) > 1e-6 * scale   # not a trivially small pairing
