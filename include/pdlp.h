@@ -188,8 +188,11 @@ int pdlp_problem_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_pt
  * Validation and the internal row/column labelling run on the host, so the
  * arrays are first copied to the host on hip_stream, after the work already
  * queued there; the caller keeps ownership and may free them when the call
- * returns.  Errors as for pdlp_problem_create; HIP_ERROR for a pointer the
- * runtime cannot copy from.
+ * returns.  The lengths are trusted: row_ptr_dev must hold m + 1 entries,
+ * col_dev and val_dev nnz, c_dev, lv_dev and uv_dev n, lc_dev and uc_dev m
+ * (the library copies exactly those byte counts; shorter arrays are read
+ * past their end).  Errors as for pdlp_problem_create; HIP_ERROR for a
+ * pointer the runtime cannot copy from.
  */
 int pdlp_problem_create_device(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr_dev,
                                const int32_t *col_dev, const double *val_dev, const double *c_dev,

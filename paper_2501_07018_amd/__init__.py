@@ -550,8 +550,18 @@ class Problem:
             if t.dtype != want or not t.is_contiguous() or not t.is_cuda:
                 raise ValueError("tensors must be contiguous CUDA tensors: int32 row_ptr and "
                                  "col, float64 val, c, lc, uc, lv, uv")
+        m, n = int(m), int(n)
+        if m < 0 or n < 0:
+            raise ValueError("m and n must be >= 0")
+        nnz = col.numel()
+        want_len = {"row_ptr": m + 1, "col": nnz, "val": nnz, "c": n, "lc": m, "uc": m,
+                    "lv": n, "uv": n}
+        for name, t in zip(want_len, ts):
+            if t.numel() != want_len[name]:
+                raise ValueError(f"{name} has {t.numel()} elements, expected {want_len[name]} "
+                                 f"(m={m}, n={n}, nnz={nnz})")
         self = cls.__new__(cls)
-        self.m, self.n = int(m), int(n)
+        self.m, self.n = m, n
         self.h = None
         self.h = pdlp_problem_create_device(
             m, n, col.numel(), *[t.data_ptr() for t in ts], obj_offset, params,

@@ -58,21 +58,6 @@ struct Arena {
         ptrs.push_back(p);
         return static_cast<T *>(p);
     }
-#ifdef PDLP_PROBE_UNCACHED_MATRIX
-    // experiment only: uncached matrix arrays, never freed (process lifetime)
-    template <class T>
-    T *dev_uncached(size_t count) {
-        void *p = nullptr;
-        HIPCHECK(hipExtMallocWithFlags(&p, std::max<size_t>(count, 1) * sizeof(T),
-                                       hipDeviceMallocUncached));
-        return static_cast<T *>(p);
-    }
-#else
-    template <class T>
-    T *dev_uncached(size_t count) {
-        return dev<T>(count);
-    }
-#endif
     template <class T>
     T *host(size_t count) {
         void *p = nullptr;
@@ -126,15 +111,24 @@ int guarded(F &&f) {
 // enqueued as graph launches of those sizes (greedily), i.e. exactly the
 // launches an eager loop would make.  Capture runs on a private stream
 // (capturing executes nothing); replays go to the caller's stream.
+//
+// Lifetime rules: a capture either installs all three executable graphs or
+// none (a failure ends the capture, frees what it made and leaves the object
+// empty); replaced executable graphs are not destroyed while the owner runs
+// but kept until the object is destroyed, which first waits for the last
+// replay stream, so no executable graph is freed while work or a runtime
+// record of a replay may still refer to it.
 struct AttemptGraphs {
     hipStream_t cap = nullptr;
+    hipStream_t replay = nullptr;  // stream of the last replay
     hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+    std::vector<hipGraphExec_t> retired;
     static constexpr long long kSizes[3] = {64, 8, 1};
-    bool ready() const { return exec[0] != nullptr; }
+    bool ready() const { return exec[0] && exec[1] && exec[2]; }
     void reset() {
         for (auto &e : exec)
             if (e) {
-                (void)hipGraphExecDestroy(e);
+                retired.push_back(e);
                 e = nullptr;
             }
     }
@@ -142,22 +136,50 @@ struct AttemptGraphs {
     void capture(F &&attempt) {
         reset();
         if (!cap) HIPCHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        for (int g = 0; g < 3; ++g) {
-            hipGraph_t graph = nullptr;
-            HIPCHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
-            for (long long a = 0; a < kSizes[g]; ++a) attempt(cap);
-            HIPCHECK(hipStreamEndCapture(cap, &graph));
-            const hipError_t e = hipGraphInstantiate(&exec[g], graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            HIPCHECK(e);
+        hipGraphExec_t made[3] = {nullptr, nullptr, nullptr};
+        try {
+            for (int g = 0; g < 3; ++g) {
+                HIPCHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+                try {
+                    for (long long a = 0; a < kSizes[g]; ++a) attempt(cap);
+                } catch (...) {
+                    hipGraph_t junk = nullptr;
+                    (void)hipStreamEndCapture(cap, &junk);
+                    if (junk) (void)hipGraphDestroy(junk);
+                    (void)hipGetLastError();
+                    throw;
+                }
+                hipGraph_t graph = nullptr;
+                HIPCHECK(hipStreamEndCapture(cap, &graph));
+                if (!graph) throw LibError(PDLP_ERR_HIP, "graph capture returned no graph");
+                size_t nodes = 0;
+                const hipError_t en = hipGraphGetNodes(graph, nullptr, &nodes);
+                hipError_t e = en;
+                if (en == hipSuccess && nodes == 0) {
+                    (void)hipGraphDestroy(graph);
+                    throw LibError(PDLP_ERR_STATE, "captured step attempt is empty");
+                }
+                if (en == hipSuccess) e = hipGraphInstantiate(&made[g], graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                HIPCHECK(e);
+            }
+        } catch (...) {
+            for (auto &e : made)
+                if (e) (void)hipGraphExecDestroy(e);
+            throw;
         }
+        for (int g = 0; g < 3; ++g) exec[g] = made[g];
     }
-    void launch(hipStream_t s, long long n) const {
+    void launch(hipStream_t s, long long n) {
+        if (!ready()) throw LibError(PDLP_ERR_STATE, "graph replay without a complete capture");
+        replay = s;
         for (int g = 0; g < 3; ++g)
             for (; n >= kSizes[g]; n -= kSizes[g]) HIPCHECK(hipGraphLaunch(exec[g], s));
     }
     ~AttemptGraphs() {
+        if (replay) (void)hipStreamSynchronize(replay);
         reset();
+        for (auto e : retired) (void)hipGraphExecDestroy(e);
         if (cap) (void)hipStreamDestroy(cap);
     }
 };

@@ -9,7 +9,6 @@
 // known in advance), feasibility-polishing points (Algorithm 4) and the
 // iteration cap.  Inside a block the step attempts (Algorithm 2) run on the
 // device with their accept/reject decision in the device control block.
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <chrono>
@@ -344,8 +343,8 @@ void build_transpose(pdlp_problem *P, const int32_t *rp0, const int32_t *col0, c
     T.cols = P->m;
     T.nnz = nnz;
     T.row_ptr = P->arena.dev<int32_t>((size_t)P->n + 1);
-    T.col = P->arena.dev_uncached<int32_t>(nnz);
-    T.val = P->arena.dev_uncached<double>(nnz);
+    T.col = P->arena.dev<int32_t>(nnz);
+    T.val = P->arena.dev<double>(nnz);
     if (nnz == 0) {
         HIPCHECK(hipMemsetAsync(T.row_ptr, 0, sizeof(int32_t) * ((size_t)P->n + 1), s));
         HIPCHECK(hipStreamSynchronize(s));
@@ -360,16 +359,15 @@ void build_transpose(pdlp_problem *P, const int32_t *rp0, const int32_t *col0, c
     HIPCHECK(pdlp::launch_row_ids_mapped(s, P->m, rp0, new_row, rowid));
     HIPCHECK(pdlp::launch_relabel(s, nnz, col0, new_col, keys_in));
     HIPCHECK(pdlp::launch_iota(s, nnz, vals_in));
-    int end_bit = 1;
-    while (end_bit < 31 && (1LL << end_bit) <= (long long)P->n) ++end_bit;
-    size_t temp_bytes = 0;
-    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, keys_in, keys_out, vals_in,
-                                                vals_out, (int)nnz, 0, end_bit, s));
-    void *temp = tmp.dev<char>(temp_bytes);
-    HIPCHECK(hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, vals_in,
-                                                vals_out, (int)nnz, 0, end_bit, s));
-    HIPCHECK(pdlp::launch_transpose_finish(s, nnz, P->n, reinterpret_cast<const int32_t *>(keys_out),
-                                           vals_out, rowid, val0, T.row_ptr, T.col, T.val));
+    int key_bits = 1;
+    while (key_bits < 31 && (1LL << key_bits) <= (long long)P->n) ++key_bits;
+    int32_t *temp = tmp.dev<int32_t>((size_t)pdlp::radix_sort_temp_ints(nnz));
+    uint32_t *keys[2] = {keys_in, keys_out};
+    int32_t *vals[2] = {vals_in, vals_out};
+    int which = 0;
+    HIPCHECK(pdlp::radix_sort_pairs(s, nnz, key_bits, keys, vals, temp, &which));
+    HIPCHECK(pdlp::launch_transpose_finish(s, nnz, P->n, reinterpret_cast<const int32_t *>(keys[which]),
+                                           vals[which], rowid, val0, T.row_ptr, T.col, T.val));
     HIPCHECK(hipStreamSynchronize(s));
 }
 
@@ -1201,8 +1199,8 @@ pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *r
             A.cols = n;
             A.nnz = nnz;
             A.row_ptr = a.dev<int32_t>((size_t)m + 1);
-            A.col = a.dev_uncached<int32_t>(nnz);
-            A.val = a.dev_uncached<double>(nnz);
+            A.col = a.dev<int32_t>(nnz);
+            A.val = a.dev<double>(nnz);
             HIPCHECK(hipMemcpyAsync(A.row_ptr, new_rp.data(), sizeof(int32_t) * ((size_t)m + 1),
                                     hipMemcpyHostToDevice, s));
             {

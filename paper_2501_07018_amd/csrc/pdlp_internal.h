@@ -212,6 +212,13 @@ hipError_t launch_permute_rows(hipStream_t s, int m, const int32_t *row_order,
                                const int32_t *new_rp, int32_t *ncol, double *nval,
                                int32_t *orig_pos);
 hipError_t launch_iota(hipStream_t s, int64_t len, int32_t *a);
+// Stable LSD radix sort of n (key, value) pairs by the low key_bits bits of
+// the keys (8 bits per pass).  keys[0]/vals[0] hold the input, keys[1]/vals[1]
+// are buffers of the same length; the sorted pairs end in keys[*which] /
+// vals[*which].  temp holds radix_sort_temp_ints(n) int32.
+int64_t radix_sort_temp_ints(int64_t n);
+hipError_t radix_sort_pairs(hipStream_t s, int64_t n, int key_bits, uint32_t *keys[2],
+                            int32_t *vals[2], int32_t *temp, int *which);
 hipError_t launch_transpose_finish(hipStream_t s, int64_t nnz, int n, const int32_t *sorted_cols,
                                    const int32_t *perm, const int32_t *rowid, const double *val,
                                    int32_t *t_row_ptr, int32_t *t_col, double *t_val);

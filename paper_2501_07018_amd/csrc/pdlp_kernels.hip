@@ -423,6 +423,164 @@ __global__ __launch_bounds__(kThreads) void k_iota(int64_t len, int32_t *a) {
         a[i] = (int32_t)i;
 }
 
+// Stable LSD radix sort of (key, value) pairs, 8 key bits per pass (used to
+// build A^T: sorting the caller-order entries by column label keeps each
+// column's entries in caller row order).  One pass is three steps:
+//   k_radix_count   per wave tile of kRadixTile consecutive items, the count
+//                   of every digit, stored digit-major (counts[d * ntiles + t]);
+//   k_scan_*        exclusive prefix sum of the counts in that order, i.e. the
+//                   first output slot of digit d from tile t;
+//   k_radix_scatter each wave re-reads its tile in order, 64 items per round;
+//                   lanes holding the same digit find each other with eight
+//                   ballots (one per digit bit), take their rank among the
+//                   lower lanes, and the lowest of them advances the tile's
+//                   running slot of that digit.  Items keep their input order
+//                   within a digit, so the pass is stable.
+// Integer counts only; results do not depend on scheduling.
+constexpr int kRadixBins = 256;
+constexpr int kRadixRounds = 64;
+constexpr int64_t kRadixTile = 64 * kRadixRounds;  // items per wave tile
+constexpr int kScanItems = 16;                     // per thread in the count scan
+constexpr int64_t kScanChunk = (int64_t)kThreads * kScanItems;
+
+__global__ __launch_bounds__(kThreads) void k_radix_count(int64_t n, const uint32_t *__restrict__ key,
+                                                          int shift, int64_t ntiles,
+                                                          int32_t *__restrict__ counts) {
+    __shared__ int32_t hist[kWaveRows][kRadixBins];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * kWaveRows + w;
+    for (int d = lane; d < kRadixBins; d += 64) hist[w][d] = 0;
+    __syncthreads();
+    if (tile < ntiles) {
+        const int64_t base = tile * kRadixTile;
+        for (int r = 0; r < kRadixRounds; ++r) {
+            const int64_t i = base + (int64_t)r * 64 + lane;
+            if (i < n) atomicAdd(&hist[w][(key[i] >> shift) & (kRadixBins - 1)], 1);
+        }
+    }
+    __syncthreads();
+    if (tile < ntiles)
+        for (int d = lane; d < kRadixBins; d += 64) counts[(int64_t)d * ntiles + tile] = hist[w][d];
+}
+
+__device__ __forceinline__ int32_t wave_incl_scan_i32(int32_t v) {
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive prefix sum over the kThreads threads of a workgroup (in thread
+// order); returns the block total through *total.
+__device__ __forceinline__ int32_t block_excl_scan_i32(int32_t v, int32_t *lds, int32_t *total) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t inc = wave_incl_scan_i32(v);
+    __syncthreads();
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    int32_t before = 0, all = 0;
+    for (int q = 0; q < kWaveRows; ++q) {
+        if (q < w) before += lds[q];
+        all += lds[q];
+    }
+    *total = all;
+    return before + inc - v;
+}
+
+// sums[b] = sum of chunk b (kScanChunk consecutive counts)
+__global__ __launch_bounds__(kThreads) void k_scan_chunks(int64_t len, const int32_t *__restrict__ in,
+                                                          int32_t *__restrict__ sums) {
+    __shared__ int32_t lds[kWaveRows];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanChunk;
+    int32_t s = 0;
+    for (int q = 0; q < kScanItems; ++q) {
+        const int64_t i = b0 + (int64_t)q * kThreads + threadIdx.x;
+        if (i < len) s += in[i];
+    }
+    int32_t total = 0;
+    (void)block_excl_scan_i32(s, lds, &total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// exclusive scan of the chunk sums in place (one workgroup)
+__global__ __launch_bounds__(kThreads) void k_scan_sums(int64_t len, int32_t *__restrict__ sums) {
+    __shared__ int32_t lds[kWaveRows];
+    int32_t carry = 0;
+    for (int64_t b = 0; b < len; b += kThreads) {
+        const int64_t i = b + threadIdx.x;
+        const int32_t v = i < len ? sums[i] : 0;
+        int32_t total = 0;
+        const int32_t ex = block_excl_scan_i32(v, lds, &total);
+        if (i < len) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+// exclusive scan of each chunk from its base; thread t owns kScanItems
+// consecutive counts of the chunk
+__global__ __launch_bounds__(kThreads) void k_scan_apply(int64_t len, int32_t *__restrict__ a,
+                                                         const int32_t *__restrict__ sums) {
+    __shared__ int32_t lds[kWaveRows];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int32_t s = 0;
+    for (int q = 0; q < kScanItems; ++q) {
+        v[q] = (b0 + q < len) ? a[b0 + q] : 0;
+        s += v[q];
+    }
+    int32_t total = 0;
+    int32_t run = sums[blockIdx.x] + block_excl_scan_i32(s, lds, &total);
+    for (int q = 0; q < kScanItems; ++q) {
+        if (b0 + q < len) a[b0 + q] = run;
+        run += v[q];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(int64_t n, const uint32_t *__restrict__ kin,
+                                                            const int32_t *__restrict__ vin,
+                                                            uint32_t *__restrict__ kout,
+                                                            int32_t *__restrict__ vout, int shift,
+                                                            int64_t ntiles,
+                                                            const int32_t *__restrict__ offs) {
+    __shared__ int32_t slot[kWaveRows][kRadixBins];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t tile = (int64_t)blockIdx.x * kWaveRows + w;
+    if (tile < ntiles)
+        for (int d = lane; d < kRadixBins; d += 64) slot[w][d] = offs[(int64_t)d * ntiles + tile];
+    __syncthreads();
+    if (tile >= ntiles) return;
+    const uint64_t lower = (1ull << lane) - 1ull;
+    const int64_t base = tile * kRadixTile;
+    for (int r = 0; r < kRadixRounds; ++r) {
+        const int64_t first = base + (int64_t)r * 64;
+        if (first >= n) break;  // uniform over the wave
+        const int64_t i = first + lane;
+        const bool ok = i < n;
+        const uint32_t k = ok ? kin[i] : 0u;
+        const int32_t v = ok ? vin[i] : 0;
+        const uint32_t d = (k >> shift) & (kRadixBins - 1);
+        uint64_t same = __ballot(ok);
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t set = __ballot(bit);
+            same &= bit ? set : ~set;
+        }
+        if (!ok) same = 0;
+        const uint64_t below = same & lower;
+        const int32_t at = slot[w][d];  // all lanes read before the leader advances it
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        if (ok) {
+            const int32_t pos = at + __popcll(below);
+            kout[pos] = k;
+            vout[pos] = v;
+            if (below == 0) slot[w][d] = at + __popcll(same);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+}
+
 // A^T from a stable sort of A's entries by column: row_ptr by lower_bound,
 // col = original row, val gathered.
 __global__ __launch_bounds__(kThreads) void k_transpose_finish(int64_t nnz, int n,
@@ -1221,6 +1379,41 @@ hipError_t launch_permute_rows(hipStream_t s, int m, const int32_t *row_order,
 
 hipError_t launch_iota(hipStream_t s, int64_t len, int32_t *a) {
     if (len > 0) hipLaunchKernelGGL(k_iota, dim3(grid_for(len)), dim3(kThreads), 0, s, len, a);
+    return hipGetLastError();
+}
+
+int64_t radix_sort_temp_ints(int64_t n) {
+    const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+    const int64_t len = ntiles * kRadixBins;
+    const int64_t nchunks = (len + kScanChunk - 1) / kScanChunk;
+    return len + nchunks + 64;
+}
+
+hipError_t radix_sort_pairs(hipStream_t s, int64_t n, int key_bits, uint32_t *keys[2],
+                            int32_t *vals[2], int32_t *temp, int *which) {
+    int cur = 0;
+    if (n > 0) {
+        const int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+        const int64_t len = ntiles * kRadixBins;
+        const int64_t nchunks = (len + kScanChunk - 1) / kScanChunk;
+        int32_t *counts = temp, *sums = temp + len;
+        const int64_t wgs = (ntiles + kWaveRows - 1) / kWaveRows;
+        if (wgs > 0x7fffffffLL || nchunks > 0x7fffffffLL) return hipErrorInvalidValue;
+        for (int shift = 0; shift < key_bits; shift += 8) {
+            hipLaunchKernelGGL(k_radix_count, dim3((unsigned)wgs), dim3(kThreads), 0, s, n,
+                               keys[cur], shift, ntiles, counts);
+            hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(kThreads), 0, s, len,
+                               counts, sums);
+            hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kThreads), 0, s, nchunks, sums);
+            hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nchunks), dim3(kThreads), 0, s, len,
+                               counts, sums);
+            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)wgs), dim3(kThreads), 0, s, n,
+                               keys[cur], vals[cur], keys[cur ^ 1], vals[cur ^ 1], shift, ntiles,
+                               counts);
+            cur ^= 1;
+        }
+    }
+    *which = cur;
     return hipGetLastError();
 }
 

@@ -103,8 +103,21 @@ p = pd.Problem.from_tensors(lp.m, lp.n, t(lp.row_ptr, i32), t(lp.col, i32), t(lp
                             t(lp.c, f64), t(lp.lc, f64), t(lp.uc, f64), t(lp.lv, f64),
                             t(lp.uv, f64))
 r = p.solve(pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6, max_iters=20000))
+# tensors of the wrong length are refused before anything is copied
+short = []
+for k in ("row_ptr", "col", "val", "c", "lc", "uc", "lv", "uv"):
+    a = {kk: np.asarray(getattr(lp, kk)) for kk in ("row_ptr", "col", "val", "c", "lc", "uc",
+                                                    "lv", "uv")}
+    a[k] = a[k][:-1]
+    ts = [t(a["row_ptr"], i32), t(a["col"], i32)] + [t(a[kk], f64) for kk in
+                                                   ("val", "c", "lc", "uc", "lv", "uv")]
+    try:
+        pd.Problem.from_tensors(lp.m, lp.n, *ts)
+        short.append((k, "accepted"))
+    except ValueError:
+        short.append((k, "refused"))
 print(json.dumps({"status": r["status_name"], "iterations": r["iterations"],
-                  "x": r["x"].tolist()}))
+                  "x": r["x"].tolist(), "short": short}))
 """
 
 
@@ -119,3 +132,4 @@ def test_torch_tensors_give_the_host_problem():
                                                                   max_iters=20000))
     assert got["status"] == r["status_name"] and got["iterations"] == r["iterations"]
     assert np.array_equal(np.array(got["x"]), r["x"])
+    assert got["short"] and all(v == "refused" for _, v in got["short"]), got["short"]
