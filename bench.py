@@ -77,23 +77,51 @@ def algorithmic_bytes(m, n, nnz):
     return dual, primal
 
 
+def host_identity():
+    """CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
 def cpu_baseline(lp, steps):
+    """The FP64 oracle as it stands, single-threaded, on the preconditioned LP
+    (10 Ruiz rounds + Pock-Chambolle, as the GPU path runs it): `steps`
+    accepted adaptive steps (Algorithm 2, rejected attempts included), with
+    the oracle's KKT passes counted over the sample."""
     import oracle
     t0 = time.perf_counter()
-    s = oracle.Solver(lp, oracle.Params(), scale=False)
-    log(f"oracle initialized in {time.perf_counter() - t0:.1f}s; timing {steps} steps")
+    s = oracle.Solver(lp, oracle.Params(), scale=True)
+    t_setup = time.perf_counter() - t0
+    log(f"oracle preconditioned and initialized in {t_setup:.1f}s; timing {steps} steps")
+    p0 = s.counters()["kkt_passes"]
     t0 = time.perf_counter()
     for _ in range(steps):
         s.step()
     dt = time.perf_counter() - t0
-    return {"value": steps / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{steps} adaptive PDHG steps (Algorithm 2, accepted steps incl. any "
-                       f"rejected attempts) of the single-threaded FP64 oracle on the same "
-                       f"{lp.m}x{lp.n} LP (unscaled; restart/termination checks excluded); "
-                       f"{dt:.1f} s")}
+    passes = s.counters()["kkt_passes"] - p0
+    out = {"value": steps / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
+           "kkt_passes_per_s": passes / dt,
+           "sample": (f"{steps} adaptive PDHG steps (Algorithm 2, accepted steps incl. any "
+                      f"rejected attempts) of the single-threaded FP64 oracle on the same "
+                      f"{lp.m}x{lp.n} LP after its preconditioning (restart/termination checks "
+                      f"excluded); {dt:.1f} s timed, {t_setup:.1f} s of preconditioning before")}
+    out.update(host_identity())
+    return out
 
 
-def batch_section(pd, count, loop_n):
+def batch_section(pd, count, loop_n, cap):
     """Batched solver on the planted batch workload: `count` LPs with m ~ U{200..20000},
     n = 1.5 m, 8 distinct rows per column, relative KKT tolerance 1e-6, against
     pdlp_solve looped over a seeded sample of the same instances."""
@@ -104,7 +132,7 @@ def batch_section(pd, count, loop_n):
     lps = [lpgen.batch_lp(i, m, n) for i, (m, n) in enumerate(sizes)]
     nnz = sum(lp.nnz for lp in lps)
     log(f"batch: generated {count} LPs ({nnz} nonzeros) in {time.perf_counter() - t0:.1f}s")
-    prm = pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6, max_iters=200000, graphs=GRAPHS)
+    prm = pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6, max_iters=cap, graphs=GRAPHS)
     b = pd.Batch(lps)
     t0 = time.perf_counter()
     res = b.solve(prm, want_solution=False)
@@ -115,30 +143,40 @@ def batch_section(pd, count, loop_n):
         status[r["status_name"]] = status.get(r["status_name"], 0) + 1
     log(f"batch: solved in {tb:.2f}s {status} {st}")
     b.close()
+    # the loop leg on equal terms: problems created (uploaded, scaled) before the
+    # timed region, as the batch's are
     rng = np.random.default_rng(2025)
     idx = rng.choice(count, size=min(loop_n, count), replace=False)
+    probs = [pd.Problem(lps[i], prm) for i in idx]
     t0 = time.perf_counter()
-    loop_it = 0
-    for i in idx:
-        p = pd.Problem(lps[i])
-        loop_it += p.solve(prm)["iterations"]
-        p.close()
+    loop_it, loop_ok = 0, 0
+    for p in probs:
+        r = p.solve(prm)
+        loop_it += r["iterations"]
+        loop_ok += r["status_name"] == "OPTIMAL"
     tl = time.perf_counter() - t0
-    log(f"batch: loop of {len(idx)} pdlp_solve in {tl:.2f}s")
+    for p in probs:
+        p.close()
+    log(f"batch: loop of {len(idx)} pdlp_solve in {tl:.2f}s ({loop_ok} optimal)")
+    n_opt = status.get("OPTIMAL", 0)
+    stragglers = [{"instance": i, "m": sizes[i][0], "n": sizes[i][1],
+                   "status": r["status_name"], "iterations": r["iterations"]}
+                  for i, r in enumerate(res) if r["status_name"] != "OPTIMAL"]
     return {
         "workload": (f"{count} planted LPs, m ~ U{{200..20000}}, n = 1.5 m, 8 rows per column, "
-                     f"{nnz} nonzeros in total; relative KKT 1e-6, iteration cap 200000"),
-        "lps_per_s": count / tb, "seconds": tb, "status": status,
+                     f"{nnz} nonzeros in total; relative KKT 1e-6, iteration cap {cap}"),
+        "lps_per_s": count / tb, "optimal_lps_per_s": n_opt / tb, "seconds": tb,
+        "status": status, "not_optimal": stragglers,
         "iters_per_s_aggregate": st["total_iterations"] / tb,
         "max_iterations": st["max_iterations"], "total_iterations": st["total_iterations"],
         "rounds": st["rounds"], "step_seconds": st["step_seconds"],
         "check_seconds": st["check_seconds"],
-        "loop_sample": int(len(idx)), "loop_lps_per_s": len(idx) / tl,
-        "loop_iters_per_s": loop_it / tl,
+        "loop_sample": int(len(idx)), "loop_optimal": int(loop_ok),
+        "loop_lps_per_s": len(idx) / tl, "loop_iters_per_s": loop_it / tl,
         "speedup_lps": (count / tb) / (len(idx) / tl),
-        "note": ("lps_per_s = instances / wall time of one pdlp_batch_solve on resident inputs "
-                 "(set by the slowest instance); loop figures time pdlp_solve (creation included) "
-                 "on a seeded random sample"),
+        "note": ("lps_per_s = instances / wall time of one pdlp_batch_solve; loop figures time "
+                 "pdlp_solve over a seeded random sample of the same instances; both legs "
+                 "start from problems already created on the GPU (creation excluded from both)"),
     }
 
 
@@ -249,8 +287,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-count", type=int, default=1024,
                     help="instances of the batched-solver measurement (0 skips it)")
-    ap.add_argument("--batch-loop", type=int, default=16,
+    ap.add_argument("--batch-loop", type=int, default=48,
                     help="instances solved one by one for the loop comparison")
+    ap.add_argument("--batch-cap", type=int, default=200_000,
+                    help="iteration cap per instance of the batched-solver measurement")
     ap.add_argument("--unroll-count", type=int, default=256,
                     help="instances of the differentiable-layer measurement (0 skips it)")
     ap.add_argument("--unroll-k", type=int, default=500)
@@ -290,6 +330,7 @@ def main():
         log(f"warmup {w}: k={r['iterations']} gap={r['rel_gap']:.3e} pres={r['primal_res_rel']:.2e}")
     state.kernel_stats(reset=True)
     k0 = r["iterations"] if args.warmup else 0
+    passes0 = r["kkt_passes"] if args.warmup else 0
     polish_iters = 0
     status = "ITERATION_LIMIT"
     steps_done = 0
@@ -315,10 +356,12 @@ def main():
     avg_primal = ks["primal_ms"] / max(ks["primal_launches"], 1)
     gbs_dual = b_dual / (avg_dual * 1e-3) / 1e9 if avg_dual > 0 else 0.0
     gbs_primal = b_primal / (avg_primal * 1e-3) / 1e9 if avg_primal > 0 else 0.0
+    seg = ks.get("primal_gather_ms", 0.0) > 0.0
+    primal_name = "k_seg_gather_primal+k_seg_primal" if seg else "k_spmv_primal"
     if ks["dual_ms"] >= ks["primal_ms"]:
         dom = ("k_spmv_dual", gbs_dual, avg_dual, b_dual, ks["dual_launches"])
     else:
-        dom = ("k_spmv_primal", gbs_primal, avg_primal, b_primal, ks["primal_launches"])
+        dom = (primal_name, gbs_primal, avg_primal, b_primal, ks["primal_launches"])
     pair_gbs = (b_dual + b_primal) / ((avg_dual + avg_primal) * 1e-3) / 1e9
     # achievable device rates: streaming copy, and random FP64 gathers from
     # an array the size of each product's gathered vector
@@ -353,14 +396,18 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": dom[1] / HBM_PEAK_GBS,
-            "traffic": (TRAFFIC_RECORD[dom[0]] if hot_source_hash() == TRAFFIC_RECORD["hot_source"]
-                        else None),
+            "traffic": (TRAFFIC_RECORD.get(dom[0])
+                        if hot_source_hash() == TRAFFIC_RECORD["hot_source"] else None),
             "avg_launch_ms": dom[2],
             "algorithmic_bytes_per_launch": dom[3],
             "launches": dom[4],
         },
         "spmv_pair": {"achieved_gbs": pair_gbs, "frac": pair_gbs / HBM_PEAK_GBS,
                       "dual_ms": avg_dual, "primal_ms": avg_primal,
+                      "primal_gather_ms": (ks.get("primal_gather_ms", 0.0)
+                                           / max(ks["primal_launches"], 1)),
+                      "primal_product": ("two-phase (segmented gathers of y')" if seg
+                                         else "one pass"),
                       "dual_gbs": gbs_dual, "primal_gbs": gbs_primal},
         "device_rates": {
             "copy_gbs": rates_n["copy_gbs"],
@@ -372,12 +419,12 @@ def main():
             "dual_gather_floor_ms": nnz / rates_n["gather_gps"] / 1e6,
             "primal_gather_floor_ms": nnz / rates_m["gather_gps"] / 1e6,
         },
-        "kkt_passes_per_s": iters / elapsed,
+        "kkt_passes_per_s": (r["kkt_passes"] - passes0) / elapsed,
         "setup_s": setup_s,
         "check_ms_per_step": ks["check_ms"] / max(steps_done, 1),
     }
     if args.batch_count > 0:
-        out["batched"] = batch_section(pd, args.batch_count, args.batch_loop)
+        out["batched"] = batch_section(pd, args.batch_count, args.batch_loop, args.batch_cap)
     if args.unroll_count > 0:
         out["unroll"] = unroll_section(pd, args.unroll_count, args.unroll_k)
     if args.tol_sweep:

@@ -104,6 +104,13 @@ typedef struct pdlp_params {
                                  short-row blocks of A and A^T sorted by column (22 bytes per
                                  nonzero) where that cuts the cache lines a wave gathers from;
                                  0 leaves it out.  Results are identical either way. */
+    int32_t segmented_gathers;/* single problems: the product A~^T y' of every step in two
+                                 phases (y' cut into 2 MB segments, each gathered by one XCD
+                                 while it sits in that XCD's L2; then the pair sums staged per
+                                 row block and the primal step run on them).  -1 (default):
+                                 when y' exceeds 32 MB; 1 always; 0 never.  Rows of at most 64
+                                 nonzeros are summed exactly as by the one-pass product; longer
+                                 rows per segment, then over the segments. */
 } pdlp_params;
 
 /* Result of a solve.  x, y, r are caller buffers of length n, m, n (or NULL);
@@ -257,6 +264,8 @@ typedef struct pdlp_kernel_stats {
     int64_t dual_launches, primal_launches, attempts;
     double dual_ms, primal_ms, decide_ms, standalone_primal_ms;
     double check_ms;          /* host wall time spent at block boundaries */
+    double primal_gather_ms;  /* part of primal_ms spent in the gather phase of the two-phase
+                                 product (0 when the one-pass product runs) */
 } pdlp_kernel_stats;
 int pdlp_state_kernel_stats(pdlp_state *s, pdlp_kernel_stats *stats, int32_t reset);
 

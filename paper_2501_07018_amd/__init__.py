@@ -48,7 +48,8 @@ class Params(C.Structure):
                 ("detect_infeasibility", C.c_int32), ("eps_infeasible", C.c_double),
                 ("restart_period", C.c_int64), ("fixed_step_size", C.c_double),
                 ("fixed_primal_weight", C.c_double), ("graphs", C.c_int32),
-                ("stream_block", C.c_int32), ("sorted_gathers", C.c_int32)]
+                ("stream_block", C.c_int32), ("sorted_gathers", C.c_int32),
+                ("segmented_gathers", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -79,7 +80,7 @@ class KernelStats(C.Structure):
     _fields_ = [("dual_launches", C.c_int64), ("primal_launches", C.c_int64),
                 ("attempts", C.c_int64), ("dual_ms", C.c_double), ("primal_ms", C.c_double),
                 ("decide_ms", C.c_double), ("standalone_primal_ms", C.c_double),
-                ("check_ms", C.c_double)]
+                ("check_ms", C.c_double), ("primal_gather_ms", C.c_double)]
 
 
 class DeviceRates(C.Structure):

@@ -60,6 +60,32 @@ __device__ __forceinline__ void write_partials(double (&v)[NV], double *lds, dou
     }
 }
 
+__device__ __forceinline__ int32_t wave_incl_scan_i32(int32_t v) {
+    const int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t t = __shfl_up(v, o, 64);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Exclusive prefix sum over the kThreads threads of a workgroup (in thread
+// order); returns the block total through *total.
+__device__ __forceinline__ int32_t block_excl_scan_i32(int32_t v, int32_t *lds, int32_t *total) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t inc = wave_incl_scan_i32(v);
+    __syncthreads();
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    int32_t before = 0, all = 0;
+    for (int q = 0; q < kWaveRows; ++q) {
+        if (q < w) before += lds[q];
+        all += lds[q];
+    }
+    *total = all;
+    return before + inc - v;
+}
+
 __device__ __forceinline__ double clampd(double v, double lo, double hi) {
     return v < lo ? lo : (v > hi ? hi : v);
 }
@@ -186,14 +212,11 @@ __device__ __forceinline__ T stream_load(const T *p) {
 // with the row's product s; end(b, acc, red) is called after the block
 // (per-block partial sums in the batched solver).
 template <int NACC, class Epi>
-__device__ __forceinline__ void stream_spmv(const DCsr &A, Epi &epi, double (&acc)[NACC],
-                                            double *prod, double *red) {
+__device__ __forceinline__ void stream_block(const DCsr &A, Epi &epi, int b, double (&acc)[NACC],
+                                             double *prod, double *red) {
     constexpr int kPer = kStage / kThreads;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int nb = epi.count(A);
-    for (int bi = blockIdx.x; bi < nb; bi += gridDim.x) {
-        const int b = epi.block(bi);
-        if (!epi.begin(b)) continue;
+    {
         const double *__restrict__ x = epi.src();
         const int r0 = A.blk[b], r1 = A.blk[b + 1];
         const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
@@ -283,7 +306,85 @@ __device__ __forceinline__ void stream_spmv(const DCsr &A, Epi &epi, double (&ac
             block_reduce<1>(t, red);
             if (threadIdx.x == 0) epi.apply(r0, t[0], acc, epi.prefetch(r0));
         }
+    }
+}
+
+template <int NACC, class Epi>
+__device__ __forceinline__ void stream_spmv(const DCsr &A, Epi &epi, double (&acc)[NACC],
+                                            double *prod, double *red) {
+    const int nb = epi.count(A);
+    for (int bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+        const int b = epi.block(bi);
+        if (!epi.begin(b)) continue;
+        stream_block<NACC>(A, epi, b, acc, prod, red);
         epi.end(b, acc, red);
+    }
+}
+
+// Phase 2 of the two-phase product (SegCsr): the pair sums of each row block
+// of sg.P are read from their 2S runs of Q and staged in LDS at their slots;
+// then one lane per row sums the row's pairs in slot order and runs the row
+// work, as in the short-row path of stream_spmv.  Every block of sg.P fits
+// the stage (at most kStage pairs).  lds_i holds 2 * kThreads + kWaveRows ints.
+template <int NACC, class Epi>
+__device__ __forceinline__ void staged_spmv(const SegCsr &sg, Epi &epi, double (&acc)[NACC],
+                                            double *prod, int32_t *lds_i) {
+    const DCsr &M = sg.P;
+    const int S = 2 * sg.S;  // runs per block
+    int32_t *run_lo = lds_i, *run_at = lds_i + kThreads;
+    const int nb = epi.count(M);
+    for (int bi = blockIdx.x; bi < nb; bi += gridDim.x) {
+        const int b = epi.block(bi);
+        if (!epi.begin(b)) continue;
+        const int r0 = M.blk[b], r1 = M.blk[b + 1];
+        const int p0 = M.row_ptr[r0];
+        const int len = M.row_ptr[r1] - p0;
+        const int rr = r0 + threadIdx.x;
+        int ra = 0, rz = 0;
+        typename Epi::Pre pre{};
+        if (rr < r1) {
+            ra = M.row_ptr[rr] - p0;
+            rz = M.row_ptr[rr + 1] - p0;
+            pre = epi.prefetch(rr);
+        }
+        // runs of the block: start in Q and position in the block's pair list
+        int32_t cnt = 0, lo = 0;
+        if ((int)threadIdx.x < S) {
+            lo = sg.qoff[(int64_t)b * S + threadIdx.x];
+            cnt = sg.qoff[(int64_t)(b + 1) * S + threadIdx.x] - lo;
+        }
+        int32_t total = 0;
+        const int32_t at = block_excl_scan_i32(cnt, lds_i + 2 * kThreads, &total);
+        if ((int)threadIdx.x < S) {
+            run_lo[threadIdx.x] = lo;
+            run_at[threadIdx.x] = at;
+        }
+        __syncthreads();
+        for (int q = threadIdx.x; q < len; q += kThreads) {
+            // the last run that starts at or before q holds it
+            int a = 0, z = S - 1;
+            while (a < z) {
+                const int mid = (a + z + 1) >> 1;
+                if (run_at[mid] <= q) a = mid;
+                else z = mid - 1;
+            }
+            const int64_t qi = (int64_t)run_lo[a] + (q - run_at[a]);
+            prod[stream_load(sg.slot + qi)] = stream_load(sg.Q + qi);
+        }
+        __syncthreads();
+        if (rr < r1) {
+            double s = 0.0;
+            for (int q = ra; q < rz; ++q) s += prod[q];
+            epi.apply(rr, s, acc, pre);
+        }
+        for (int r = rr + kThreads; r < r1; r += kThreads) {
+            const int a = M.row_ptr[r] - p0, z = M.row_ptr[r + 1] - p0;
+            double s = 0.0;
+            for (int q = a; q < z; ++q) s += prod[q];
+            epi.apply(r, s, acc, epi.prefetch(r));
+        }
+        __syncthreads();
+        epi.end(b, acc, nullptr);
     }
 }
 

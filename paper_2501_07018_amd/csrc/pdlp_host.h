@@ -198,6 +198,8 @@ inline void check_params(const pdlp_params &p) {
         !(p.stream_block >= 64 && p.stream_block <= pdlp::kStage))
         invalid("stream_block must be 0, -1 or in [64, 2048]");
     if (p.sorted_gathers != 0 && p.sorted_gathers != 1) invalid("sorted_gathers must be 0 or 1");
+    if (p.segmented_gathers < -1 || p.segmented_gathers > 1)
+        invalid("segmented_gathers must be -1, 0 or 1");
     if (p.restart_period > 0) {
         if (!(p.fixed_step_size > 0.0) || !std::isfinite(p.fixed_step_size))
             invalid("restart_period > 0 needs a finite fixed_step_size > 0");
@@ -227,6 +229,7 @@ struct pdlp_problem {
     hipStream_t stream = nullptr;
     pdlp::host::Arena arena;
     pdlp::DCsr A, AT;
+    pdlp::SegCsr segT;  // two-phase layout of A^T (built for long y; S = 0 otherwise)
     double *d1 = nullptr, *d2 = nullptr;                                // scaling
     double *c = nullptr, *lc = nullptr, *uc = nullptr, *lv = nullptr, *uv = nullptr;  // original
     double *cs = nullptr, *lcs = nullptr, *ucs = nullptr, *lvs = nullptr, *uvs = nullptr;

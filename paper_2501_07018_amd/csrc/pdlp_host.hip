@@ -54,7 +54,8 @@ using pdlp::Vecs;
 // `breaks` (sorted, optional) lists rows at which a block must start: the
 // first rows of the instances of a batch.
 std::vector<int32_t> make_blocks(const int32_t *rp, int32_t rows,
-                                 const std::vector<int32_t> *breaks, int32_t stage) {
+                                 const std::vector<int32_t> *breaks, int32_t stage,
+                                 int32_t max_rows = pdlp::kMaxBlockRows) {
     std::vector<int32_t> blk;
     blk.push_back(0);
     int32_t r = 0;
@@ -74,7 +75,7 @@ std::vector<int32_t> make_blocks(const int32_t *rp, int32_t rows,
         } else {
             const int32_t start = r;
             int64_t nz = 0;
-            while (r < lim && r - start < pdlp::kMaxBlockRows) {
+            while (r < lim && r - start < max_rows) {
                 const int32_t l = L(r);
                 if (l > pdlp::kMedRow || nz + l > stage) break;
                 nz += l;
@@ -235,6 +236,271 @@ std::vector<int32_t> order_cols(const std::vector<int32_t> &cdeg, const int32_t 
     }
     return order;
 }
+
+// Two-phase layout (pdlp::SegCsr) of M for products with a gathered vector
+// of M.cols entries.  Segments: S = 8 * ceil(cols / 2^18 / 8) (at most 128)
+// contiguous index ranges balanced by nonzeros (each at most 2^19 indices
+// unless the balance needs more), segment s belonging to XCD s mod 8.
+// Pairs: a row of at most kMedRow nonzeros gives one pair per nonzero in
+// stored order; a longer row one pair per segment it touches, in segment
+// order, its entries in stored order.  Phase-2 blocks: consecutive rows with
+// at most kStage pairs and kMaxBlockRows rows.  Q order: single-entry pairs
+// first, then the others; inside each class by segment, then block, then
+// position in the block.  Phase-1 work of segment s (chunks of at most
+// kStage singles, then blocks of G) is listed for XCD s mod 8.  Values are
+// taken from M.val on the device (call after scaling).
+void build_segmented(pdlp_problem *P, const DCsr &M, pdlp::SegCsr &sg) {
+    hipStream_t s = P->stream;
+    const int32_t R = M.rows, C = M.cols;
+    const int64_t nnz = M.nnz;
+    if (nnz == 0 || R == 0 || C == 0) return;
+    std::vector<int32_t> rp((size_t)R + 1), col((size_t)nnz);
+    HIPCHECK(hipMemcpyAsync(rp.data(), M.row_ptr, sizeof(int32_t) * rp.size(),
+                            hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(col.data(), M.col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+#ifndef PDLP_SEG_LEN_LOG2
+#define PDLP_SEG_LEN_LOG2 18
+#endif
+    constexpr int64_t kSegLen = 1 << PDLP_SEG_LEN_LOG2;
+    constexpr int kMaxSeg = 128;
+    int S = (int)std::min<int64_t>(kMaxSeg, (C + kSegLen - 1) / kSegLen);
+    S = std::min(kMaxSeg, (S + 7) / 8 * 8);
+    if (C < S) return;
+    // segments balanced by nonzeros
+    std::vector<int64_t> cnt((size_t)C, 0);
+    for (int64_t e = 0; e < nnz; ++e) cnt[(size_t)col[(size_t)e]] += 1;
+    std::vector<uint8_t> seg_of((size_t)C);
+    {
+        int64_t rem = nnz;
+        int32_t i = 0;
+        for (int k = 0; k < S; ++k) {
+            const int32_t lo = i;
+            if (k == S - 1) {
+                i = C;
+            } else {
+                const int64_t target = rem / (S - k);
+                const int64_t max_end =
+                    std::min<int64_t>((int64_t)C - (S - 1 - k), (int64_t)i + 2 * kSegLen);
+                int64_t e = 0;
+                while (i < max_end && (e == 0 || e + cnt[(size_t)i] <= target)) e += cnt[(size_t)i++];
+                rem -= e;
+            }
+            for (int32_t q = lo; q < i; ++q) seg_of[(size_t)q] = (uint8_t)k;
+        }
+    }
+    // pairs in pair-space order (rows in order)
+    std::vector<int32_t> prp((size_t)R + 1, 0);
+    std::vector<uint8_t> pseg;
+    std::vector<int32_t> pn;               // entries per pair
+    std::vector<int32_t> ent((size_t)nnz); // entries in pair-space order
+    pseg.reserve((size_t)nnz);
+    pn.reserve((size_t)nnz);
+    {
+        std::vector<int32_t> sc((size_t)S), so((size_t)S);
+        int64_t k = 0;
+        for (int32_t r = 0; r < R; ++r) {
+            const int32_t a = rp[(size_t)r], z = rp[(size_t)r + 1];
+            if (z - a <= pdlp::kMedRow) {
+                for (int32_t e = a; e < z; ++e) {
+                    pseg.push_back(seg_of[(size_t)col[(size_t)e]]);
+                    pn.push_back(1);
+                    ent[(size_t)k++] = e;
+                }
+            } else {
+                std::fill(sc.begin(), sc.end(), 0);
+                for (int32_t e = a; e < z; ++e) sc[seg_of[(size_t)col[(size_t)e]]] += 1;
+                int32_t acc = 0;
+                for (int q = 0; q < S; ++q) {
+                    so[(size_t)q] = acc;
+                    acc += sc[(size_t)q];
+                    if (sc[(size_t)q] > 0) {
+                        pseg.push_back((uint8_t)q);
+                        pn.push_back(sc[(size_t)q]);
+                    }
+                }
+                for (int32_t e = a; e < z; ++e)
+                    ent[(size_t)(k + so[seg_of[(size_t)col[(size_t)e]]]++)] = e;
+                k += z - a;
+            }
+            prp[(size_t)r + 1] = (int32_t)pseg.size();
+        }
+    }
+    const int64_t NP = (int64_t)pseg.size();
+    std::vector<int64_t> pent((size_t)NP + 1, 0);
+    for (int64_t p = 0; p < NP; ++p) pent[(size_t)p + 1] = pent[(size_t)p] + pn[(size_t)p];
+    // phase-2 blocks
+    std::vector<int32_t> blk2{0};
+    for (int32_t r = 0; r < R;) {
+        const int32_t first = r;
+        while (r < R && r - first < pdlp::kMaxBlockRows &&
+               prp[(size_t)r + 1] - prp[(size_t)first] <= pdlp::kStage)
+            ++r;
+        blk2.push_back(r);
+    }
+    const int32_t NB = (int32_t)blk2.size() - 1;
+    // Q order, run starts and slots; class c = 0 single-entry pairs, 1 the others
+    const int RS = 2 * S;  // runs per block
+    std::vector<int64_t> ccount((size_t)RS, 0);
+    for (int64_t p = 0; p < NP; ++p) ccount[(size_t)((pn[(size_t)p] > 1) * S + pseg[(size_t)p])] += 1;
+    std::vector<int64_t> cstart((size_t)RS + 1, 0);
+    for (int q = 0; q < RS; ++q) cstart[(size_t)q + 1] = cstart[(size_t)q] + ccount[(size_t)q];
+    const int64_t N1 = cstart[(size_t)S];
+    std::vector<int32_t> qoff(((size_t)NB + 1) * RS);
+    std::vector<int64_t> next(cstart.begin(), cstart.end() - 1);
+    std::vector<int32_t> pair_of_q((size_t)NP);
+    std::vector<uint16_t> slot((size_t)NP);
+    for (int32_t b = 0; b < NB; ++b) {
+        for (int q = 0; q < RS; ++q) qoff[(size_t)b * RS + q] = (int32_t)next[(size_t)q];
+        const int32_t p0 = prp[(size_t)blk2[(size_t)b]], p1 = prp[(size_t)blk2[(size_t)b + 1]];
+        for (int32_t p = p0; p < p1; ++p) {
+            const int64_t qi = next[(size_t)((pn[(size_t)p] > 1) * S + pseg[(size_t)p])]++;
+            pair_of_q[(size_t)qi] = p;
+            slot[(size_t)qi] = (uint16_t)(p - p0);
+        }
+    }
+    for (int q = 0; q < RS; ++q) qoff[(size_t)NB * RS + q] = (int32_t)next[(size_t)q];
+    // singles: gathered index and source entry
+    std::vector<int32_t> c1((size_t)std::max<int64_t>(N1, 1));
+    std::vector<int64_t> src1((size_t)std::max<int64_t>(N1, 1));
+    for (int64_t qi = 0; qi < N1; ++qi) {
+        const int32_t e = ent[(size_t)pent[(size_t)pair_of_q[(size_t)qi]]];
+        c1[(size_t)qi] = col[(size_t)e];
+        src1[(size_t)qi] = e;
+    }
+    // G: one row per multi-entry pair in Q order
+    const int64_t N2 = NP - N1;
+    const int64_t nnz2 = nnz - N1;
+    std::vector<int32_t> grp((size_t)N2 + 1, 0), gcol((size_t)std::max<int64_t>(nnz2, 1));
+    std::vector<int64_t> gsrc((size_t)std::max<int64_t>(nnz2, 1));
+    {
+        int64_t k = 0;
+        for (int64_t t = 0; t < N2; ++t) {
+            const int32_t p = pair_of_q[(size_t)(N1 + t)];
+            for (int64_t u = pent[(size_t)p]; u < pent[(size_t)p + 1]; ++u) {
+                const int32_t e = ent[(size_t)u];
+                gcol[(size_t)k] = col[(size_t)e];
+                gsrc[(size_t)k] = e;
+                ++k;
+            }
+            grp[(size_t)t + 1] = (int32_t)k;
+        }
+    }
+    std::vector<int32_t> gbreaks((size_t)S);
+    for (int q = 0; q < S; ++q) gbreaks[(size_t)q] = (int32_t)(cstart[(size_t)S + q] - N1);
+    std::vector<int32_t> gblk = make_blocks(grp.data(), (int32_t)N2, &gbreaks, pdlp::kStage);
+    const int32_t GB = (int32_t)gblk.size() - 1;
+    // phase-1 work items by XCD: per segment, its singles in equal chunks, then
+    // its G blocks; each segment's chunks and blocks are padded (-1) to a
+    // multiple of the XCD's workgroups (kWgPerXcd: the persistent grid of
+    // 2048 on 8 XCDs), so that every workgroup of the XCD takes the same
+    // number of chunks and of blocks of a segment and the XCD's workgroups
+    // move from one segment to the next together (its L2 then holds one
+    // segment of v at a time)
+    constexpr int64_t kWgPerXcd = PDLP_STREAM_GRID_CAP / 8;
+    std::vector<int32_t> chunks;
+    std::vector<std::vector<int32_t>> lx(8);
+    {
+        auto pad = [&](std::vector<int32_t> &L) {
+            while ((int64_t)L.size() % kWgPerXcd) L.push_back(-1);
+        };
+        int32_t gb = 0;
+        for (int q = 0; q < S; ++q) {
+            auto &L = lx[(size_t)(q % 8)];
+            const int64_t lo = cstart[(size_t)q], hi = cstart[(size_t)q + 1];
+            if (hi > lo) {
+                int64_t nch = (hi - lo + pdlp::kStage - 1) / pdlp::kStage;
+                nch = (nch + kWgPerXcd - 1) / kWgPerXcd * kWgPerXcd;
+                const int64_t csz = (hi - lo + nch - 1) / nch;
+                for (int64_t k = 0; k < nch; ++k) {
+                    const int64_t a = std::min(hi, lo + k * csz), z = std::min(hi, a + csz);
+                    if (z > a) {
+                        L.push_back(-2 - (int32_t)(chunks.size() / 2));
+                        chunks.push_back((int32_t)a);
+                        chunks.push_back((int32_t)z);
+                    } else {
+                        L.push_back(-1);
+                    }
+                }
+            }
+            const int32_t gend = q + 1 < S ? gbreaks[(size_t)q + 1] : (int32_t)N2;
+            const size_t before = L.size();
+            for (; gb < GB && gblk[(size_t)gb] < gend; ++gb) L.push_back(gb);
+            if (L.size() > before) pad(L);
+        }
+    }
+    size_t T = 0;
+    for (auto &v : lx) T = std::max(T, v.size());
+    std::vector<int32_t> glist(8 * T, -1);
+    for (size_t t = 0; t < T; ++t)
+        for (int x = 0; x < 8; ++x)
+            if (t < lx[(size_t)x].size()) glist[t * 8 + (size_t)x] = lx[(size_t)x][t];
+    // upload
+    Arena &a = P->arena;
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes) HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    };
+    sg.n1 = N1;
+    int32_t *c1d = a.dev<int32_t>(std::max<int64_t>(N1, 1));
+    double *v1d = a.dev<double>(std::max<int64_t>(N1, 1));
+    up(c1d, c1.data(), sizeof(int32_t) * N1);
+    sg.c1 = c1d;
+    sg.v1 = v1d;
+    int32_t *chd = a.dev<int32_t>(std::max<size_t>(chunks.size(), 1));
+    up(chd, chunks.data(), sizeof(int32_t) * chunks.size());
+    sg.chunk = chd;
+    DCsr &G = sg.G;
+    G.rows = (int32_t)N2;
+    G.cols = C;
+    G.nnz = nnz2;
+    G.row_ptr = a.dev<int32_t>((size_t)N2 + 1);
+    G.col = a.dev<int32_t>(std::max<int64_t>(nnz2, 1));
+    G.val = a.dev<double>(std::max<int64_t>(nnz2, 1));
+    G.nblk = GB;
+    G.blk = a.dev<int32_t>(gblk.size());
+    G.grid = 0;  // G is walked through glist only
+    up(G.row_ptr, grp.data(), sizeof(int32_t) * grp.size());
+    up(G.col, gcol.data(), sizeof(int32_t) * nnz2);
+    up(G.blk, gblk.data(), sizeof(int32_t) * gblk.size());
+    int32_t *gl = a.dev<int32_t>(std::max<size_t>(glist.size(), 1));
+    up(gl, glist.data(), sizeof(int32_t) * glist.size());
+    sg.glist = gl;
+    sg.glen = (int32_t)glist.size();
+    sg.grid1 = (int32_t)std::min<size_t>(glist.size(), PDLP_STREAM_GRID_CAP);
+    sg.Q = a.dev<double>(NP);
+    uint16_t *sl = a.dev<uint16_t>(NP);
+    up(sl, slot.data(), sizeof(uint16_t) * NP);
+    sg.slot = sl;
+    int32_t *qo = a.dev<int32_t>(qoff.size());
+    up(qo, qoff.data(), sizeof(int32_t) * qoff.size());
+    sg.qoff = qo;
+    DCsr &PP = sg.P;
+    PP.rows = R;
+    PP.cols = C;
+    PP.nnz = NP;
+    PP.row_ptr = a.dev<int32_t>((size_t)R + 1);
+    up(PP.row_ptr, prp.data(), sizeof(int32_t) * prp.size());
+    PP.nblk = NB;
+    PP.blk = a.dev<int32_t>(blk2.size());
+    up(PP.blk, blk2.data(), sizeof(int32_t) * blk2.size());
+    PP.grid = std::min<int32_t>(NB, PDLP_STREAM_GRID_CAP);
+    {
+        Arena tmp;
+        int64_t *src = tmp.dev<int64_t>(std::max<int64_t>(std::max(N1, nnz2), 1));
+        if (N1 > 0) {
+            up(src, src1.data(), sizeof(int64_t) * N1);
+            HIPCHECK(pdlp::launch_take(s, N1, src, M.val, v1d));
+            HIPCHECK(hipStreamSynchronize(s));
+        }
+        if (nnz2 > 0) {
+            up(src, gsrc.data(), sizeof(int64_t) * nnz2);
+            HIPCHECK(pdlp::launch_take(s, nnz2, src, M.val, G.val));
+            HIPCHECK(hipStreamSynchronize(s));
+        }
+    }
+    sg.S = S;
+}
+
 // [hot-path layout end]
 
 }  // namespace
@@ -439,6 +705,13 @@ enum { TERM_NONE = 0, TERM_FULL = 1, TERM_PRIMAL = 2, TERM_DUAL = 3 };
 enum { RUN_OK = 0, RUN_LIMIT = 1, RUN_TIME = 2, RUN_NUMERR = 3, RUN_PINF = 4, RUN_DINF = 5,
        RUN_POLISHED = 10 };
 
+// A~^T y as the step kernels compute it: the two-phase product when it is
+// built, else the one-pass stream product.
+hipError_t spmv_t(pdlp_problem *P, hipStream_t s, const double *y, double *out) {
+    return P->segT.S ? pdlp::launch_seg_plain(s, P->segT, y, out)
+                     : pdlp::launch_spmv_plain(s, P->AT, y, out);
+}
+
 // One PDLP run (the main run or a feasibility-polishing run) on the device.
 struct Engine {
     pdlp_problem *P = nullptr;
@@ -493,7 +766,7 @@ struct Engine {
         ctrl_d = arena.dev<Ctrl>(1);
         ctrl_h = arena.host<Ctrl>(1);
         gd = P->A.grid;
-        gpf = P->AT.grid;
+        gpf = P->segT.S ? P->segT.P.grid : P->AT.grid;
         gps = red_grid(n);
         part_dual = arena.dev<double>(2 * (size_t)std::max(gd, 1));
         part_pf = arena.dev<double>(std::max(gpf, 1));
@@ -536,7 +809,7 @@ struct Engine {
         HIPCHECK(pdlp::launch_copy(s(), n, x_src, it.X[0]));
         HIPCHECK(pdlp::launch_copy(s(), m, y_src, it.Y[0]));
         HIPCHECK(pdlp::launch_spmv_plain(s(), P->A, it.X[0], it.AX[0]));
-        HIPCHECK(pdlp::launch_spmv_plain(s(), P->AT, it.Y[0], it.ATY[0]));
+        HIPCHECK(spmv_t(P, s(), it.Y[0], it.ATY[0]));
         HIPCHECK(pdlp::launch_copy(s(), n, it.X[0], x0));
         HIPCHECK(pdlp::launch_copy(s(), m, it.Y[0], y0));
         HIPCHECK(pdlp::launch_fill(s(), n, it.sx, 0.0));
@@ -568,21 +841,31 @@ struct Engine {
         mu_c_prev = INFINITY;
     }
 
-    // One step attempt: four predicated launches; with profiling each launch
-    // records its own start/stop events (8 per attempt).
+    // One step attempt: four predicated launches (five with the two-phase
+    // A^T y'); with profiling each launch records its own start/stop events
+    // (kEv per attempt).
+    static constexpr int kEv = 10;
     void enqueue_attempt_on(hipStream_t st) {
         HIPCHECK(pdlp::launch_primal(st, n, v, it, ctrl_d, part_ps, gps, nullptr));
         HIPCHECK(pdlp::launch_spmv_dual(st, P->A, v, it, ctrl_d, part_dual, nullptr));
         HIPCHECK(pdlp::launch_step_decide(st, ctrl_d, part_dual, gd, part_ps, gps, part_pf, gpf,
                                           nullptr));
-        HIPCHECK(pdlp::launch_spmv_primal(st, P->AT, v, it, ctrl_d, part_pf, nullptr));
+        if (P->segT.S)
+            HIPCHECK(pdlp::launch_seg_primal(st, P->segT, v, it, ctrl_d, part_pf, nullptr));
+        else
+            HIPCHECK(pdlp::launch_spmv_primal(st, P->AT, v, it, ctrl_d, part_pf, nullptr));
     }
     void enqueue_attempt(hipEvent_t *e) {
         HIPCHECK(pdlp::launch_primal(s(), n, v, it, ctrl_d, part_ps, gps, e ? e + 0 : nullptr));
         HIPCHECK(pdlp::launch_spmv_dual(s(), P->A, v, it, ctrl_d, part_dual, e ? e + 2 : nullptr));
         HIPCHECK(pdlp::launch_step_decide(s(), ctrl_d, part_dual, gd, part_ps, gps, part_pf, gpf,
                                           e ? e + 4 : nullptr));
-        HIPCHECK(pdlp::launch_spmv_primal(s(), P->AT, v, it, ctrl_d, part_pf, e ? e + 6 : nullptr));
+        if (P->segT.S)
+            HIPCHECK(pdlp::launch_seg_primal(s(), P->segT, v, it, ctrl_d, part_pf,
+                                             e ? e + 6 : nullptr));
+        else
+            HIPCHECK(pdlp::launch_spmv_primal(s(), P->AT, v, it, ctrl_d, part_pf,
+                                              e ? e + 6 : nullptr));
     }
 
     float ev_ms(int a, int b) {
@@ -606,7 +889,7 @@ struct Engine {
             if (n_att > 4096) n_att = 4096;
             const long long att0 = c.attempts, acc0 = c.block_acc;
             if (profile) {
-                while ((long long)ev.size() < 8 * n_att) {
+                while ((long long)ev.size() < kEv * n_att) {
                     hipEvent_t e;
                     HIPCHECK(hipEventCreate(&e));
                     ev.push_back(e);
@@ -614,7 +897,7 @@ struct Engine {
             }
             if (profile || !use_graphs) {
                 for (long long a = 0; a < n_att; ++a)
-                    enqueue_attempt(profile ? &ev[8 * a] : nullptr);
+                    enqueue_attempt(profile ? &ev[kEv * a] : nullptr);
             } else {
                 const bool same = graphs_v.c == v.c && graphs_v.lc == v.lc && graphs_v.uc == v.uc &&
                                   graphs_v.lv == v.lv && graphs_v.uv == v.uv;
@@ -628,11 +911,15 @@ struct Engine {
             if (profile) {
                 const long long ran = c.attempts - att0;
                 for (long long a = 0; a < ran; ++a) {
-                    const int b = (int)(8 * a);
+                    const int b = (int)(kEv * a);
                     kst.standalone_primal_ms += ev_ms(b, b + 1);
                     kst.dual_ms += ev_ms(b + 2, b + 3);
                     kst.decide_ms += ev_ms(b + 4, b + 5);
                     kst.primal_ms += ev_ms(b + 6, b + 7);
+                    if (P->segT.S) {
+                        kst.primal_gather_ms += ev_ms(b + 6, b + 7);
+                        kst.primal_ms += ev_ms(b + 8, b + 9);
+                    }
                 }
                 kst.attempts += ran;
                 kst.dual_launches += ran;
@@ -653,7 +940,7 @@ struct Engine {
         HIPCHECK(pdlp::launch_average(s(), n, it.sx, seta, xb));
         HIPCHECK(pdlp::launch_average(s(), m, it.sy, seta, yb));
         HIPCHECK(pdlp::launch_spmv_plain(s(), P->A, xb, axb));
-        HIPCHECK(pdlp::launch_spmv_plain(s(), P->AT, yb, atyb));
+        HIPCHECK(spmv_t(P, s(), yb, atyb));
         kkt_passes += 1;
     }
 
@@ -694,7 +981,7 @@ struct Engine {
             HIPCHECK(pdlp::launch_cert_point(s(), m, xs ? n : 0, it.X[cur], it.X[cur ^ 1],
                                              it.Y[cur], it.Y[cur ^ 1], P->lc, P->uc, P->lv, P->uv,
                                              cx, cy));
-            HIPCHECK(pdlp::launch_spmv_plain(s(), P->AT, cy, caty));
+            HIPCHECK(spmv_t(P, s(), cy, caty));
             cpy = cy;
             cpaty = caty;
         } else {
@@ -1138,6 +1425,7 @@ void pdlp_params_default(pdlp_params *p) {
     p->fixed_primal_weight = 1.0;
     p->graphs = 1;
     p->sorted_gathers = 1;
+    p->segmented_gathers = -1;
 }
 
 }  // extern "C"
@@ -1261,6 +1549,9 @@ pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *r
                 P->blkT = choose_blocks(P, P->AT, trp.data(), col_breaks, prm.stream_block);
             }
             precondition(P, prm);
+            const bool seg = prm.segmented_gathers == 1 ||
+                             (prm.segmented_gathers < 0 && (int64_t)m * 8 > (int64_t)(32 << 20));
+            if (seg && !row_breaks && !col_breaks) build_segmented(P, P->AT, P->segT);
         } catch (...) {
             delete P;
             throw;
@@ -1455,7 +1746,8 @@ int pdlp_spmv(const pdlp_problem *pc, int32_t transpose, int32_t scaled, const d
         HIPCHECK(hipEventCreate(&e0));
         HIPCHECK(hipEventCreate(&e1));
         HIPCHECK(hipEventRecord(e0, s));
-        for (int r = 0; r < repeat; ++r) HIPCHECK(pdlp::launch_spmv_plain(s, M, xi, yo));
+        for (int r = 0; r < repeat; ++r)
+            HIPCHECK(transpose ? spmv_t(p, s, xi, yo) : pdlp::launch_spmv_plain(s, M, xi, yo));
         HIPCHECK(hipEventRecord(e1, s));
         HIPCHECK(hipEventSynchronize(e1));
         float el = 0.f;

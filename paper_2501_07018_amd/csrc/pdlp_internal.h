@@ -55,6 +55,43 @@ struct DCsr {
     const uint8_t *sblk = nullptr;
 };
 
+// Two-phase product out = M v for a gathered vector v too large for the
+// caches: v's index range is cut into S segments of a few MB (balanced by
+// nonzeros, S a multiple of 8, at most 128), and segment s is worked by XCD
+// s mod 8 only, so that its slice of v stays in that XCD's L2 while it is
+// gathered.  Pairs: a row of at most kMedRow nonzeros makes one pair per
+// nonzero, a longer row one pair per segment it touches (its entries there
+// in stored order).
+//   phase 1 (gather): Q receives the sum of every pair -- single-entry pairs
+//     (Q[0, n1)) as plain products in chunks of consecutive entries, pairs of
+//     two or more entries (Q[n1, ...)) as rows of the CSR matrix G; the work
+//     items of segment s are listed for XCD s mod 8 (glist);
+//   phase 2 (stage): per row block of P, the block's pairs are read from
+//     their 2S runs of Q (run (b, c, s) = Q[qoff[b*2S+c*S+s] ..
+//     qoff[(b+1)*2S+c*S+s]) for the single (c = 0) and multi-entry (c = 1)
+//     pairs of segment s), staged in LDS at their slot (the pair's position
+//     in the block: rows in order and, inside a row, its entries' stored
+//     order or its pairs' segment order), and each row is summed in that
+//     order before the row work.
+// A row of at most kMedRow nonzeros is thus summed exactly as by the single
+// pass (same products, same order).
+struct SegCsr {
+    int32_t S = 0;                    // segments (0: not built)
+    int64_t n1 = 0;                   // single-entry pairs
+    const int32_t *c1 = nullptr;      // their gathered index
+    const double *v1 = nullptr;       // and value
+    const int32_t *chunk = nullptr;   // singles chunk k: Q[chunk[2k], chunk[2k+1])
+    DCsr G;                           // multi-entry pairs: row t -> Q[n1 + t]
+    const int32_t *glist = nullptr;   // work items by XCD, glist[t*8 + x]: G block (>= 0),
+                                      // singles chunk -2-k, or nothing (-1)
+    int32_t glen = 0;
+    int32_t grid1 = 0;                // workgroups of phase 1 (a multiple of 8)
+    double *Q = nullptr;              // pair sums
+    const uint16_t *slot = nullptr;   // slot of pair q in its phase-2 block
+    const int32_t *qoff = nullptr;    // (P.nblk + 1) * 2S run starts
+    DCsr P;                           // phase 2: rows of M, row_ptr over pairs, blocks
+};
+
 // Scaled problem vectors seen by the iteration.
 struct Vecs {
     const double *c, *lc, *uc, *lv, *uv;
@@ -157,6 +194,12 @@ hipError_t launch_step_decide(hipStream_t s, Ctrl *ctrl, const double *part_dual
 hipError_t launch_spmv_primal(hipStream_t s, const DCsr &AT, Vecs v, Iter it, const Ctrl *ctrl,
                               double *part, hipEvent_t *ev = nullptr);
 hipError_t launch_flush_sy(hipStream_t s, int m, Iter it, Ctrl *ctrl);
+// A^T y' + primal row work in two phases (SegCsr); ev = {start, stop} of
+// phase 1 then phase 2 (four events)
+hipError_t launch_seg_primal(hipStream_t s, const SegCsr &sg, Vecs v, Iter it, const Ctrl *ctrl,
+                             double *part, hipEvent_t *ev = nullptr);
+// plain two-phase product out = M v (both phases)
+hipError_t launch_seg_plain(hipStream_t s, const SegCsr &sg, const double *v, double *out);
 
 // plain products and vector helpers
 hipError_t launch_spmv_plain(hipStream_t s, const DCsr &A, const double *x, double *out);

@@ -89,7 +89,109 @@ PDLP_STREAM_KERNEL void k_spmv_primal(DCsr AT, Vecs v, Iter it,
     if (next) write_partials<1>(acc, red, part);
 }
 
+// Two-phase A^T y' (SegCsr): phase 1 sums the (row, segment) pairs of G,
+// whose blocks are dealt to XCDs by segment through sg.glist (workgroup w
+// of the persistent grid, a multiple of 8, runs on XCD w mod 8 and visits
+// list positions = w mod 8); phase 2 stages the pair sums per row block and
+// runs the primal row work.
+#ifndef PDLP_SEG_NT_Q
+#define PDLP_SEG_NT_Q 0
+#endif
+struct SegGatherEpi : NoPrefetch {
+    const int32_t *list;
+    int32_t len;
+    const double *gsrc;
+    double *out;
+    __device__ __forceinline__ int count(const DCsr &) const { return len; }
+    __device__ __forceinline__ int block(int bi) const { return list[bi]; }
+    __device__ __forceinline__ bool begin(int b) const { return b >= 0; }
+    __device__ __forceinline__ const double *src() const { return gsrc; }
+    template <int N>
+    __device__ __forceinline__ void apply(int r, double s, double (&)[N], const Pre &) const {
+#if PDLP_SEG_NT_Q
+        __builtin_nontemporal_store(s, out + r);
+#else
+        out[r] = s;
+#endif
+    }
+    template <int N>
+    __device__ __forceinline__ void end(int, double (&)[N], double *) {}
+};
+
+__device__ __forceinline__ void seg_gather(const SegCsr &sg, const double *__restrict__ v) {
+    constexpr int kPer = kStage / kThreads;
+    __shared__ double prod[kStage];
+    __shared__ double red[kThreads / 64];
+    SegGatherEpi epi;
+    epi.list = sg.glist;
+    epi.len = sg.glen;
+    epi.gsrc = v;
+    epi.out = sg.Q + sg.n1;
+    double acc[1] = {0.0};
+    for (int bi = blockIdx.x; bi < sg.glen; bi += gridDim.x) {
+        const int item = sg.glist[bi];
+        if (item >= 0) {
+            stream_block<1>(sg.G, epi, item, acc, prod, red);
+        } else if (item <= -2) {
+            // single-entry pairs: plain products, kPer gathers in flight per lane
+            const int k = -2 - item;
+            const int lo = sg.chunk[2 * k], hi = sg.chunk[2 * k + 1];
+            int ci[kPer];
+            double vv[kPer];
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int q = lo + i * kThreads + (int)threadIdx.x;
+                ci[i] = q < hi ? stream_load(sg.c1 + q) : 0;
+                vv[i] = q < hi ? stream_load(sg.v1 + q) : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < kPer; ++i) {
+                const int q = lo + i * kThreads + (int)threadIdx.x;
+#if PDLP_SEG_NT_Q
+                if (q < hi) __builtin_nontemporal_store(vv[i] * v[ci[i]], sg.Q + q);
+#else
+                if (q < hi) sg.Q[q] = vv[i] * v[ci[i]];
+#endif
+            }
+        }
+    }
+}
+
+PDLP_STREAM_KERNEL void k_seg_gather_primal(SegCsr sg, Iter it, const Ctrl *ctrl) {
+    if (!ctrl->run_at) return;
+    seg_gather(sg, it.Y[ctrl->cur]);
+}
+
+PDLP_STREAM_KERNEL void k_seg_primal(SegCsr sg, Vecs v, Iter it, const Ctrl *ctrl, double *part) {
+    if (!ctrl->run_at) return;
+    __shared__ double prod[kStage];
+    __shared__ int32_t lds_i[2 * kThreads + kWaveRows];
+    __shared__ double red[kThreads / 64];
+    const int cur = ctrl->cur;
+    const int next = !ctrl->stop;
+    PrimalEpi epi;
+    epi.gsrc = nullptr;
+    epi.row = PrimalRow{it.X[cur], v.c, v.lv, v.uv, it.ATY[cur], it.X[cur ^ 1], it.sx,
+                        ctrl->eta_used, ctrl->eta / ctrl->omega, next};
+    double acc[1] = {0.0};
+    staged_spmv<1>(sg, epi, acc, prod, lds_i);
+    if (next) write_partials<1>(acc, red, part);
+}
+
 // [hot-path kernels end]
+
+// Plain two-phase product out = M v (SegCsr; row sums as in k_seg_primal).
+PDLP_STREAM_KERNEL void k_seg_gather_plain(SegCsr sg, const double *v) { seg_gather(sg, v); }
+
+PDLP_STREAM_KERNEL void k_seg_plain(SegCsr sg, double *out) {
+    __shared__ double prod[kStage];
+    __shared__ int32_t lds_i[2 * kThreads + kWaveRows];
+    PlainEpi epi;
+    epi.gsrc = nullptr;
+    epi.out = out;
+    double acc[1] = {0.0};
+    staged_spmv<1>(sg, epi, acc, prod, lds_i);
+}
 
 // Standalone primal step: x' = proj_X(x - tau (c - A^T y)).
 __global__ __launch_bounds__(kThreads) void k_primal(int n, Vecs v, Iter it, const Ctrl *ctrl,
@@ -461,32 +563,6 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(int64_t n, const uint3
     __syncthreads();
     if (tile < ntiles)
         for (int d = lane; d < kRadixBins; d += 64) counts[(int64_t)d * ntiles + tile] = hist[w][d];
-}
-
-__device__ __forceinline__ int32_t wave_incl_scan_i32(int32_t v) {
-    const int lane = threadIdx.x & 63;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
-    return v;
-}
-
-// Exclusive prefix sum over the kThreads threads of a workgroup (in thread
-// order); returns the block total through *total.
-__device__ __forceinline__ int32_t block_excl_scan_i32(int32_t v, int32_t *lds, int32_t *total) {
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int32_t inc = wave_incl_scan_i32(v);
-    __syncthreads();
-    if (lane == 63) lds[w] = inc;
-    __syncthreads();
-    int32_t before = 0, all = 0;
-    for (int q = 0; q < kWaveRows; ++q) {
-        if (q < w) before += lds[q];
-        all += lds[q];
-    }
-    *total = all;
-    return before + inc - v;
 }
 
 // sums[b] = sum of chunk b (kScanChunk consecutive counts)
@@ -1212,6 +1288,21 @@ hipError_t launch_spmv_primal(hipStream_t s, const DCsr &AT, Vecs v, Iter it, co
 hipError_t launch_flush_sy(hipStream_t s, int m, Iter it, Ctrl *ctrl) {
     if (m > 0) hipLaunchKernelGGL(k_flush_sy, dim3(grid_for(m)), dim3(kThreads), 0, s, m, it, ctrl);
     hipLaunchKernelGGL(k_clear_pending, dim3(1), dim3(64), 0, s, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_primal(hipStream_t s, const SegCsr &sg, Vecs v, Iter it, const Ctrl *ctrl,
+                             double *part, hipEvent_t *ev) {
+    if (sg.grid1 > 0) PDLP_LAUNCH(k_seg_gather_primal, sg.grid1, ev, s, sg, it, ctrl);
+    if (sg.P.grid > 0) PDLP_LAUNCH(k_seg_primal, sg.P.grid, ev ? ev + 2 : nullptr, s, sg, v, it, ctrl, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_plain(hipStream_t s, const SegCsr &sg, const double *v, double *out) {
+    if (sg.grid1 > 0)
+        hipLaunchKernelGGL(k_seg_gather_plain, dim3(sg.grid1), dim3(kThreads), 0, s, sg, v);
+    if (sg.P.grid > 0)
+        hipLaunchKernelGGL(k_seg_plain, dim3(sg.P.grid), dim3(kThreads), 0, s, sg, out);
     return hipGetLastError();
 }
 
