@@ -226,6 +226,23 @@ int pdlp_problem_get_scaled(const pdlp_problem *p, double *d1, double *d2, doubl
 int pdlp_spmv(const pdlp_problem *p, int32_t transpose, int32_t scaled, const double *x_host,
               double *out_host, int32_t repeat, double *ms);
 
+/*
+ * pdlp_spmv without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  x_dev (length n, or m when transpose = 1) and out_dev (m, or n)
+ * are caller buffers in GPU memory, in the caller's order; scaled as for
+ * pdlp_spmv.  The work is enqueued on hip_stream (NULL: the problem's stream)
+ * and the call returns without waiting; out_dev is valid once the stream has
+ * reached it.  Staging of the permuted vectors lives in a fixed device array
+ * of 2^23 doubles (64 MiB) per GPU, kept until the process ends: m + n above
+ * 2^23 is rejected with INVALID_ARGUMENT.  Every call on a GPU shares that
+ * array (and the problem's own product buffers), so calls that overlap on one
+ * GPU race; nothing in the array needs clearing between calls.  Allocates
+ * nothing: no hipMalloc, hipFree or allocating library routine.
+ */
+int pdlp_spmv_noalloc(const pdlp_problem *p, int32_t transpose, int32_t scaled,
+                      const double *x_dev, double *out_dev, void *hip_stream);
+
 void pdlp_params_default(pdlp_params *params);
 
 /*

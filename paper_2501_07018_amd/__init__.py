@@ -122,7 +122,7 @@ EXPORTS = ("pdlp_problem_create", "pdlp_problem_create_device", "pdlp_problem_de
            "pdlp_batch_destroy", "pdlp_batch_dims", "pdlp_batch_solve", "pdlp_batch_get_stats",
            "pdlp_unroll_create", "pdlp_unroll_destroy", "pdlp_unroll_set_data",
            "pdlp_unroll_forward", "pdlp_unroll_replay", "pdlp_unroll_backward",
-           "pdlp_unroll_get_tape", "pdlp_unroll_get_stats")
+           "pdlp_unroll_get_tape", "pdlp_unroll_get_stats", "pdlp_spmv_noalloc")
 
 
 def lib() -> C.CDLL:
@@ -144,6 +144,7 @@ def lib() -> C.CDLL:
     L.pdlp_problem_dims.argtypes = [vp, I32, I32, C.POINTER(C.c_int64)]
     L.pdlp_problem_get_scaled.argtypes = [vp, D, D, D, D, D, D, D, D]
     L.pdlp_spmv.argtypes = [vp, C.c_int32, C.c_int32, D, D, C.c_int32, D]
+    L.pdlp_spmv_noalloc.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
     L.pdlp_params_default.argtypes = [C.POINTER(Params)]
     L.pdlp_params_default.restype = None
     L.pdlp_solve.argtypes = [vp, C.POINTER(Params), D, D, C.POINTER(Result)]
@@ -262,6 +263,14 @@ def pdlp_spmv(h, x, transpose=False, scaled=True, repeat=1):
     _check(lib().pdlp_spmv(h, int(bool(transpose)), int(bool(scaled)), _d(x), _d(out),
                            int(repeat), C.byref(ms)))
     return out, ms.value
+
+
+def pdlp_spmv_noalloc(h, x_dev, out_dev, transpose=False, scaled=True, stream=None):
+    """Product on device buffers (integer addresses) with no allocation; asynchronous on
+    `stream` (a HIP stream handle, None for the problem's stream)."""
+    _check(lib().pdlp_spmv_noalloc(h, int(bool(transpose)), int(bool(scaled)),
+                                   C.c_void_p(x_dev), C.c_void_p(out_dev),
+                                   C.c_void_p(stream) if stream else None))
 
 
 def pdlp_solve(h, params: Params | None = None, x0=None, y0=None) -> dict:

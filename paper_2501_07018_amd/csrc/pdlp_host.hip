@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -2064,6 +2065,67 @@ int pdlp_state_kernel_stats(pdlp_state *S, pdlp_kernel_stats *st, int32_t reset)
         if (!S || !st) invalid("NULL argument");
         *st = S->E->kst;
         if (reset) std::memset(&S->E->kst, 0, sizeof(pdlp_kernel_stats));
+    });
+}
+
+}  // extern "C"
+
+// --------------------------------------------- products without allocation
+//
+// Staging of pdlp_spmv_noalloc: a file-scope device array (one copy per GPU,
+// held until the process ends).  Host code never passes the array's name to
+// a kernel: its address on each device is looked up once, with that device
+// current, and kept per device.
+constexpr int64_t kNoAllocDoubles = int64_t(1) << 23;  // 64 MiB: m + n <= 8,388,608
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+double *scratch_on_current_device() {
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        throw LibError(PDLP_ERR_HIP, "device index " + std::to_string(dev) + " out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw LibError(PDLP_ERR_HIP, "no device address for the staging array");
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int pdlp_spmv_noalloc(const pdlp_problem *pc, int32_t transpose, int32_t scaled,
+                      const double *x_dev, double *out_dev, void *hip_stream) {
+    return guarded([&] {
+        auto *p = const_cast<pdlp_problem *>(pc);
+        if (!p) invalid("NULL problem");
+        const int64_t in_len = transpose ? p->m : p->n, out_len = transpose ? p->n : p->m;
+        if ((in_len > 0 && !x_dev) || (out_len > 0 && !out_dev)) invalid("NULL vector");
+        if (in_len + out_len > kNoAllocDoubles)
+            invalid("pdlp_spmv_noalloc: m + n = " + std::to_string(in_len + out_len) +
+                    " exceeds the staging capacity of " + std::to_string(kNoAllocDoubles) +
+                    " doubles; use pdlp_spmv");
+        double *st = scratch_on_current_device();
+        hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : p->stream;
+        const DCsr &M = transpose ? p->AT : p->A;
+        const double *din = transpose ? p->d1 : p->d2;  // original = D1^-1 A~ D2^-1
+        const double *dout = transpose ? p->d2 : p->d1;
+        const int32_t *pin = transpose ? p->row_order : p->col_order;
+        const int32_t *pout = transpose ? p->col_order : p->row_order;
+        double *xi = st, *yo = st + in_len;
+        HIPCHECK(pdlp::launch_gather(s, in_len, pin, x_dev, xi));
+        if (!scaled) HIPCHECK(pdlp::launch_scale_div(s, in_len, xi, din, xi));
+        HIPCHECK(transpose ? spmv_t(p, s, xi, yo) : pdlp::launch_spmv_plain(s, M, xi, yo));
+        if (!scaled) HIPCHECK(pdlp::launch_scale_div(s, out_len, yo, dout, yo));
+        HIPCHECK(pdlp::launch_scatter(s, out_len, pout, yo, out_dev));
     });
 }
 
