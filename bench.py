@@ -77,6 +77,59 @@ def algorithmic_bytes(m, n, nnz):
     return dual, primal
 
 
+def verify_point(lp, x, y, r):
+    """Relative residuals of eq. "rescaled-termination-criteria" and the objective of a
+    returned point, recomputed in numpy from the LP as generated (independent of the
+    library and the oracle)."""
+    import numpy as np
+    A = lp.csr()
+    ax = A @ x
+    aty = A.T @ y
+    lc, uc, c = lp.lc, lp.uc, lp.c
+    fin_l, fin_u = np.isfinite(lc), np.isfinite(uc)
+    al = np.where(fin_l & (lc != 0), np.abs(lc), 0.0)
+    au = np.where(fin_u & (uc != 0), np.abs(uc), 0.0)
+    q = np.where((al > 0) | (au > 0), np.maximum(al, au), 1.0)
+    viol = np.maximum(np.maximum(np.where(fin_l, lc - ax, 0.0), np.where(fin_u, ax - uc, 0.0)), 0.0)
+    w = np.where(c != 0, np.abs(c), 1.0)
+    out = {"primal_res_rel_numpy": float(np.max(viol / q)) if lp.m else 0.0,
+           "dual_res_rel_numpy": float(np.max(np.abs(c - aty - r) / w)) if lp.n else 0.0,
+           "bounds_violation": float(max(np.max(lp.lv - x), np.max(x - lp.uv), 0.0)),
+           "objective": float(c @ x + lp.obj_offset)}
+    if lp.p_star is not None:
+        out["p_star"] = float(lp.p_star)
+        out["objective_rel_err"] = abs(out["objective"] - lp.p_star) / max(abs(lp.p_star), 1e-300)
+    return out
+
+
+def solve_section(lp, state, r, solve_wall, polish_iters, budget):
+    """Continue the bench's solve (Algorithm 1 with the checks, polishing at
+    k = 100, 200, 400, ... once the average's gap is below 1%) until the
+    termination criteria hold or `budget` seconds pass; the returned point is
+    then checked in numpy."""
+    t0 = time.perf_counter()
+    chunk = 1280
+    while r["status_name"] == "ITERATION_LIMIT" and time.perf_counter() - t0 < budget:
+        tc = time.perf_counter()
+        # the point of a polished termination exists only in the call that found it
+        r = state.solve(chunk, want_solution=True)
+        solve_wall += time.perf_counter() - tc
+        polish_iters += r["polish_iters"]
+        log(f"solve: k={r['iterations']} gap={r['rel_gap']:.3e} pres={r['primal_res_rel']:.2e} "
+            f"dres={r['dual_res_rel']:.2e} polish_attempts={r['polish_attempts']} "
+            f"status={r['status_name']} ({solve_wall:.1f}s)")
+    out = {"status": r["status_name"], "iterations": r["iterations"],
+           "polish_attempts": r["polish_attempts"], "polish_iterations": polish_iters,
+           "polished": r["polished"], "restarts": r["restarts"], "kkt_passes": r["kkt_passes"],
+           "seconds_to_solution": solve_wall, "rel_gap": r["rel_gap"],
+           "primal_res_rel": r["primal_res_rel"], "dual_res_rel": r["dual_res_rel"],
+           "note": ("seconds_to_solution = wall time of all iteration blocks from the initial "
+                    "point (setup excluded); residuals recomputed in numpy from the generated LP")}
+    if r["status_name"] == "OPTIMAL" and "x" in r:
+        out.update(verify_point(lp, r["x"], r["y"], r["r"]))
+    return out
+
+
 def host_identity():
     """CPU model and the cores this process may use."""
     model = "unknown"
@@ -118,6 +171,23 @@ def cpu_baseline(lp, steps):
                       f"{lp.m}x{lp.n} LP after its preconditioning (restart/termination checks "
                       f"excluded); {dt:.1f} s timed, {t_setup:.1f} s of preconditioning before")}
     out.update(host_identity())
+    # all host cores: the OpenMP build of the same oracle source (row shards,
+    # Section 5 "Multithreading"), same LP and sample
+    try:
+        oracle.set_threaded(True)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or out["usable_cores"]
+        s2 = oracle.Solver(lp, oracle.Params(), precond=(s.scaled.val, s.d1, s.d2))
+        p0 = s2.counters()["kkt_passes"]
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s2.step()
+        dt2 = time.perf_counter() - t0
+        out["all_cores"] = {"value": steps / dt2, "unit": "iters/s", "cores": threads,
+                            "kkt_passes_per_s": (s2.counters()["kkt_passes"] - p0) / dt2,
+                            "sample": f"the same {steps} steps with the OpenMP build; {dt2:.1f} s"}
+        log(f"oracle all cores ({threads} threads): {steps / dt2:.3f} iters/s")
+    finally:
+        oracle.set_threaded(False)
     return out
 
 
@@ -294,6 +364,9 @@ def main():
     ap.add_argument("--unroll-count", type=int, default=256,
                     help="instances of the differentiable-layer measurement (0 skips it)")
     ap.add_argument("--unroll-k", type=int, default=500)
+    ap.add_argument("--solve-budget", type=float, default=0.0,
+                    help="after the timed steps, continue the same solve to its tolerances "
+                         "(1% gap, polishing to 1e-8) for at most this many seconds")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch step attempts one by one (same results; for tracing tools)")
     ap.add_argument("--tol-sweep", action="store_true",
@@ -325,8 +398,11 @@ def main():
     log(f"problem on the GPU (upload, transpose, scaling, init) in {setup_s:.2f}s")
 
     step_k = 64
+    solve_wall = 0.0
     for w in range(args.warmup):
+        tw = time.perf_counter()
         r = state.solve(step_k)
+        solve_wall += time.perf_counter() - tw
         log(f"warmup {w}: k={r['iterations']} gap={r['rel_gap']:.3e} pres={r['primal_res_rel']:.2e}")
     state.kernel_stats(reset=True)
     k0 = r["iterations"] if args.warmup else 0
@@ -343,6 +419,7 @@ def main():
             status = r["status_name"]
             break
     elapsed = time.perf_counter() - t0
+    solve_wall += elapsed
     ks = state.kernel_stats()
     iters = r["iterations"] - k0 + polish_iters
     log(f"timed {steps_done} steps: {iters} iterations in {elapsed:.3f}s; last: k={r['iterations']} "
@@ -423,6 +500,9 @@ def main():
         "setup_s": setup_s,
         "check_ms_per_step": ks["check_ms"] / max(steps_done, 1),
     }
+    if args.solve_budget > 0:
+        out["solve_to_tolerance"] = solve_section(lp, state, r, solve_wall, polish_iters,
+                                                  args.solve_budget)
     if args.batch_count > 0:
         out["batched"] = batch_section(pd, args.batch_count, args.batch_loop, args.batch_cap)
     if args.unroll_count > 0:

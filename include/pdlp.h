@@ -441,6 +441,35 @@ int pdlp_unroll_replay(pdlp_unroll *u, double *x, int64_t *signature);
 int pdlp_unroll_backward(pdlp_unroll *u, const double *gx, double *gc, double *glc,
                          double *guc, double *gval);
 
+/* Tangent-linear map (forward mode) of the same linearization as
+ * pdlp_unroll_backward: dx (sum n, original units) receives the directional
+ * derivative of x_K along the data direction (dc (sum n), dlc, duc (sum m),
+ * dval (sum nnz, CSR order), original units; NULL parts are zero), with the
+ * recorded decisions and the replay's selections held fixed.  For any gx,
+ * <dx, gx> equals the pairing of the direction with pdlp_unroll_backward's
+ * gradients of <gx, x_K> up to rounding (the dot-product test).  Needs a
+ * forward pass. */
+int pdlp_unroll_tangent(pdlp_unroll *u, const double *dc, const double *dlc, const double *duc,
+                        const double *dval, double *dx);
+
+/* Device-memory variants of set_data, forward, backward and tangent, for
+ * callers whose tensors live on the GPU (e.g. torch): the same arguments as
+ * GPU pointers (same lengths and layouts; the data checks of set_data run
+ * on the device).  The work runs on the library's stream after the work
+ * queued on hip_stream so far (an event join; NULL or the library's own
+ * stream: no join) and the call returns when its outputs are written, so
+ * they may be used on hip_stream at once.  Errors as the host variants. */
+int pdlp_unroll_set_data_device(pdlp_unroll *u, const double *c_dev, const double *lc_dev,
+                                const double *uc_dev, const double *val_dev, void *hip_stream);
+int pdlp_unroll_forward_device(pdlp_unroll *u, const pdlp_params *params, int64_t K,
+                               int32_t ckpt_every, double *x_dev, void *hip_stream);
+int pdlp_unroll_backward_device(pdlp_unroll *u, const double *gx_dev, double *gc_dev,
+                                double *glc_dev, double *guc_dev, double *gval_dev,
+                                void *hip_stream);
+int pdlp_unroll_tangent_device(pdlp_unroll *u, const double *dc_dev, const double *dlc_dev,
+                               const double *duc_dev, const double *dval_dev, double *dx_dev,
+                               void *hip_stream);
+
 /* Recorded decisions, count x K each (instance-major): eta and omega of
  * every accepted step; restart[i K + k] = 0, 1 (to the current iterate) or
  * 2 (to the average) for a restart right after step k. */
@@ -453,6 +482,7 @@ typedef struct pdlp_unroll_stats {
     double backward_seconds;         /* pdlp_unroll_backward, after copying gx in, before copying out */
     double backward_replay_seconds;  /* its segment replays */
     double backward_reverse_seconds; /* its reverse steps */
+    double tangent_seconds;          /* pdlp_unroll_tangent, after copying the direction in */
 } pdlp_unroll_stats;
 int pdlp_unroll_get_stats(const pdlp_unroll *u, pdlp_unroll_stats *stats);
 

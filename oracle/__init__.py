@@ -27,16 +27,23 @@ D = C.POINTER(C.c_double)
 I32 = C.POINTER(C.c_int32)
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2 -ffp-contract=off)."""
+OMP_LIB_PATH = os.path.join(HERE, "liboracle_pdlp_omp.so")
+
+
+def build(force: bool = False, threaded: bool = False) -> str:
+    """Compile the oracle with gcc (-O2 -ffp-contract=off).  threaded: the
+    OpenMP build of the same source used only by the all-cores CPU baseline
+    (row-sharded products, Section 5 "Multithreading"); the plain build is
+    the oracle the tests use."""
+    path = OMP_LIB_PATH if threaded else LIB_PATH
     newest = max(os.path.getmtime(f) for f in SRCS + [os.path.join(HERE, "pdlp_oracle.h")])
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < newest:
-        tmp = LIB_PATH + ".tmp"
+    if force or not os.path.exists(path) or os.path.getmtime(path) < newest:
+        tmp = path + ".tmp"
         cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-Wall",
-               "-fPIC", "-shared", "-o", tmp, *SRCS, "-lm"]
+               "-Wno-unknown-pragmas", *(["-fopenmp"] if threaded else []), "-fPIC", "-shared", "-o", tmp, *SRCS, "-lm"]
         subprocess.run(cmd, check=True, cwd=HERE)
-        os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+        os.replace(tmp, path)
+    return path
 
 
 class _LP(C.Structure):
@@ -115,14 +122,27 @@ class _KKT(C.Structure):
                 ("dual_res_abs", C.c_double), ("dual_res_rel", C.c_double)]
 
 
-_lib = None
+_libs = {}
+_threaded = False
+
+
+def set_threaded(on: bool) -> None:
+    """Route later oracle calls to the OpenMP build (all-cores CPU baseline) or
+    back to the plain build."""
+    global _threaded
+    _threaded = bool(on)
 
 
 def lib():
-    global _lib
-    if _lib is None:
-        build()
-        L = C.CDLL(LIB_PATH)
+    key = _threaded
+    if key not in _libs:
+        _libs[key] = _load(build(threaded=key))
+    return _libs[key]
+
+
+def _load(path):
+    if True:
+        L = C.CDLL(path)
         L.orc_spmv.argtypes = [C.POINTER(_LP), D, D]
         L.orc_spmv_t.argtypes = [C.POINTER(_LP), D, D]
         L.orc_precondition.argtypes = [C.c_int32, C.c_int32, I32, I32, D, C.c_int32, C.c_int32, D, D]
@@ -171,8 +191,7 @@ def lib():
         L.orc_unroll_tangent.argtypes = [C.POINTER(_LP), C.POINTER(_Tape), C.c_int64, D, D, D, D,
                                          D]
         L.orc_unroll_tangent.restype = C.c_int32
-        _lib = L
-    return _lib
+    return L
 
 
 def _d(a: np.ndarray):
@@ -332,12 +351,14 @@ class Solver:
     of :meth:`kkt` and the unscaled solution returned by :meth:`solution`.
     """
 
-    def __init__(self, lp, params: Params | None = None, scale: bool = True):
+    def __init__(self, lp, params: Params | None = None, scale: bool = True, precond=None):
         self.lp = lp
         self.params = params or Params()
         m, n = lp.m, lp.n
         self.m, self.n = m, n
-        if scale:
+        if precond is not None:      # (val, d1, d2) of an earlier precondition(lp, ...)
+            val, d1, d2 = precond
+        elif scale:
             val, d1, d2 = precondition(lp, self.params.ruiz_iters, self.params.pc)
         else:
             val, d1, d2 = np.array(lp.val, dtype=np.float64), np.ones(m), np.ones(n)

@@ -40,6 +40,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_LIMIT 1
@@ -54,6 +57,7 @@ static int is_fin(double v) { return isfinite(v); }
 
 /* out = A x, each row summed in column order starting from 0. */
 void orc_spmv(const orc_lp *lp, const double *x, double *out) {
+#pragma omp parallel for schedule(dynamic, 4096)
     for (int32_t i = 0; i < lp->m; ++i) {
         double s = 0.0;
         for (int32_t p = lp->row_ptr[i]; p < lp->row_ptr[i + 1]; ++p)
@@ -62,12 +66,52 @@ void orc_spmv(const orc_lp *lp, const double *x, double *out) {
     }
 }
 
-/* out = A^T y; each column accumulates its terms in increasing row order. */
-void orc_spmv_t(const orc_lp *lp, const double *y, double *out) {
-    for (int32_t j = 0; j < lp->n; ++j) out[j] = 0.0;
-    for (int32_t i = 0; i < lp->m; ++i)
+/* out = A^T y; each column accumulates its terms in increasing row order.
+ * The threaded build (OpenMP, for the all-cores CPU baseline only) follows
+ * the paper's multithreading scheme (Section 5): T shards of consecutive
+ * rows balanced by nonzeros, each accumulated in increasing row order into
+ * its own vector, the shard vectors then added in shard order -- the same
+ * products in a fixed order for a fixed T.  The plain build is the oracle. */
+static void spmv_t_seq(const orc_lp *lp, const double *y, double *out, int32_t r0, int32_t r1) {
+    for (int32_t i = r0; i < r1; ++i)
         for (int32_t p = lp->row_ptr[i]; p < lp->row_ptr[i + 1]; ++p)
             out[lp->col[p]] += lp->val[p] * y[i];
+}
+
+void orc_spmv_t(const orc_lp *lp, const double *y, double *out) {
+    for (int32_t j = 0; j < lp->n; ++j) out[j] = 0.0;
+#ifdef _OPENMP
+    const int T = omp_get_max_threads();
+    double *part = T > 1 ? malloc(sizeof(double) * (size_t)(T - 1) * (size_t)(lp->n + 1)) : NULL;
+    if (part) {
+        const int64_t nnz = lp->row_ptr[lp->m];
+#pragma omp parallel num_threads(T)
+        {
+            const int t = omp_get_thread_num();
+            /* shard t: rows whose first entry lies in [t nnz / T, (t+1) nnz / T) */
+            int32_t lo = 0, hi = lp->m;
+            {
+                const int64_t a = nnz * t / T, z = nnz * (t + 1) / T;
+                int32_t l = 0, h = lp->m;
+                while (l < h) { int32_t mid = l + (h - l) / 2; if (lp->row_ptr[mid] < a) l = mid + 1; else h = mid; }
+                lo = l;
+                l = 0; h = lp->m;
+                while (l < h) { int32_t mid = l + (h - l) / 2; if (lp->row_ptr[mid] < z) l = mid + 1; else h = mid; }
+                hi = t == T - 1 ? lp->m : l;
+            }
+            double *dst = t == 0 ? out : part + (size_t)(t - 1) * (size_t)(lp->n + 1);
+            if (t > 0) memset(dst, 0, sizeof(double) * (size_t)lp->n);
+            spmv_t_seq(lp, y, dst, lo, hi);
+#pragma omp barrier
+#pragma omp for schedule(static)
+            for (int32_t j = 0; j < lp->n; ++j)
+                for (int q = 1; q < T; ++q) out[j] += part[(size_t)(q - 1) * (size_t)(lp->n + 1) + j];
+        }
+        free(part);
+        return;
+    }
+#endif
+    spmv_t_seq(lp, y, out, 0, lp->m);
 }
 
 static double dot(const double *a, const double *b, int64_t len) {
@@ -246,11 +290,13 @@ double orc_dual_case(double yhat, double sigma, double lc, double uc) {
 static void pdhg_candidate(const orc_lp *lp, const orc_state *st, double eta,
                            double *xn, double *axn, double *yn, double *num, double *cross) {
     double tau = eta / st->omega, sigma = eta * st->omega;
+#pragma omp parallel for schedule(static)
     for (int32_t j = 0; j < lp->n; ++j) {
         double g = lp->c[j] - st->aty[j];
         xn[j] = clampd(st->x[j] - tau * g, lp->lv[j], lp->uv[j]);
     }
     orc_spmv(lp, xn, axn);
+#pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < lp->m; ++i) {
         double yhat = st->y[i] - sigma * (2.0 * axn[i] - st->ax[i]);
         yn[i] = orc_dual_case(yhat, sigma, lp->lc[i], lp->uc[i]);

@@ -100,7 +100,7 @@ class UnrollStats(C.Structure):
     _fields_ = [("K", C.c_int64), ("ckpt", C.c_int64), ("restarts", C.c_int64),
                 ("forward_seconds", C.c_double), ("replay_seconds", C.c_double),
                 ("backward_seconds", C.c_double), ("backward_replay_seconds", C.c_double),
-                ("backward_reverse_seconds", C.c_double)]
+                ("backward_reverse_seconds", C.c_double), ("tangent_seconds", C.c_double)]
 
 
 class StateBlob(C.Structure):
@@ -122,7 +122,9 @@ EXPORTS = ("pdlp_problem_create", "pdlp_problem_create_device", "pdlp_problem_de
            "pdlp_batch_destroy", "pdlp_batch_dims", "pdlp_batch_solve", "pdlp_batch_get_stats",
            "pdlp_unroll_create", "pdlp_unroll_destroy", "pdlp_unroll_set_data",
            "pdlp_unroll_forward", "pdlp_unroll_replay", "pdlp_unroll_backward",
-           "pdlp_unroll_get_tape", "pdlp_unroll_get_stats", "pdlp_spmv_noalloc")
+           "pdlp_unroll_get_tape", "pdlp_unroll_get_stats", "pdlp_spmv_noalloc",
+           "pdlp_unroll_tangent", "pdlp_unroll_set_data_device", "pdlp_unroll_forward_device",
+           "pdlp_unroll_backward_device", "pdlp_unroll_tangent_device")
 
 
 def lib() -> C.CDLL:
@@ -174,6 +176,11 @@ def lib() -> C.CDLL:
     L.pdlp_unroll_forward.argtypes = [vp, C.POINTER(Params), C.c_int64, C.c_int32, D]
     L.pdlp_unroll_replay.argtypes = [vp, D, I64]
     L.pdlp_unroll_backward.argtypes = [vp, D, D, D, D, D]
+    L.pdlp_unroll_tangent.argtypes = [vp, D, D, D, D, D]
+    L.pdlp_unroll_set_data_device.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.pdlp_unroll_forward_device.argtypes = [vp, C.POINTER(Params), C.c_int64, C.c_int32, vp, vp]
+    L.pdlp_unroll_backward_device.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.pdlp_unroll_tangent_device.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.pdlp_unroll_get_tape.argtypes = [vp, D, D, I32]
     L.pdlp_unroll_get_stats.argtypes = [vp, C.POINTER(UnrollStats)]
     L.pdlp_last_error.argtypes = []
@@ -463,6 +470,10 @@ def _pack(lps):
     return m, n, nnz, rp, cl, cat
 
 
+def _vp(a):
+    return None if a is None else C.c_void_p(int(a))
+
+
 class Unroll:
     """Owner of a pdlp_unroll handle: the differentiable K-step map over a batch.
 
@@ -508,6 +519,32 @@ class Unroll:
         _check(lib().pdlp_unroll_backward(self.h, _d(gx), _d(out["c"]), _d(out["lc"]),
                                           _d(out["uc"]), _d(out["val"])))
         return out
+
+    def tangent(self, dc=None, dlc=None, duc=None, dval=None):
+        """Directional derivative of x_K along a data direction (original units; None = 0)."""
+        arrs = [None if a is None else _f64(a) for a in (dc, dlc, duc, dval)]
+        dx = np.empty(self.N)
+        _check(lib().pdlp_unroll_tangent(self.h, *[_d(a) for a in arrs], _d(dx)))
+        return dx
+
+    # device-memory variants: arguments are device addresses (int) or None
+    def set_data_device(self, c=None, lc=None, uc=None, val=None, stream=None):
+        _check(lib().pdlp_unroll_set_data_device(self.h, *[_vp(a) for a in (c, lc, uc, val)],
+                                                 _vp(stream)))
+
+    def forward_device(self, K, ckpt, x_ptr, params: Params | None = None, stream=None):
+        _check(lib().pdlp_unroll_forward_device(
+            self.h, C.byref(params) if params is not None else None, int(K), int(ckpt),
+            _vp(x_ptr), _vp(stream)))
+        self.K = int(K)
+
+    def backward_device(self, gx_ptr, gc_ptr, glc_ptr, guc_ptr, gval_ptr, stream=None):
+        _check(lib().pdlp_unroll_backward_device(
+            self.h, *[_vp(a) for a in (gx_ptr, gc_ptr, glc_ptr, guc_ptr, gval_ptr)], _vp(stream)))
+
+    def tangent_device(self, dc_ptr, dlc_ptr, duc_ptr, dval_ptr, dx_ptr, stream=None):
+        _check(lib().pdlp_unroll_tangent_device(
+            self.h, *[_vp(a) for a in (dc_ptr, dlc_ptr, duc_ptr, dval_ptr, dx_ptr)], _vp(stream)))
 
     def tape(self):
         K = self.K or 0

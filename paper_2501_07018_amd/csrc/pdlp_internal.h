@@ -390,6 +390,25 @@ hipError_t launch_u_reverse(hipStream_t s, const DCsr &A, const DCsr &AT, UStepA
                             const uint8_t *seg_q, double *xb, double *yb, const double *sxb,
                             const double *syb, double *yhb, double *vb, double *gc, double *glc,
                             double *guc, double *gval);
+// one replayed step (as launch_u_step, without segment storage) and its
+// tangent: dA / dAT carry the direction's scaled values in A's pattern,
+// (dc, dlc, duc) the rest of the direction; (dx, dy, dax, daty) -> (dxn, dyn,
+// daxn, datyn), tangent sums dsx, dsy; tm*, tn* are work vectors (m, n)
+hipError_t launch_u_tangent_step(hipStream_t s, const DCsr &A, const DCsr &AT, const DCsr &dA,
+                                 const DCsr &dAT, Vecs v, UStepArgs u, const double *dc,
+                                 const double *dlc, const double *duc, const double *x,
+                                 const double *y, const double *ax, const double *aty,
+                                 double *xn, double *yn, double *axn, double *atyn, double *sx,
+                                 double *sy, const double *dx, const double *dy, const double *dax,
+                                 const double *daty, double *dxn, double *dyn, double *daxn,
+                                 double *datyn, double *dsx, double *dsy, double *tm1,
+                                 double *tm2, double *tn1, double *tn2);
+hipError_t launch_u_add(hipStream_t s, int64_t len, const double *a, const double *b, double *out);
+// bad[0] += invalid entries of new data in device memory (see ku_check_data)
+hipError_t launch_u_check_data(hipStream_t s, int64_t N, int64_t M, int64_t NZ, const double *c,
+                               const double *lc, const double *uc, const double *val,
+                               const double *cur_lc, const double *cur_uc,
+                               unsigned long long *bad);
 hipError_t launch_u_scale_values(hipStream_t s, const DCsr &A, const double *val, const double *d1,
                                  const double *d2, const int32_t *a2t, double *va, double *vt);
 hipError_t launch_u_finish(hipStream_t s, const DCsr &A, int64_t N, const double *d1,

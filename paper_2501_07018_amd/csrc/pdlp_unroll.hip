@@ -51,7 +51,17 @@ struct pdlp_unroll {
     double *sv_d, *sv_h, *zero_d;
     unsigned long long *sig_d, *sig_h;
     pdlp_unroll_stats stats{};
+    // tangent (forward-mode) buffers, allocated at the first tangent
+    Arena *tan_arena = nullptr;
+    double *dav, *datv, *dcs, *dlcs, *ducs, *dir_c, *dir_l, *dir_u, *dir_v;
+    double *tdx, *tdxn, *tdaty, *tdatyn, *tdsx, *tn1, *tn2;
+    double *tdy, *tdyn, *tdax, *tdaxn, *tdsy, *tm1, *tm2;
+    // checks of data in device memory
+    unsigned long long *bad_d = nullptr, *bad_h = nullptr;
+    hipEvent_t join = nullptr;  // orders the library's stream after a caller's stream
     ~pdlp_unroll() {
+        if (join) (void)hipEventDestroy(join);
+        delete tan_arena;
         delete tape_arena;
         delete arena;
         delete b;
@@ -63,6 +73,33 @@ namespace {
 hipStream_t stream_of(const pdlp_unroll *u) { return u->b->P->stream; }
 
 void sync(pdlp_unroll *u) { HIPCHECK(hipStreamSynchronize(stream_of(u))); }
+
+// Where the caller's arrays live.  Device arrays are read and written on the
+// library's stream after the work already queued on the caller's stream
+// (join_caller); every call returns after its work has finished.
+enum class Mem { host, device };
+
+void join_caller(pdlp_unroll *u, hipStream_t caller) {
+    hipStream_t own = stream_of(u);
+    if (!caller || caller == own) return;
+    if (!u->join) HIPCHECK(hipEventCreateWithFlags(&u->join, hipEventDisableTiming));
+    HIPCHECK(hipEventRecord(u->join, caller));
+    HIPCHECK(hipStreamWaitEvent(own, u->join, 0));
+}
+
+void copy_in(pdlp_unroll *u, double *dst, const double *src, int64_t len, Mem mem) {
+    if (len > 0 && src)
+        HIPCHECK(hipMemcpyAsync(dst, src, sizeof(double) * len,
+                                mem == Mem::host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                                stream_of(u)));
+}
+
+void copy_out(pdlp_unroll *u, double *dst, const double *src, int64_t len, Mem mem) {
+    if (len > 0 && dst)
+        HIPCHECK(hipMemcpyAsync(dst, src, sizeof(double) * len,
+                                mem == Mem::host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice,
+                                stream_of(u)));
+}
 
 // Replay and reverse buffers for segments of `ckpt` steps (allocated once per cadence).
 void ensure_work(pdlp_unroll *u, int32_t ckpt) {
@@ -193,39 +230,146 @@ void download(pdlp_unroll *u, double *host, const double *dev, int64_t len) {
 
 // Original-unit data -> the problem's original copies and scaled data.
 void set_data(pdlp_unroll *u, const double *c, const double *lc, const double *uc,
-              const double *val) {
+              const double *val, Mem mem) {
     pdlp_problem *P = u->b->P;
     hipStream_t st = stream_of(u);
     const int64_t N = u->N, M = u->M;
-    if (c)
-        for (int64_t j = 0; j < N; ++j)
-            if (!std::isfinite(c[j])) invalid("non-finite objective coefficient " + std::to_string(j));
-    if (val)
-        for (int64_t e = 0; e < u->NZ; ++e)
-            if (!std::isfinite(val[e])) invalid("non-finite matrix value " + std::to_string(e));
-    if (lc || uc) {
-        std::vector<double> l(M), h(M);
-        HIPCHECK(hipMemcpy(l.data(), P->lc, sizeof(double) * M, hipMemcpyDeviceToHost));
-        HIPCHECK(hipMemcpy(h.data(), P->uc, sizeof(double) * M, hipMemcpyDeviceToHost));
-        for (int64_t i = 0; i < M; ++i) {
-            const double a = lc ? lc[i] : l[i], z = uc ? uc[i] : h[i];
-            if (std::isnan(a) || std::isnan(z) || a == INFINITY || z == -INFINITY || a > z)
-                invalid("bad constraint bounds in row " + std::to_string(i));
+    if (mem == Mem::host) {
+        if (c)
+            for (int64_t j = 0; j < N; ++j)
+                if (!std::isfinite(c[j]))
+                    invalid("non-finite objective coefficient " + std::to_string(j));
+        if (val)
+            for (int64_t e = 0; e < u->NZ; ++e)
+                if (!std::isfinite(val[e])) invalid("non-finite matrix value " + std::to_string(e));
+        if (lc || uc) {
+            std::vector<double> l(M), h(M);
+            HIPCHECK(hipMemcpy(l.data(), P->lc, sizeof(double) * M, hipMemcpyDeviceToHost));
+            HIPCHECK(hipMemcpy(h.data(), P->uc, sizeof(double) * M, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < M; ++i) {
+                const double a = lc ? lc[i] : l[i], z = uc ? uc[i] : h[i];
+                if (std::isnan(a) || std::isnan(z) || a == INFINITY || z == -INFINITY || a > z)
+                    invalid("bad constraint bounds in row " + std::to_string(i));
+            }
         }
+    } else if (c || lc || uc || val) {
+        if (!u->bad_d) {
+            u->bad_d = u->arena->dev<unsigned long long>(1);
+            u->bad_h = u->arena->host<unsigned long long>(1);
+        }
+        HIPCHECK(hipMemsetAsync(u->bad_d, 0, sizeof(unsigned long long), st));
+        HIPCHECK(pdlp::launch_u_check_data(st, c ? N : 0, (lc || uc) ? M : 0, val ? u->NZ : 0, c,
+                                           lc, uc, val, P->lc, P->uc, u->bad_d));
+        HIPCHECK(hipMemcpyAsync(u->bad_h, u->bad_d, sizeof(unsigned long long),
+                                hipMemcpyDeviceToHost, st));
+        sync(u);
+        if (*u->bad_h)
+            invalid(std::to_string(*u->bad_h) +
+                    " invalid entries (non-finite objective or matrix values, or bounds with "
+                    "NaN, lc = +inf, uc = -inf or lc > uc)");
     }
-    if (c) HIPCHECK(hipMemcpyAsync(P->c, c, sizeof(double) * N, hipMemcpyHostToDevice, st));
-    if (lc && M > 0) HIPCHECK(hipMemcpyAsync(P->lc, lc, sizeof(double) * M, hipMemcpyHostToDevice, st));
-    if (uc && M > 0) HIPCHECK(hipMemcpyAsync(P->uc, uc, sizeof(double) * M, hipMemcpyHostToDevice, st));
+    if (c) copy_in(u, P->c, c, N, mem);
+    if (lc) copy_in(u, P->lc, lc, M, mem);
+    if (uc) copy_in(u, P->uc, uc, M, mem);
     if (c || lc || uc)
         HIPCHECK(pdlp::launch_scale_vectors(st, (int)M, (int)N, P->d1, P->d2, P->c, P->lc, P->uc,
                                             P->lv, P->uv, P->cs, P->lcs, P->ucs, P->lvs, P->uvs));
     if (val && u->NZ > 0) {
-        HIPCHECK(hipMemcpyAsync(u->val_orig, val, sizeof(double) * u->NZ, hipMemcpyHostToDevice,
-                                st));
+        copy_in(u, u->val_orig, val, u->NZ, mem);
         HIPCHECK(pdlp::launch_u_scale_values(st, P->A, u->val_orig, P->d1, P->d2, u->a2t,
                                              P->A.val, P->AT.val));
         refresh_block_gathers(P, st);
     }
+    sync(u);
+}
+
+void ensure_tangent(pdlp_unroll *u) {
+    if (u->tan_arena) return;
+    u->tan_arena = new Arena();
+    Arena &a = *u->tan_arena;
+    const int64_t N = u->N, M = u->M;
+    double **vn[] = {&u->dcs, &u->dir_c, &u->tdx, &u->tdxn, &u->tdaty, &u->tdatyn, &u->tdsx,
+                     &u->tn1, &u->tn2};
+    double **vm[] = {&u->dlcs, &u->ducs, &u->dir_l, &u->dir_u, &u->tdy, &u->tdyn, &u->tdax,
+                     &u->tdaxn, &u->tdsy, &u->tm1, &u->tm2};
+    for (auto p : vn) *p = a.dev<double>(N);
+    for (auto p : vm) *p = a.dev<double>(M);
+    u->dav = a.dev<double>(u->NZ);
+    u->datv = a.dev<double>(u->NZ);
+    u->dir_v = a.dev<double>(u->NZ);
+}
+
+// Tangent of the recorded map along a direction in original units (null
+// parts are zero): dc~ = D2 dc, (dlc~, duc~) = D1 (dlc, duc), dA~_ij =
+// D1_i dA_ij D2_j; the replay runs beside it; dx = D2 dx~_K.
+void tangent(pdlp_unroll *u, const double *dc, const double *dlc, const double *duc,
+             const double *dval, double *dx, Mem mem) {
+    if (!u->recorded) invalid("no recorded forward pass");
+    ensure_tangent(u);
+    const pdlp_problem *P = u->b->P;
+    hipStream_t st = stream_of(u);
+    const int64_t N = u->N, M = u->M, K = u->rec.K;
+    const double t0 = now_s();
+    struct Dir {
+        double *dst;
+        const double *src;
+        int64_t len;
+    } dirs[] = {{u->dir_c, dc, N}, {u->dir_l, dlc, M}, {u->dir_u, duc, M}, {u->dir_v, dval, u->NZ}};
+    for (auto &d : dirs) {
+        if (d.src) copy_in(u, d.dst, d.src, d.len, mem);
+        else HIPCHECK(pdlp::launch_fill(st, d.len, d.dst, 0.0));
+    }
+    HIPCHECK(pdlp::launch_scale_mul(st, N, u->dir_c, P->d2, u->dcs));
+    HIPCHECK(pdlp::launch_scale_mul(st, M, u->dir_l, P->d1, u->dlcs));
+    HIPCHECK(pdlp::launch_scale_mul(st, M, u->dir_u, P->d1, u->ducs));
+    if (u->NZ > 0)
+        HIPCHECK(pdlp::launch_u_scale_values(st, P->A, u->dir_v, P->d1, P->d2, u->a2t, u->dav,
+                                             u->datv));
+    // the direction as matrices with the pattern of A~ and A~^T (no sorted copies)
+    DCsr dA = P->A, dAT = P->AT;
+    dA.val = u->dav;
+    dAT.val = u->datv;
+    dA.scol = dAT.scol = nullptr;
+    dA.sval = dAT.sval = nullptr;
+    dA.slot = dAT.slot = nullptr;
+    dA.sblk = dAT.sblk = nullptr;
+    replay_from_start(u);
+    for (double *p : {u->tdx, u->tdaty, u->tdsx}) HIPCHECK(pdlp::launch_fill(st, N, p, 0.0));
+    for (double *p : {u->tdy, u->tdsy}) HIPCHECK(pdlp::launch_fill(st, M, p, 0.0));
+    HIPCHECK(pdlp::launch_spmv_plain(st, dA, u->rx, u->tdax));  // d(A~ x_0) = dA~ x_0
+    for (int64_t s = 0; s < K; ++s) {
+        HIPCHECK(pdlp::launch_u_tangent_step(
+            st, P->A, P->AT, dA, dAT, P->scaled(), step_args(u, s), u->dcs, u->dlcs, u->ducs,
+            u->rx, u->ry, u->rax, u->raty, u->rxn, u->ryn, u->raxn, u->ratyn, u->rsx, u->rsy,
+            u->tdx, u->tdy, u->tdax, u->tdaty, u->tdxn, u->tdyn, u->tdaxn, u->tdatyn, u->tdsx,
+            u->tdsy, u->tm1, u->tm2, u->tn1, u->tn2));
+        std::swap(u->rx, u->rxn);
+        std::swap(u->ry, u->ryn);
+        std::swap(u->rax, u->raxn);
+        std::swap(u->raty, u->ratyn);
+        std::swap(u->tdx, u->tdxn);
+        std::swap(u->tdy, u->tdyn);
+        std::swap(u->tdax, u->tdaxn);
+        std::swap(u->tdaty, u->tdatyn);
+        if (!u->rst[s].empty()) {
+            apply_restarts(u, s);  // values; leaves this step's masks in mavg_d, many_d, sv_d
+            HIPCHECK(pdlp::launch_b_elementwise(st, P->A, P->AT, u->all, u->mavg_d, 0, u->sv_d,
+                                                u->tdsx, u->tdx, u->tdsy, u->tdy));
+            // product tangents of the current points (unchanged where nothing restarted)
+            HIPCHECK(pdlp::launch_spmv_plain(st, dA, u->rx, u->tm1));
+            HIPCHECK(pdlp::launch_spmv_plain(st, P->A, u->tdx, u->tm2));
+            HIPCHECK(pdlp::launch_u_add(st, M, u->tm1, u->tm2, u->tdax));
+            HIPCHECK(pdlp::launch_spmv_plain(st, dAT, u->ry, u->tn1));
+            HIPCHECK(pdlp::launch_spmv_plain(st, P->AT, u->tdy, u->tn2));
+            HIPCHECK(pdlp::launch_u_add(st, N, u->tn1, u->tn2, u->tdaty));
+            HIPCHECK(pdlp::launch_b_elementwise(st, P->A, P->AT, u->all, u->many_d, 2, u->zero_d,
+                                                nullptr, u->tdsx, nullptr, u->tdsy));
+        }
+    }
+    HIPCHECK(pdlp::launch_scale_mul(st, N, u->tdx, P->d2, u->tmp_n));
+    sync(u);
+    u->stats.tangent_seconds = now_s() - t0;
+    copy_out(u, dx, u->tmp_n, N, mem);
     sync(u);
 }
 
@@ -314,13 +458,44 @@ int pdlp_unroll_set_data(pdlp_unroll *u, const double *c, const double *lc, cons
                          const double *val) {
     return guarded([&] {
         if (!u) invalid("unroll is NULL");
-        set_data(u, c, lc, uc, val);
+        set_data(u, c, lc, uc, val, Mem::host);
     });
 }
 
-int pdlp_unroll_forward(pdlp_unroll *u, const pdlp_params *params, int64_t K, int32_t ckpt,
-                        double *x) {
+int pdlp_unroll_set_data_device(pdlp_unroll *u, const double *c, const double *lc,
+                                const double *uc, const double *val, void *hip_stream) {
     return guarded([&] {
+        if (!u) invalid("unroll is NULL");
+        join_caller(u, static_cast<hipStream_t>(hip_stream));
+        set_data(u, c, lc, uc, val, Mem::device);
+    });
+}
+
+int pdlp_unroll_tangent(pdlp_unroll *u, const double *dc, const double *dlc, const double *duc,
+                        const double *dval, double *dx) {
+    return guarded([&] {
+        if (!u || !dx) invalid("NULL argument");
+        tangent(u, dc, dlc, duc, dval, dx, Mem::host);
+    });
+}
+
+int pdlp_unroll_tangent_device(pdlp_unroll *u, const double *dc, const double *dlc,
+                               const double *duc, const double *dval, double *dx,
+                               void *hip_stream) {
+    return guarded([&] {
+        if (!u || !dx) invalid("NULL argument");
+        join_caller(u, static_cast<hipStream_t>(hip_stream));
+        tangent(u, dc, dlc, duc, dval, dx, Mem::device);
+    });
+}
+
+}  // extern "C"
+
+namespace {
+
+void forward(pdlp_unroll *u, const pdlp_params *params, int64_t K, int32_t ckpt, double *x,
+             Mem mem) {
+    {
         if (!u) invalid("unroll is NULL");
         if (K < 0 || ckpt < 1) invalid("need K >= 0 and ckpt >= 1");
         pdlp_params prm;
@@ -377,9 +552,44 @@ int pdlp_unroll_forward(pdlp_unroll *u, const pdlp_params *params, int64_t K, in
         u->stats.ckpt = ckpt;
         u->stats.restarts = nrst;
         u->stats.forward_seconds = now_s() - t0;
-        download(u, x, u->tmp_n, N);
+        copy_out(u, x, u->tmp_n, N, mem);
         sync(u);
         u->recorded = true;
+    }
+}
+
+void backward(pdlp_unroll *u, const double *gx, double *gc, double *glc, double *guc,
+              double *gval, Mem mem);
+
+}  // namespace
+
+extern "C" {
+
+int pdlp_unroll_forward(pdlp_unroll *u, const pdlp_params *params, int64_t K, int32_t ckpt,
+                        double *x) {
+    return guarded([&] { forward(u, params, K, ckpt, x, Mem::host); });
+}
+
+int pdlp_unroll_forward_device(pdlp_unroll *u, const pdlp_params *params, int64_t K,
+                               int32_t ckpt, double *x, void *hip_stream) {
+    return guarded([&] {
+        if (!u) invalid("unroll is NULL");
+        join_caller(u, static_cast<hipStream_t>(hip_stream));
+        forward(u, params, K, ckpt, x, Mem::device);
+    });
+}
+
+int pdlp_unroll_backward(pdlp_unroll *u, const double *gx, double *gc, double *glc, double *guc,
+                         double *gval) {
+    return guarded([&] { backward(u, gx, gc, glc, guc, gval, Mem::host); });
+}
+
+int pdlp_unroll_backward_device(pdlp_unroll *u, const double *gx, double *gc, double *glc,
+                                double *guc, double *gval, void *hip_stream) {
+    return guarded([&] {
+        if (!u) invalid("unroll is NULL");
+        join_caller(u, static_cast<hipStream_t>(hip_stream));
+        backward(u, gx, gc, glc, guc, gval, Mem::device);
     });
 }
 
@@ -405,9 +615,13 @@ int pdlp_unroll_replay(pdlp_unroll *u, double *x, int64_t *signature) {
     });
 }
 
-int pdlp_unroll_backward(pdlp_unroll *u, const double *gx, double *gc, double *glc, double *guc,
-                         double *gval) {
-    return guarded([&] {
+}  // extern "C"
+
+namespace {
+
+void backward(pdlp_unroll *u, const double *gx, double *gc, double *glc, double *guc,
+              double *gval, Mem mem) {
+    {
         if (!u || !gx) invalid("NULL argument");
         if (!u->recorded) invalid("no recorded forward pass");
         const pdlp_problem *P = u->b->P;
@@ -415,7 +629,7 @@ int pdlp_unroll_backward(pdlp_unroll *u, const double *gx, double *gc, double *g
         const int64_t N = u->N, M = u->M, K = u->rec.K;
         const int32_t ck = u->rec.ckpt;
         const int B = u->b->B;
-        HIPCHECK(hipMemcpyAsync(u->gx_d, gx, sizeof(double) * N, hipMemcpyHostToDevice, st));
+        copy_in(u, u->gx_d, gx, N, mem);
         sync(u);
         const double t0 = now_s();
         double t_replay = 0.0, t_rev = 0.0;
@@ -463,13 +677,18 @@ int pdlp_unroll_backward(pdlp_unroll *u, const double *gx, double *gc, double *g
         u->stats.backward_seconds = now_s() - t0;
         u->stats.backward_replay_seconds = t_replay;
         u->stats.backward_reverse_seconds = t_rev;
-        download(u, gc, u->oc, N);
-        download(u, glc, u->olc, M);
-        download(u, guc, u->ouc, M);
-        download(u, gval, u->oval, u->NZ);
+        copy_out(u, gc, u->oc, N, mem);
+        copy_out(u, glc, u->olc, M, mem);
+        copy_out(u, guc, u->ouc, M, mem);
+        copy_out(u, gval, u->oval, u->NZ, mem);
         sync(u);
-    });
+    }
 }
+
+}  // namespace
+
+extern "C" {
+
 
 int pdlp_unroll_get_tape(const pdlp_unroll *u, double *eta, double *omega, int32_t *restart) {
     return guarded([&] {

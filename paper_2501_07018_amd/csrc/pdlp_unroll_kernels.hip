@@ -17,6 +17,8 @@
 // (n), y before the step (m), interior flag of v (n bytes), dual case (m bytes).
 #include "pdlp_device.h"
 
+#include <algorithm>
+
 namespace pdlp {
 
 // Decisions of step s of every instance.
@@ -311,6 +313,100 @@ __global__ __launch_bounds__(kThreads) void ku_rA(DCsr A, UStep us, const double
     }
 }
 
+// ----------------------------------------------------------------- tangent
+//
+// Forward-mode derivative of one replayed step with the selections of the
+// replay (which runs beside it with the value kernels above): with d(.) the
+// tangent of each quantity,
+//   dx+ = dx - tau (dc~ - d(A~^T y)) where v lies strictly inside the box, else 0
+//   d(A~ x+) = dA~ x+ + A~ dx+,   dyhat = dy - sigma (2 d(A~ x+) - d(A~ x))
+//   dy+ = dyhat + sigma duc~ (case 1), dyhat + sigma dlc~ (case 2), 0 (case 0)
+//   d(A~^T y+) = dA~^T y+ + A~^T dy+,   dSx += eta dx+,  dSy += eta dy+.
+// v and yhat are recomputed with the value kernels' arithmetic, so the
+// selections are bitwise those of the replay.
+
+__global__ __launch_bounds__(kThreads) void kt_primal(DCsr AT, Vecs v, UStep us, const double *dc,
+                                                      const double *x, const double *aty,
+                                                      const double *dx, const double *daty,
+                                                      double *dxn) {
+    for (int b = blockIdx.x; b < AT.nblk; b += gridDim.x) {
+        const int i = us.tblk_inst[b];
+        const double tau = us.eta_of(i) / us.omega_of(i);
+        for (int j = AT.blk[b] + threadIdx.x; j < AT.blk[b + 1]; j += kThreads) {
+            const double vj = x[j] - tau * (v.c[j] - aty[j]);
+            const bool in = vj > v.lv[j] && vj < v.uv[j];
+            dxn[j] = in ? dx[j] - tau * (dc[j] - daty[j]) : 0.0;
+        }
+    }
+}
+
+// rows: d(A~ x+) = t1 + t2 (dA~ x+ and A~ dx+), the dual tangent and dSy
+__global__ __launch_bounds__(kThreads) void kt_dual(DCsr A, Vecs v, UStep us, const double *y,
+                                                    const double *ax, const double *axn,
+                                                    const double *dy, const double *dax,
+                                                    const double *t1, const double *t2,
+                                                    const double *dlc, const double *duc,
+                                                    double *daxn, double *dyn, double *dsy) {
+    for (int b = blockIdx.x; b < A.nblk; b += gridDim.x) {
+        const int i = us.ablk_inst[b];
+        const double eta = us.eta_of(i), sigma = eta * us.omega_of(i);
+        for (int r = A.blk[b] + threadIdx.x; r < A.blk[b + 1]; r += kThreads) {
+            const double da = t1[r] + t2[r];
+            daxn[r] = da;
+            const double yhat = y[r] - sigma * (2.0 * axn[r] - ax[r]);
+            const int br = dual_branch(yhat, sigma, v.lc[r], v.uc[r]);
+            const double dyhat = dy[r] - sigma * (2.0 * da - dax[r]);
+            const double d = br == 1 ? dyhat + sigma * duc[r] : (br == 2 ? dyhat + sigma * dlc[r] : 0.0);
+            dyn[r] = d;
+            dsy[r] += eta * d;
+        }
+    }
+}
+
+// columns: d(A~^T y+) = t1 + t2 (dA~^T y+ and A~^T dy+) and dSx
+__global__ __launch_bounds__(kThreads) void kt_col(DCsr AT, UStep us, const double *t1,
+                                                   const double *t2, const double *dxn,
+                                                   double *datyn, double *dsx) {
+    for (int b = blockIdx.x; b < AT.nblk; b += gridDim.x) {
+        const double eta = us.eta_of(us.tblk_inst[b]);
+        for (int j = AT.blk[b] + threadIdx.x; j < AT.blk[b + 1]; j += kThreads) {
+            datyn[j] = t1[j] + t2[j];
+            dsx[j] += eta * dxn[j];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void kt_add(int64_t len, const double *a, const double *b,
+                                                   double *out) {
+    for (int64_t k = blockIdx.x * (int64_t)kThreads + threadIdx.x; k < len;
+         k += (int64_t)gridDim.x * kThreads)
+        out[k] = a[k] + b[k];
+}
+
+// Checks of new data in device memory: counts non-finite objective entries
+// and matrix values, and rows whose bounds are invalid (NaN, lc = +inf,
+// uc = -inf or lc > uc), taking the current bound where one is not given.
+__global__ __launch_bounds__(kThreads) void ku_check_data(int64_t N, int64_t M, int64_t NZ,
+                                                          const double *c, const double *lc,
+                                                          const double *uc, const double *val,
+                                                          const double *cur_lc,
+                                                          const double *cur_uc,
+                                                          unsigned long long *bad) {
+    unsigned long long nb = 0;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    const int64_t t0 = blockIdx.x * (int64_t)kThreads + threadIdx.x;
+    if (c)
+        for (int64_t j = t0; j < N; j += stride) nb += !isfinite(c[j]);
+    if (val)
+        for (int64_t e = t0; e < NZ; e += stride) nb += !isfinite(val[e]);
+    if (lc || uc)
+        for (int64_t i = t0; i < M; i += stride) {
+            const double a = lc ? lc[i] : cur_lc[i], z = uc ? uc[i] : cur_uc[i];
+            nb += isnan(a) || isnan(z) || a == INFINITY || z == -INFINITY || a > z;
+        }
+    if (nb) atomicAdd(bad, nb);
+}
+
 // ------------------------------------------------------- data and results
 
 // A~ = D1 A D2 entry by entry as (d1_i a_ij) d2_j, into A~ and (through a2t) A~^T.
@@ -396,6 +492,54 @@ hipError_t launch_u_reverse(hipStream_t s, const DCsr &A, const DCsr &AT, UStepA
     if (A.nblk > 0)
         hipLaunchKernelGGL(ku_rA, dim3(blk_grid(A.nblk, 2048)), dim3(kThreads), 0, s, A, us, vb,
                            seg_w, seg_y, yhb, yb, gval);
+    return hipGetLastError();
+}
+
+hipError_t launch_u_tangent_step(hipStream_t s, const DCsr &A, const DCsr &AT, const DCsr &dA,
+                                 const DCsr &dAT, Vecs v, UStepArgs u, const double *dc,
+                                 const double *dlc, const double *duc, const double *x,
+                                 const double *y, const double *ax, const double *aty,
+                                 double *xn, double *yn, double *axn, double *atyn, double *sx,
+                                 double *sy, const double *dx, const double *dy, const double *dax,
+                                 const double *daty, double *dxn, double *dyn, double *daxn,
+                                 double *datyn, double *dsx, double *dsy, double *tm1,
+                                 double *tm2, double *tn1, double *tn2) {
+    const UStep us{u.eta, u.omega, u.K, u.s, u.ablk_inst, u.tblk_inst};
+    hipLaunchKernelGGL(kt_primal, dim3(blk_grid(AT.nblk, 4096)), dim3(kThreads), 0, s, AT, v, us,
+                       dc, x, aty, dx, daty, dxn);
+    hipError_t e = launch_u_step(s, A, AT, v, u, x, y, ax, aty, xn, yn, axn, atyn, sx, sy, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr);
+    if (e != hipSuccess) return e;
+    if (A.nblk > 0) {
+        e = launch_spmv_plain(s, dA, xn, tm1);
+        if (e != hipSuccess) return e;
+        e = launch_spmv_plain(s, A, dxn, tm2);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kt_dual, dim3(blk_grid(A.nblk, 4096)), dim3(kThreads), 0, s, A, v, us,
+                           y, ax, axn, dy, dax, tm1, tm2, dlc, duc, daxn, dyn, dsy);
+    }
+    e = launch_spmv_plain(s, dAT, yn, tn1);
+    if (e != hipSuccess) return e;
+    e = launch_spmv_plain(s, AT, dyn, tn2);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kt_col, dim3(blk_grid(AT.nblk, 4096)), dim3(kThreads), 0, s, AT, us, tn1,
+                       tn2, dxn, datyn, dsx);
+    return hipGetLastError();
+}
+
+hipError_t launch_u_add(hipStream_t s, int64_t len, const double *a, const double *b, double *out) {
+    if (len > 0)
+        hipLaunchKernelGGL(kt_add, dim3(grid_of(len, 4096)), dim3(kThreads), 0, s, len, a, b, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_u_check_data(hipStream_t s, int64_t N, int64_t M, int64_t NZ, const double *c,
+                               const double *lc, const double *uc, const double *val,
+                               const double *cur_lc, const double *cur_uc,
+                               unsigned long long *bad) {
+    const int64_t len = std::max(N, std::max(M, NZ));
+    hipLaunchKernelGGL(ku_check_data, dim3(grid_of(len, 4096)), dim3(kThreads), 0, s, N, M, NZ, c,
+                       lc, uc, val, cur_lc, cur_uc, bad);
     return hipGetLastError();
 }
 

@@ -1,8 +1,9 @@
 """torch.autograd.Function around the unrolled, differentiable PDHG map.
 
 Argument marshalling only: the forward and backward passes run in the HIP
-library (pdlp_unroll_forward / pdlp_unroll_backward).  Tensors may live on
-any device; they are handed over as float64 host arrays.
+library (pdlp_unroll_*).  Tensors on the GPU are handed over by device
+address with the current torch stream (the pdlp_unroll_*_device calls: no
+host copies); tensors on the host are handed over as float64 arrays.
 """
 from __future__ import annotations
 
@@ -16,6 +17,14 @@ def _np(t: torch.Tensor) -> np.ndarray:
     return np.ascontiguousarray(t.detach().to("cpu", torch.float64).numpy())
 
 
+def _f64(t: torch.Tensor) -> torch.Tensor:
+    return t.detach().to(torch.float64).contiguous()
+
+
+def _stream(dev: torch.device) -> int:
+    return torch.cuda.current_stream(dev).cuda_stream
+
+
 class UnrolledPDHG(torch.autograd.Function):
     """x_K = map(c, lc, uc, val) with the decisions recorded by its own forward
     pass held fixed in the backward pass (see pdlp_unroll_* in include/pdlp.h).
@@ -25,17 +34,31 @@ class UnrolledPDHG(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, c, lc, uc, val, unroll: Unroll, K: int, ckpt: int, params=None):
-        unroll.set_data(_np(c), _np(lc), _np(uc), _np(val))
-        x = unroll.forward(K, ckpt, params)
+        if c.is_cuda:
+            ts = [_f64(t) for t in (c, lc, uc, val)]
+            s = _stream(c.device)
+            unroll.set_data_device(*[t.data_ptr() for t in ts], stream=s)
+            x = torch.empty(unroll.N, dtype=torch.float64, device=c.device)
+            unroll.forward_device(K, ckpt, x.data_ptr(), params, stream=s)
+        else:
+            unroll.set_data(_np(c), _np(lc), _np(uc), _np(val))
+            x = torch.from_numpy(unroll.forward(K, ckpt, params))
         unroll.version = getattr(unroll, "version", 0) + 1
         ctx.unroll, ctx.version, ctx.device = unroll, unroll.version, c.device
-        return torch.from_numpy(x).to(c.device)
+        return x
 
     @staticmethod
     def backward(ctx, gx):
         u = ctx.unroll
         if getattr(u, "version", None) != ctx.version:
             raise RuntimeError("the unrolled map was run forward again before this backward")
+        if gx.is_cuda:
+            g = _f64(gx)
+            out = [torch.empty(k, dtype=torch.float64, device=gx.device)
+                   for k in (u.N, u.M, u.M, u.NZ)]
+            u.backward_device(g.data_ptr(), *[o.data_ptr() for o in out],
+                              stream=_stream(gx.device))
+            return (*out, None, None, None, None)
         g = u.backward(_np(gx))
         t = lambda a: torch.from_numpy(a).to(ctx.device)
         return t(g["c"]), t(g["lc"]), t(g["uc"]), t(g["val"]), None, None, None, None

@@ -133,3 +133,48 @@ def test_torch_tensors_give_the_host_problem():
     assert got["status"] == r["status_name"] and got["iterations"] == r["iterations"]
     assert np.array_equal(np.array(got["x"]), r["x"])
     assert got["short"] and all(v == "refused" for _, v in got["short"]), got["short"]
+
+
+_LAYER_CHILD = r"""
+import json, sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import lpgen
+import paper_2501_07018_amd as pd
+from paper_2501_07018_amd.layer import LPLayer
+lps = [lpgen.planted_uniform(60, 100, 5, seed=3), lpgen.planted_uniform(150, 225, 8, seed=101)]
+cat = lambda k: np.concatenate([np.asarray(getattr(lp, k), dtype=np.float64) for lp in lps])
+gx = np.random.default_rng(3).standard_normal(sum(lp.n for lp in lps))
+out = {}
+for where in ("cpu", "cuda"):
+    layer = LPLayer(lps, K=60, ckpt=25)
+    ts = [torch.tensor(cat(k), device=where, requires_grad=True) for k in ("c", "lc", "uc", "val")]
+    x = layer(*ts)
+    (x * torch.tensor(gx, device=where)).sum().backward()
+    out[where] = [x.detach().cpu().numpy()] + [t.grad.detach().cpu().numpy() for t in ts]
+    out[where + "_device"] = str(x.device)
+same = [bool(np.array_equal(a, b)) for a, b in zip(out["cpu"], out["cuda"])]
+# the device variants reject invalid data like the host ones
+u = pd.Unroll(lps)
+bad = torch.tensor(cat("c"), device="cuda")
+bad[3] = float("nan")
+try:
+    u.set_data_device(c=bad.data_ptr(), stream=torch.cuda.current_stream().cuda_stream)
+    refused = False
+except pd.PdlpError as e:
+    refused = e.code == pd.PDLP_ERR_INVALID_ARGUMENT
+print(json.dumps({"same": same, "device": out["cuda_device"], "refused": refused}))
+"""
+
+
+def test_layer_on_device_tensors_matches_the_host_path():
+    say("LPLayer on CUDA tensors vs host tensors (child process)")
+    pytest.importorskip("torch")
+    out = subprocess.run([sys.executable, "-c", _LAYER_CHILD, ROOT], capture_output=True,
+                         text=True, timeout=240)
+    assert out.returncode == 0, out.stderr[-2000:]
+    got = json.loads(out.stdout.strip().splitlines()[-1])
+    assert got["device"].startswith("cuda"), got
+    assert all(got["same"]), got    # x_K and the four gradients, bitwise
+    assert got["refused"], got
