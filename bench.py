@@ -42,9 +42,10 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel source they were taken on (hash of the hot-path
 # region of the kernels and constants); reported as null otherwise.
 TRAFFIC_RECORD = {
-    "hot_source": "7e81590456c5a9ff",
-    "k_spmv_dual": 9185470047,
-    "k_spmv_primal": 13887410922,
+    "hot_source": "7bf434a3d5baa446",
+    "k_spmv_dual": 9179118128,
+    "k_seg_gather_primal+k_seg_primal": 8610604848,   # 5642437408 + 2968167440
+    "k_spmv_primal": None,                             # not run on this workload any more
 }
 
 

@@ -208,5 +208,6 @@ def test_unroll_full_config_replay_and_linearity():
         print(f"[dot] K=500 seed={seed} <Jv,w>={lhs:.17g} <v,J^T w>={rhs:.17g} "
               f"|diff|/(|Jv||w|)={abs(lhs - rhs) / scale:.3e} |diff|/|rhs|={abs(lhs - rhs) / abs(rhs):.3e}",
               flush=True)
-        assert abs(lhs - rhs) <= 1e-8 * scale, (seed, lhs, rhs, scale)
+        # measured on MI355X: |diff| / (|Jv| |w|) = 1.2e-15 and 8e-17 for these seeds
+        assert abs(lhs - rhs) <= 1e-12 * scale, (seed, lhs, rhs, scale)
     u.close()
