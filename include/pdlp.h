@@ -235,7 +235,8 @@ int pdlp_spmv(const pdlp_problem *p, int32_t transpose, int32_t scaled, const do
  * and the call returns without waiting; out_dev is valid once the stream has
  * reached it.  Staging of the permuted vectors lives in a fixed device array
  * of 2^23 doubles (64 MiB) per GPU, kept until the process ends: m + n above
- * 2^23 is rejected with INVALID_ARGUMENT.  Every call on a GPU shares that
+ * 2^23 is rejected with INVALID_ARGUMENT, and so is a call while another GPU
+ * than the problem's is current.  Every call on a GPU shares that
  * array (and the problem's own product buffers), so calls that overlap on one
  * GPU race; nothing in the array needs clearing between calls.  Allocates
  * nothing: no hipMalloc, hipFree or allocating library routine.

@@ -226,6 +226,7 @@ long long next_art(long long k, long long t, double beta, long long cap);
 struct pdlp_problem {
     int32_t m = 0, n = 0;
     int64_t nnz = 0;
+    int device = 0;  // the GPU holding the problem (current at creation)
     hipStream_t stream = nullptr;
     pdlp::host::Arena arena;
     pdlp::DCsr A, AT;

@@ -1449,6 +1449,7 @@ pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *r
             P->m = m;
             P->n = n;
             P->nnz = nnz;
+            HIPCHECK(hipGetDevice(&P->device));
             P->obj_offset = obj_offset;
             P->scale_params = prm;
             P->stream = static_cast<hipStream_t>(hip_stream);
@@ -2084,9 +2085,7 @@ constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
 double *g_scratch_ptr[kMaxDevices] = {};
 
-double *scratch_on_current_device() {
-    int dev = 0;
-    HIPCHECK(hipGetDevice(&dev));
+double *scratch_on_device(int dev) {
     if (dev < 0 || dev >= kMaxDevices)
         throw LibError(PDLP_ERR_HIP, "device index " + std::to_string(dev) + " out of range");
     std::lock_guard<std::mutex> lock(g_scratch_mu);
@@ -2113,7 +2112,12 @@ int pdlp_spmv_noalloc(const pdlp_problem *pc, int32_t transpose, int32_t scaled,
             invalid("pdlp_spmv_noalloc: m + n = " + std::to_string(in_len + out_len) +
                     " exceeds the staging capacity of " + std::to_string(kNoAllocDoubles) +
                     " doubles; use pdlp_spmv");
-        double *st = scratch_on_current_device();
+        int dev = 0;
+        HIPCHECK(hipGetDevice(&dev));
+        if (dev != p->device)
+            invalid("pdlp_spmv_noalloc: make the problem's device (" + std::to_string(p->device) +
+                    ") current");
+        double *st = scratch_on_device(dev);
         hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : p->stream;
         const DCsr &M = transpose ? p->AT : p->A;
         const double *din = transpose ? p->d1 : p->d2;  // original = D1^-1 A~ D2^-1
