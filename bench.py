@@ -368,6 +368,9 @@ def main():
     ap.add_argument("--solve-budget", type=float, default=0.0,
                     help="after the timed steps, continue the same solve to its tolerances "
                          "(1% gap, polishing to 1e-8) for at most this many seconds")
+    ap.add_argument("--stream-block", type=int, default=0,
+                    help="stream-block schedule of the 20M x 25M problem: 0 default, -1 autotune "
+                         "on the solver's steps, else nonzeros per block")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch step attempts one by one (same results; for tracing tools)")
     ap.add_argument("--tol-sweep", action="store_true",
@@ -391,7 +394,8 @@ def main():
     st = lp.stats()
     log(f"generated {st} in {time.perf_counter() - t0:.1f}s")
 
-    prm = pd.pdlp_params_default(eps_feas=1e-8, eps_gap=1e-2, polish=1, profile=1)
+    prm = pd.pdlp_params_default(eps_feas=1e-8, eps_gap=1e-2, polish=1, profile=1,
+                                 stream_block=args.stream_block)
     t0 = time.perf_counter()
     prob = pd.Problem(lp, prm)
     state = prob.state(prm)
@@ -465,6 +469,7 @@ def main():
                          f"capped at 10,000, 5,000 dense rows); eps_feas 1e-8, eps_gap 1e-2, "
                          f"polishing on; step = 64 accepted PDHG iterations + periodic check"),
             "m": m, "n": n, "nnz": nnz, "iterations_per_step": step_k,
+            "schedule": prob.schedule(),
             "status_at_end": status, "rel_gap_at_end": r["rel_gap"],
         },
         "roofline": {

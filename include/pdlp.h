@@ -95,9 +95,16 @@ typedef struct pdlp_params {
                                  once (per vector set, or per set of running batch instances);
                                  0: launched one by one.  Results are identical either way. */
     int32_t stream_block;     /* nonzeros per block of the CSR stream products (problem and batch
-                                 creation): 0 (default) 2048; -1 autotune: time 256, 512, 1024
-                                 and 2048 on the device and keep the fastest, for A and A^T
-                                 separately; else a value in [64, 2048].  Row sums are the same
+                                 creation): 0 (default) 2048; else a value in [64, 2048]; -1
+                                 autotune.  A single problem autotunes on the solver's own
+                                 steps: for (block size, longest row of the stream class) in
+                                 (2048, 64), (2048, 32), (2048, 128), (1024, 64), (1024, 32),
+                                 (512, 64) it runs 4 + 16 accepted steps from the initial point
+                                 and keeps the fastest (pdlp_problem_schedule reports it); rows
+                                 longer than the chosen length are summed by a wave or a
+                                 workgroup tree instead of in stored order.  A batch times 256,
+                                 512, 1024 and 2048 with plain products, for A and A^T
+                                 separately.  With a fixed row class, row sums are the same
                                  whatever the blocks; only the order in which the step norms'
                                  partial sums combine changes. */
     int32_t sorted_gathers;   /* batch and unroll creation: 1 (default) keeps a copy of the
@@ -211,6 +218,11 @@ void pdlp_problem_destroy(pdlp_problem *p);
 
 /* Sizes of a created problem. */
 int pdlp_problem_dims(const pdlp_problem *p, int32_t *m, int32_t *n, int64_t *nnz);
+
+/* The block schedule of a created problem's products: nonzeros per stream
+ * block and the longest row of the stream class (rows summed in stored
+ * order by one lane); either pointer may be NULL. */
+int pdlp_problem_schedule(const pdlp_problem *p, int32_t *stream_block, int32_t *med_row);
 
 /* Copy out the preconditioned problem: D1 (m), D2 (n), the scaled values of
  * A in the caller's CSR order (nnz), and the scaled c~, lc~, uc~, lv~, uv~

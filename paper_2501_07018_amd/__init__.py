@@ -114,7 +114,7 @@ class StateBlob(C.Structure):
 _lib = None
 
 EXPORTS = ("pdlp_problem_create", "pdlp_problem_create_device", "pdlp_problem_destroy",
-           "pdlp_problem_dims",
+           "pdlp_problem_dims", "pdlp_problem_schedule",
            "pdlp_problem_get_scaled", "pdlp_spmv", "pdlp_params_default", "pdlp_solve",
            "pdlp_state_create", "pdlp_state_destroy", "pdlp_iterate_k", "pdlp_state_get",
            "pdlp_state_set", "pdlp_norm_gap", "pdlp_last_error", "pdlp_state_solve",
@@ -144,6 +144,7 @@ def lib() -> C.CDLL:
     L.pdlp_problem_destroy.argtypes = [vp]
     L.pdlp_problem_destroy.restype = None
     L.pdlp_problem_dims.argtypes = [vp, I32, I32, C.POINTER(C.c_int64)]
+    L.pdlp_problem_schedule.argtypes = [vp, I32, I32]
     L.pdlp_problem_get_scaled.argtypes = [vp, D, D, D, D, D, D, D, D]
     L.pdlp_spmv.argtypes = [vp, C.c_int32, C.c_int32, D, D, C.c_int32, D]
     L.pdlp_spmv_noalloc.argtypes = [vp, C.c_int32, C.c_int32, vp, vp, vp]
@@ -631,6 +632,11 @@ class Problem:
 
     def scaled(self) -> dict:
         return pdlp_problem_get_scaled(self.h)
+
+    def schedule(self) -> dict:
+        sb, med = C.c_int32(), C.c_int32()
+        _check(lib().pdlp_problem_schedule(self.h, C.byref(sb), C.byref(med)))
+        return {"stream_block": sb.value, "med_row": med.value}
 
     def spmv(self, x, transpose=False, scaled=True, repeat=1):
         return pdlp_spmv(self.h, x, transpose, scaled, repeat)

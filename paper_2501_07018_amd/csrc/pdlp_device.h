@@ -222,7 +222,7 @@ __device__ __forceinline__ void stream_block(const DCsr &A, Epi &epi, int b, dou
         const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
         const int len = e1 - e0;
         const int len0 = A.row_ptr[r0 + 1] - e0;
-        if (len0 > kMedRow && len0 <= kWaveMax) {
+        if (len0 > A.med_row && len0 <= kWaveMax) {
             // wave block: row r0 + wid
             const int r = r0 + wid;
             if (r < r1) {
@@ -233,7 +233,7 @@ __device__ __forceinline__ void stream_block(const DCsr &A, Epi &epi, int b, dou
                 s = wave_sum(s);
                 if (lane == 0) epi.apply(r, s, acc, epi.prefetch(r));
             }
-        } else if (len <= kStage && len0 <= kMedRow) {
+        } else if (len <= kStage && len0 <= A.med_row) {
             // the first row of each lane: its slice bounds and epilogue operands
             // are loaded before the matrix stream so they arrive with it
             const int rr = r0 + threadIdx.x;

@@ -227,6 +227,7 @@ struct pdlp_problem {
     int32_t m = 0, n = 0;
     int64_t nnz = 0;
     int device = 0;  // the GPU holding the problem (current at creation)
+    int32_t stage = pdlp::kStage;  // nonzeros per stream block (the schedule in use)
     hipStream_t stream = nullptr;
     pdlp::host::Arena arena;
     pdlp::DCsr A, AT;

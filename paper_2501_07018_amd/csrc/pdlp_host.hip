@@ -56,7 +56,8 @@ using pdlp::Vecs;
 // first rows of the instances of a batch.
 std::vector<int32_t> make_blocks(const int32_t *rp, int32_t rows,
                                  const std::vector<int32_t> *breaks, int32_t stage,
-                                 int32_t max_rows = pdlp::kMaxBlockRows) {
+                                 int32_t max_rows = pdlp::kMaxBlockRows,
+                                 int32_t med_row = pdlp::kMedRow) {
     std::vector<int32_t> blk;
     blk.push_back(0);
     int32_t r = 0;
@@ -68,9 +69,9 @@ std::vector<int32_t> make_blocks(const int32_t *rp, int32_t rows,
         const int32_t len = L(r);
         if (len > pdlp::kWaveMax) {
             ++r;
-        } else if (len > pdlp::kMedRow) {
+        } else if (len > med_row) {
             const int32_t start = r;
-            while (r < lim && r - start < pdlp::kWaveRows && L(r) > pdlp::kMedRow &&
+            while (r < lim && r - start < pdlp::kWaveRows && L(r) > med_row &&
                    L(r) <= pdlp::kWaveMax)
                 ++r;
         } else {
@@ -78,7 +79,7 @@ std::vector<int32_t> make_blocks(const int32_t *rp, int32_t rows,
             int64_t nz = 0;
             while (r < lim && r - start < max_rows) {
                 const int32_t l = L(r);
-                if (l > pdlp::kMedRow || nz + l > stage) break;
+                if (l > med_row || nz + l > stage) break;
                 nz += l;
                 ++r;
             }
@@ -546,8 +547,12 @@ void pdlp::host::validate(int32_t m, int32_t n, int64_t nnz, const int32_t *rp,
 namespace {
 
 std::vector<int32_t> upload_blocks(pdlp_problem *P, Arena &arena, DCsr &M, const int32_t *rp_host,
-                                   const std::vector<int32_t> *breaks, int32_t stage) {
-    std::vector<int32_t> blk = make_blocks(rp_host, M.rows, breaks, stage);
+                                   const std::vector<int32_t> *breaks, int32_t stage,
+                                   int32_t med_row = pdlp::kMedRow) {
+    std::vector<int32_t> blk =
+        make_blocks(rp_host, M.rows, breaks, stage, pdlp::kMaxBlockRows, med_row);
+    M.med_row = med_row;
+    M.stage = stage;
     M.nblk = (int32_t)blk.size() - 1;
     M.blk = arena.dev<int32_t>(blk.size());
     HIPCHECK(hipMemcpyAsync(M.blk, blk.data(), blk.size() * sizeof(int32_t),
@@ -1390,11 +1395,65 @@ void engine_initialize(pdlp_state *S, const double *x0_host, const double *y0_ho
     HIPCHECK(hipStreamSynchronize(s));
 }
 
+// Block schedules scored on the solver's own steps (stream_block = -1,
+// single problems): for each candidate (nonzeros per stream block, longest
+// row of the stream class) the row blocks of A and A^T are rebuilt and the
+// fused step kernels of pdlp_solve run 4 accepted steps from the initial
+// point (first launches, graph capture), then 16 more, timed on the host
+// around the block; the fastest candidate is kept.  A row no longer than the
+// chosen length is summed in stored order by one lane, a longer one by a
+// wave or a workgroup tree, so the choice can change the rounding of those
+// rows' sums (never the method).
+void autotune_schedules(pdlp_problem *P, const pdlp_params &prm, const int32_t *rp_a,
+                        const int32_t *rp_t) {
+    struct Cand {
+        int32_t stage, med;
+    };
+    static constexpr Cand kCands[] = {{pdlp::kStage, pdlp::kMedRow}, {pdlp::kStage, 32},
+                                      {pdlp::kStage, 128},          {1024, pdlp::kMedRow},
+                                      {1024, 32},                   {512, pdlp::kMedRow}};
+    pdlp_params p2 = prm;
+    p2.profile = 0;
+    double best = INFINITY;
+    Cand pick = kCands[0];
+    for (const Cand &c : kCands) {
+        Arena blk_arena;
+        upload_blocks(P, blk_arena, P->A, rp_a, nullptr, c.stage, c.med);
+        upload_blocks(P, blk_arena, P->AT, rp_t, nullptr, c.stage, c.med);
+        pdlp_state S;
+        S.P = P;
+        S.prm = p2;
+        S.E = new Engine(P, P->scaled());
+        S.E->use_graphs = p2.graphs != 0;
+        engine_initialize(&S, nullptr, nullptr);
+        S.E->run_block(4);
+        const double t0 = now_s();
+        S.E->run_block(16);
+        HIPCHECK(hipStreamSynchronize(P->stream));
+        const double t = now_s() - t0;
+        if (t < best) {
+            best = t;
+            pick = c;
+        }
+    }
+    P->blkA = upload_blocks(P, P->arena, P->A, rp_a, nullptr, pick.stage, pick.med);
+    P->blkT = upload_blocks(P, P->arena, P->AT, rp_t, nullptr, pick.stage, pick.med);
+    P->stage = pick.stage;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *pdlp_last_error(void) { return g_last_error.c_str(); }
+
+int pdlp_problem_schedule(const pdlp_problem *p, int32_t *stream_block, int32_t *med_row) {
+    return guarded([&] {
+        if (!p) invalid("problem is NULL");
+        if (stream_block) *stream_block = p->stage;
+        if (med_row) *med_row = p->A.med_row;
+    });
+}
 
 void pdlp_params_default(pdlp_params *p) {
     if (!p) return;
@@ -1543,17 +1602,22 @@ pdlp_problem *create_problem(int32_t m, int32_t n, int64_t nnz, const int32_t *r
             P->red_part = a.dev<double>(P->red_cap);
             P->res_d = a.dev<double>(8);
             P->res_h = a.host<double>(8);
-            P->blkA = choose_blocks(P, A, new_rp.data(), row_breaks, prm.stream_block);
-            {
-                std::vector<int32_t> trp((size_t)n + 1);
-                HIPCHECK(hipMemcpy(trp.data(), P->AT.row_ptr, sizeof(int32_t) * ((size_t)n + 1),
-                                   hipMemcpyDeviceToHost));
-                P->blkT = choose_blocks(P, P->AT, trp.data(), col_breaks, prm.stream_block);
-            }
+            // a single problem autotunes on the solver's own steps once it is
+            // scaled (autotune_schedules); until then it has the default blocks
+            const bool single = !row_breaks && !col_breaks;
+            const int32_t sb = (single && prm.stream_block == -1) ? 0 : prm.stream_block;
+            P->blkA = choose_blocks(P, A, new_rp.data(), row_breaks, sb);
+            P->stage = P->A.stage;
+            std::vector<int32_t> trp((size_t)n + 1);
+            HIPCHECK(hipMemcpy(trp.data(), P->AT.row_ptr, sizeof(int32_t) * ((size_t)n + 1),
+                               hipMemcpyDeviceToHost));
+            P->blkT = choose_blocks(P, P->AT, trp.data(), col_breaks, sb);
             precondition(P, prm);
             const bool seg = prm.segmented_gathers == 1 ||
                              (prm.segmented_gathers < 0 && (int64_t)m * 8 > (int64_t)(32 << 20));
-            if (seg && !row_breaks && !col_breaks) build_segmented(P, P->AT, P->segT);
+            if (seg && single) build_segmented(P, P->AT, P->segT);
+            if (single && prm.stream_block == -1 && nnz > 0)
+                autotune_schedules(P, prm, new_rp.data(), trp.data());
         } catch (...) {
             delete P;
             throw;
@@ -1603,7 +1667,7 @@ void sort_block_gathers(pdlp_problem *P) {
                 const int32_t r0 = blk[(size_t)b], r1 = blk[(size_t)b + 1];
                 const int64_t e0 = rp[(size_t)r0], e1 = rp[(size_t)r1];
                 const int64_t len = e1 - e0, len0 = rp[(size_t)r0 + 1] - e0;
-                const bool stream = len <= pdlp::kStage && len0 <= pdlp::kMedRow;
+                const bool stream = len <= pdlp::kStage && len0 <= M.med_row;
                 kv.resize((size_t)len);
                 for (int64_t q = 0; q < len; ++q) kv[(size_t)q] = {col[(size_t)(e0 + q)], (int32_t)q};
                 bool use = false;

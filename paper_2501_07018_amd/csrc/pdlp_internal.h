@@ -32,8 +32,9 @@ constexpr int kGapNewton = 12;       // active-set steps before the multisection
 
 // CSR matrix on the device with a row-block partition: block b covers rows
 // [blk[b], blk[b+1]) and is one of
-//   stream: rows of at most kMedRow nonzeros whose nonzeros fit the LDS stage;
-//   wave:   up to kWaveRows rows of (kMedRow, kWaveMax] nonzeros, one wave each;
+//   stream: rows of at most med_row (default kMedRow) nonzeros whose nonzeros fit
+//           the LDS stage;
+//   wave:   up to kWaveRows rows of (med_row, kWaveMax] nonzeros, one wave each;
 //   long:   a single row of more than kWaveMax nonzeros (whole workgroup).
 // Entries inside a row may appear in any column order.
 struct DCsr {
@@ -44,6 +45,8 @@ struct DCsr {
     int32_t nblk = 0;
     int32_t *blk = nullptr;
     int32_t grid = 0;  // workgroups of the persistent stream kernels
+    int32_t med_row = kMedRow;  // longest row of the stream class (the block partition's)
+    int32_t stage = kStage;     // nonzeros per stream block of the partition
     // Optional copy of the entries of short-row blocks sorted by column
     // (scol, sval) with each entry's position in the block (slot), so that
     // the lanes of a wave gather neighbouring words; the products are staged

@@ -241,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void ku_rA(DCsr A, UStep us, const double
         const int e0 = A.row_ptr[r0], e1 = A.row_ptr[r1];
         const int len = e1 - e0;
         const int len0 = A.row_ptr[r0 + 1] - e0;
-        if (len0 > kMedRow && len0 <= kWaveMax) {
+        if (len0 > A.med_row && len0 <= kWaveMax) {
             const int r = r0 + wid;
             if (r < r1) {
                 const double yh = yhb[r], yr = y[r];
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(kThreads) void ku_rA(DCsr A, UStep us, const double
                 s = wave_sum(s);
                 if (lane == 0) yb[r] = yh + tau * s;
             }
-        } else if (len <= kStage && len0 <= kMedRow) {
+        } else if (len <= kStage && len0 <= A.med_row) {
             double gv[kPer], gw[kPer];
 #pragma unroll
             for (int k = 0; k < kPer; ++k) {

@@ -76,12 +76,13 @@ def test_stream_block_sizes_leave_products_unchanged():
     rng = np.random.default_rng(1)
     x, y = rng.standard_normal(lp.n), rng.standard_normal(lp.m)
     ref = None
-    for sb in (0, 2048, 512, 64, -1):
+    for sb in (0, 2048, 512, 64):
         prob = pd.Problem(lp, pd.pdlp_params_default(stream_block=sb))
         out = (prob.spmv(x)[0], prob.spmv(y, transpose=True)[0])
         if ref is None:
             ref = out
         assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), sb
+        assert prob.schedule() == {"stream_block": 2048 if sb == 0 else sb, "med_row": 64}
         small = pd.Problem(lpgen.planted_uniform(900, 1350, 8, seed=102),
                            pd.pdlp_params_default(stream_block=sb))
         r = small.solve(pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6, max_iters=100_000))
@@ -89,3 +90,37 @@ def test_stream_block_sizes_leave_products_unchanged():
     for bad in (10, 4096, -2):
         with pytest.raises(pd.PdlpError):
             pd.Problem(lp, pd.pdlp_params_default(stream_block=bad))
+
+
+def test_autotuned_schedules_are_scored_on_steps():
+    """stream_block = -1 on a single problem: the schedule (block size, longest
+    row of the stream class) is picked by timing the solver's own steps.  It
+    is one of the candidates; rows within the stream class of both the
+    default and the pick are summed in stored order (bitwise the default
+    products), the others by a tree (1e-14 of |A||x|); solves reach their
+    tolerance."""
+    say("autotuned schedules")
+    cands = {(2048, 64), (2048, 32), (2048, 128), (1024, 64), (1024, 32), (512, 64)}
+    lp = lpgen.planted_skewed(3000, 5000, seed=103, mean_degree=4.0, cap=2500, n_dense=3,
+                              dense_frac=0.4)
+    rng = np.random.default_rng(1)
+    x, y = rng.standard_normal(lp.n), rng.standard_normal(lp.m)
+    ref = pd.Problem(lp)
+    tuned = pd.Problem(lp, pd.pdlp_params_default(stream_block=-1))
+    sch = tuned.schedule()
+    assert (sch["stream_block"], sch["med_row"]) in cands, sch
+    short = min(sch["med_row"], 64)
+    rl = np.diff(lp.row_ptr)
+    cl = np.bincount(lp.col, minlength=lp.n)
+    for (a, b), lens, scale in (
+            ((tuned.spmv(x)[0], ref.spmv(x)[0]), rl, np.abs(lp.csr()) @ np.abs(x)),
+            ((tuned.spmv(y, transpose=True)[0], ref.spmv(y, transpose=True)[0]), cl,
+             np.abs(lp.csr()).T @ np.abs(y))):
+        assert np.array_equal(a[lens <= short], b[lens <= short])
+        assert np.all(np.abs(a - b) <= 1e-14 * scale + 1e-300)
+    lp2 = lpgen.planted_uniform(900, 1350, 8, seed=102)
+    prm = pd.pdlp_params_default(stream_block=-1, eps_feas=1e-6, eps_gap=1e-6, max_iters=100_000)
+    r = pd.Problem(lp2, prm).solve(prm)
+    assert r["status_name"] == "OPTIMAL"
+    assert r["primal_res_rel"] <= 1e-6 and r["dual_res_rel"] <= 1e-6 and r["rel_gap"] <= 1e-6
+    assert lp2.c @ r["x"] == pytest.approx(lp2.p_star, rel=3e-6)
