@@ -155,3 +155,54 @@ def test_segmented_runs_are_deterministic():
         prob.close()
     for k in ("x", "y", "ax", "aty", "sx", "sy"):
         assert np.array_equal(out[0][k], out[1][k]), k
+
+
+def test_segmented_layout_on_sparse_wide_index_ranges():
+    """y' of 1.2M entries in 8 segments with only ~50k nonzeros: most rows
+    empty and whole segments without a short-column nonzero, long columns
+    crossing every segment, empty columns: the product against the oracle
+    (short columns bitwise), then 64 iterations against the oracle."""
+    say("segmented layout, sparse 1.2M-row LP")
+    import scipy.sparse as sp
+    rng = np.random.default_rng(17)
+    m, n = 1_200_000, 1500
+    rows, cols = [], []
+    for j in range(n):
+        if j % 500 == 7:
+            k = 4000                       # long columns over the whole row range
+            r = rng.choice(m, size=k, replace=False)
+        elif j % 3 == 0:
+            continue                       # empty columns
+        else:
+            k = int(rng.integers(1, 60))
+            r = rng.choice(200_000, size=k, replace=False) + 600_000 * (j % 2)
+        rows.append(r)
+        cols.append(np.full(r.size, j))
+    rows, cols = np.concatenate(rows), np.concatenate(cols)
+    A = sp.csr_matrix((rng.standard_normal(rows.size), (rows, cols)), shape=(m, n))
+    A.sort_indices()
+    x0 = rng.uniform(0, 1, n)
+    b = A @ x0
+    lp = lpgen.LP(m, n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data,
+                  rng.standard_normal(n), b - 0.5, b + 0.5, np.zeros(n), np.ones(n))
+    prob = pd.Problem(lp, gpu_params(ruiz_iters=0, pock_chambolle=0, segmented_gathers=1))
+    y = rng.standard_normal(m)
+    aty, _ = prob.spmv(y, transpose=True)
+    aty_o = oracle.spmv_t(oracle.LPView.of(lp), y)
+    cl = np.bincount(lp.col, minlength=n)
+    assert np.array_equal(aty[cl <= STAGE], aty_o[cl <= STAGE])
+    scale = np.abs(A).T @ np.abs(y)
+    assert np.all(np.abs(aty - aty_o) <= 1e-14 * scale + 1e-300)
+    prob.close()
+    prob = pd.Problem(lp, gpu_params(segmented_gathers=1))
+    st = prob.state(gpu_params(segmented_gathers=1))
+    o = oracle.Solver(lp)
+    info = st.iterate(64)
+    o.iterate(64)
+    oc = o.counters()
+    for key in ("k", "t", "n_outer", "attempts", "restarts_i", "restarts_ii", "restarts_iii"):
+        assert info[key] == oc[key], key
+    g = st.get()
+    for key in ("x", "y"):
+        assert rel(g[key], getattr(o, key)) <= 1e-8, key
+    prob.close()
