@@ -34,6 +34,10 @@
  *
  * Plain and sequential on purpose: every sum runs in index order, there is
  * no blocking or fusion, and the code is compiled with -ffp-contract=off.
+ * The few OpenMP pragmas and the _OPENMP branch of orc_spmv_t matter only in
+ * a separate threaded build of this file, used for the all-cores CPU
+ * baseline (row shards as in the paper's Section 5); the build the tests use
+ * ignores them.
  */
 #include "pdlp_oracle.h"
 
