@@ -355,6 +355,26 @@ int pdlp_batch_create(int32_t count, const int32_t *m, const int32_t *n, const i
                       const double *obj_offset_host, const pdlp_params *params,
                       void *hip_stream, pdlp_batch **out);
 
+/*
+ * Same as pdlp_batch_create, with the eight data arrays (row_ptr, col, val,
+ * c, lc, uc, lv, uv) in GPU memory, for instance torch tensors on the device
+ * (host memory is accepted too).  The sizes m, n, nnz and obj_offset stay
+ * host arrays: they fix how many bytes are read.  Validation and the packing
+ * run on the host, so the arrays are first copied there on hip_stream,
+ * after the work already queued on it; the caller keeps ownership and may
+ * free them when the call returns.  The lengths are trusted: row_ptr_dev
+ * must hold sum(m[i] + 1) entries, col_dev and val_dev sum(nnz[i]), c_dev,
+ * lv_dev and uv_dev sum(n[i]), lc_dev and uc_dev sum(m[i]).  Errors as
+ * pdlp_batch_create (the sizes are checked before anything is copied);
+ * HIP_ERROR for a pointer the runtime cannot copy from.
+ */
+int pdlp_batch_create_device(int32_t count, const int32_t *m, const int32_t *n,
+                             const int64_t *nnz, const int32_t *row_ptr_dev,
+                             const int32_t *col_dev, const double *val_dev, const double *c_dev,
+                             const double *lc_dev, const double *uc_dev, const double *lv_dev,
+                             const double *uv_dev, const double *obj_offset_host,
+                             const pdlp_params *params, void *hip_stream, pdlp_batch **out);
+
 void pdlp_batch_destroy(pdlp_batch *b);
 
 /* Instance count and batch totals. */
@@ -418,6 +438,15 @@ int pdlp_unroll_create(int32_t count, const int32_t *m, const int32_t *n, const 
                        const double *val_host, const double *c_host, const double *lc_host,
                        const double *uc_host, const double *lv_host, const double *uv_host,
                        const pdlp_params *params, void *hip_stream, pdlp_unroll **out);
+/* The same from data arrays in GPU memory, staged on the host on hip_stream
+ * as for pdlp_batch_create_device (sizes m, n, nnz on the host, lengths
+ * trusted).  Errors as pdlp_batch_create_device. */
+int pdlp_unroll_create_device(int32_t count, const int32_t *m, const int32_t *n,
+                              const int64_t *nnz, const int32_t *row_ptr_dev,
+                              const int32_t *col_dev, const double *val_dev,
+                              const double *c_dev, const double *lc_dev, const double *uc_dev,
+                              const double *lv_dev, const double *uv_dev,
+                              const pdlp_params *params, void *hip_stream, pdlp_unroll **out);
 void pdlp_unroll_destroy(pdlp_unroll *u);
 
 /* Replace the data (original units, concatenated as at creation; any

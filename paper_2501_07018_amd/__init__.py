@@ -124,7 +124,8 @@ EXPORTS = ("pdlp_problem_create", "pdlp_problem_create_device", "pdlp_problem_de
            "pdlp_unroll_forward", "pdlp_unroll_replay", "pdlp_unroll_backward",
            "pdlp_unroll_get_tape", "pdlp_unroll_get_stats", "pdlp_spmv_noalloc",
            "pdlp_unroll_tangent", "pdlp_unroll_set_data_device", "pdlp_unroll_forward_device",
-           "pdlp_unroll_backward_device", "pdlp_unroll_tangent_device")
+           "pdlp_unroll_backward_device", "pdlp_unroll_tangent_device",
+           "pdlp_batch_create_device", "pdlp_unroll_create_device")
 
 
 def lib() -> C.CDLL:
@@ -182,6 +183,10 @@ def lib() -> C.CDLL:
     L.pdlp_unroll_forward_device.argtypes = [vp, C.POINTER(Params), C.c_int64, C.c_int32, vp, vp]
     L.pdlp_unroll_backward_device.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.pdlp_unroll_tangent_device.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.pdlp_batch_create_device.argtypes = [C.c_int32, I32, I32, I64] + [vp] * 8 + \
+        [D, C.POINTER(Params), vp, C.POINTER(vp)]
+    L.pdlp_unroll_create_device.argtypes = [C.c_int32, I32, I32, I64] + [vp] * 8 + \
+        [C.POINTER(Params), vp, C.POINTER(vp)]
     L.pdlp_unroll_get_tape.argtypes = [vp, D, D, I32]
     L.pdlp_unroll_get_stats.argtypes = [vp, C.POINTER(UnrollStats)]
     L.pdlp_last_error.argtypes = []
@@ -423,6 +428,31 @@ def pdlp_batch_get_stats(h) -> dict:
     return {f: getattr(st, f) for f, _ in BatchStats._fields_}
 
 
+def _batch_tensors(m, n, nnz, ts):
+    """Sizes as host arrays and the device addresses of the eight data tensors
+    (row_ptr, col, val, c, lc, uc, lv, uv) of a batch in GPU memory; checks
+    dtypes and lengths before anything is handed to the library."""
+    import torch
+    m = np.ascontiguousarray(m, dtype=np.int32)
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    nnz = np.ascontiguousarray(nnz, dtype=np.int64)
+    if not (m.ndim == n.ndim == nnz.ndim == 1) or not (len(m) == len(n) == len(nnz) >= 1):
+        raise ValueError("m, n and nnz must be 1-D with one entry per instance")
+    if (m < 0).any() or (n < 1).any() or (nnz < 0).any():
+        raise ValueError("need m >= 0, n >= 1 and nnz >= 0 for every instance")
+    M, N, NZ = int(m.sum()), int(n.sum()), int(nnz.sum())
+    want = {"row_ptr": M + len(m), "col": NZ, "val": NZ, "c": N, "lc": M, "uc": M,
+            "lv": N, "uv": N}
+    for i, (name, t) in enumerate(zip(want, ts)):
+        dt = torch.int32 if i < 2 else torch.float64
+        if t.dtype != dt or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("tensors must be contiguous CUDA tensors: int32 row_ptr and col, "
+                             "float64 val, c, lc, uc, lv, uv")
+        if t.numel() != want[name]:
+            raise ValueError(f"{name} has {t.numel()} elements, expected {want[name]}")
+    return m, n, nnz, [_vp(t.data_ptr()) for t in ts]
+
+
 class Batch:
     """Owner of a batch handle; solve() returns per-instance result dicts with
     the instance's x, y, r split out of the concatenated outputs."""
@@ -431,6 +461,29 @@ class Batch:
         self.m = [int(lp.m) for lp in lps]
         self.n = [int(lp.n) for lp in lps]
         self.h = pdlp_batch_create(lps, params, stream)
+
+    @classmethod
+    def from_tensors(cls, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, obj_offset=None,
+                     params: Params | None = None) -> "Batch":
+        """Create from torch tensors in GPU memory (the instances' arrays
+        concatenated as for pdlp_batch_create), read on the current torch
+        stream; m, n, nnz and obj_offset are host sequences."""
+        import torch
+        m, n, nnz, ptrs = _batch_tensors(m, n, nnz, (row_ptr, col, val, c, lc, uc, lv, uv))
+        off = None if obj_offset is None else _f64(obj_offset)
+        if off is not None and len(off) != len(m):
+            raise ValueError("obj_offset needs one entry per instance")
+        self = cls.__new__(cls)
+        self.m, self.n = [int(v) for v in m], [int(v) for v in n]
+        self.h = None
+        h = C.c_void_p()
+        _check(lib().pdlp_batch_create_device(
+            len(m), m.ctypes.data_as(I32), n.ctypes.data_as(I32),
+            nnz.ctypes.data_as(C.POINTER(C.c_int64)), *ptrs, _d(off),
+            C.byref(params) if params is not None else None,
+            C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(h)))
+        self.h = h
+        return self
 
     def solve(self, params: Params | None = None, want_solution=True) -> list:
         res, x, y, r = pdlp_batch_solve(self.h, params, want_solution)
@@ -495,6 +548,26 @@ class Unroll:
                                         C.byref(params) if params is not None else None, stream,
                                         C.byref(self.h)))
         self.K = None
+
+    @classmethod
+    def from_tensors(cls, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv,
+                     params: Params | None = None) -> "Unroll":
+        """Create from torch tensors in GPU memory (laid out as for Batch), read
+        on the current torch stream; m, n and nnz are host sequences."""
+        import torch
+        m, n, nnz, ptrs = _batch_tensors(m, n, nnz, (row_ptr, col, val, c, lc, uc, lv, uv))
+        self = cls.__new__(cls)
+        self.count = len(m)
+        self.m, self.n, self.nnz = m, n, nnz
+        self.M, self.N, self.NZ = int(m.sum()), int(n.sum()), int(nnz.sum())
+        self.h = C.c_void_p()
+        self.K = None
+        _check(lib().pdlp_unroll_create_device(
+            self.count, m.ctypes.data_as(I32), n.ctypes.data_as(I32),
+            nnz.ctypes.data_as(C.POINTER(C.c_int64)), *ptrs,
+            C.byref(params) if params is not None else None,
+            C.c_void_p(torch.cuda.current_stream().cuda_stream), C.byref(self.h)))
+        return self
 
     def set_data(self, c=None, lc=None, uc=None, val=None):
         arrs = [None if a is None else _f64(a) for a in (c, lc, uc, val)]

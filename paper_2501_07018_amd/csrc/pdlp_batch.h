@@ -24,6 +24,23 @@ struct BatchRecord {
     int32_t nck = 0;            //   (post-restart), laid out x | y | Sx | Sy
 };
 
+// Checks the per-instance sizes of a batch (count >= 1; m >= 0, n >= 1,
+// nnz >= 0 each) and returns their totals, each below 2^31.
+void batch_totals(int32_t count, const int32_t *m, const int32_t *n, const int64_t *nnz,
+                  int64_t &M, int64_t &N, int64_t &NZ);
+
+// Host copies of a batch's concatenated instance arrays given in GPU memory
+// (the *_create_device calls): lengths from the host size arrays m, n, nnz;
+// copied on hip_stream after the work already queued there, and waited for.
+struct StagedBatch {
+    std::vector<int32_t> row_ptr, col;
+    std::vector<double> val, c, lc, uc, lv, uv;
+};
+StagedBatch stage_batch(int32_t count, const int32_t *m, const int32_t *n, const int64_t *nnz,
+                        const int32_t *row_ptr, const int32_t *col, const double *val,
+                        const double *c, const double *lc, const double *uc, const double *lv,
+                        const double *uv, void *hip_stream);
+
 // Packs `count` instances (arrays concatenated in instance order, local
 // column labels) into a batch; validates every instance.  sort_gathers adds
 // the column-sorted block copies of the matrices (refresh_block_gathers

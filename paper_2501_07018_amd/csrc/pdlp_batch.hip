@@ -925,15 +925,11 @@ void build_maps(pdlp_batch *b) {
 
 }  // namespace
 
-pdlp_batch *pdlp::host::make_batch(int32_t count, const int32_t *m, const int32_t *n,
-                                   const int64_t *nnz, const int32_t *row_ptr,
-                                   const int32_t *col, const double *val, const double *c,
-                                   const double *lc, const double *uc, const double *lv,
-                                   const double *uv, const double *obj_offset,
-                                   const pdlp_params *params, void *hip_stream, bool sort_gathers) {
+void pdlp::host::batch_totals(int32_t count, const int32_t *m, const int32_t *n,
+                               const int64_t *nnz, int64_t &M, int64_t &N, int64_t &NZ) {
     if (count < 1) invalid("count must be >= 1");
-    if (!m || !n || !nnz || !row_ptr) invalid("NULL size array");
-    int64_t M = 0, N = 0, NZ = 0;
+    if (!m || !n || !nnz) invalid("NULL size array");
+    M = N = NZ = 0;
     for (int32_t i = 0; i < count; ++i) {
         if (m[i] < 0 || n[i] < 1 || nnz[i] < 0)
             invalid("instance " + std::to_string(i) + ": need m >= 0, n >= 1, nnz >= 0");
@@ -943,7 +939,53 @@ pdlp_batch *pdlp::host::make_batch(int32_t count, const int32_t *m, const int32_
     }
     const int64_t lim = std::numeric_limits<int32_t>::max();
     if (M >= lim || N >= lim || NZ >= lim) invalid("batch totals must stay below 2^31");
-    if ((NZ > 0 && (!col || !val)) || !c || (M > 0 && (!lc || !uc)) || !lv || !uv)
+}
+
+pdlp::host::StagedBatch pdlp::host::stage_batch(int32_t count, const int32_t *m,
+                                                const int32_t *n, const int64_t *nnz,
+                                                const int32_t *row_ptr, const int32_t *col,
+                                                const double *val, const double *c,
+                                                const double *lc, const double *uc,
+                                                const double *lv, const double *uv,
+                                                void *hip_stream) {
+    int64_t M = 0, N = 0, NZ = 0;
+    batch_totals(count, m, n, nnz, M, N, NZ);
+    if (!row_ptr || (NZ > 0 && (!col || !val)) || !c || (M > 0 && (!lc || !uc)) || !lv || !uv)
+        invalid("NULL input array");
+    StagedBatch h;
+    h.row_ptr.resize((size_t)(M + count));
+    h.col.resize((size_t)NZ);
+    h.val.resize((size_t)NZ);
+    h.c.resize((size_t)N);
+    h.lc.resize((size_t)M);
+    h.uc.resize((size_t)M);
+    h.lv.resize((size_t)N);
+    h.uv.resize((size_t)N);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    auto get = [&](void *dst, const void *src, size_t bytes) {
+        if (bytes) HIPCHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, s));
+    };
+    get(h.row_ptr.data(), row_ptr, sizeof(int32_t) * h.row_ptr.size());
+    get(h.col.data(), col, sizeof(int32_t) * h.col.size());
+    get(h.val.data(), val, sizeof(double) * h.val.size());
+    get(h.c.data(), c, sizeof(double) * h.c.size());
+    get(h.lc.data(), lc, sizeof(double) * h.lc.size());
+    get(h.uc.data(), uc, sizeof(double) * h.uc.size());
+    get(h.lv.data(), lv, sizeof(double) * h.lv.size());
+    get(h.uv.data(), uv, sizeof(double) * h.uv.size());
+    HIPCHECK(hipStreamSynchronize(s));
+    return h;
+}
+
+pdlp_batch *pdlp::host::make_batch(int32_t count, const int32_t *m, const int32_t *n,
+                                   const int64_t *nnz, const int32_t *row_ptr,
+                                   const int32_t *col, const double *val, const double *c,
+                                   const double *lc, const double *uc, const double *lv,
+                                   const double *uv, const double *obj_offset,
+                                   const pdlp_params *params, void *hip_stream, bool sort_gathers) {
+    int64_t M = 0, N = 0, NZ = 0;
+    batch_totals(count, m, n, nnz, M, N, NZ);
+    if (!row_ptr || (NZ > 0 && (!col || !val)) || !c || (M > 0 && (!lc || !uc)) || !lv || !uv)
         invalid("NULL input array");
     // per-instance checks, then pack: global row pointers and column labels
     std::vector<int32_t> rp((size_t)M + 1), cg((size_t)NZ);
@@ -1023,6 +1065,23 @@ int pdlp_batch_create(int32_t count, const int32_t *m, const int32_t *n, const i
         *out = nullptr;
         *out = make_batch(count, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, obj_offset,
                           params, hip_stream, true);
+    });
+}
+
+int pdlp_batch_create_device(int32_t count, const int32_t *m, const int32_t *n,
+                             const int64_t *nnz, const int32_t *row_ptr, const int32_t *col,
+                             const double *val, const double *c, const double *lc,
+                             const double *uc, const double *lv, const double *uv,
+                             const double *obj_offset, const pdlp_params *params,
+                             void *hip_stream, pdlp_batch **out) {
+    return guarded([&] {
+        if (!out) invalid("out is NULL");
+        *out = nullptr;
+        const StagedBatch h = stage_batch(count, m, n, nnz, row_ptr, col, val, c, lc, uc, lv,
+                                          uv, hip_stream);
+        *out = make_batch(count, m, n, nnz, h.row_ptr.data(), h.col.data(), h.val.data(),
+                          h.c.data(), h.lc.data(), h.uc.data(), h.lv.data(), h.uv.data(),
+                          obj_offset, params, hip_stream, true);
     });
 }
 

@@ -373,6 +373,78 @@ void tangent(pdlp_unroll *u, const double *dc, const double *dlc, const double *
     sync(u);
 }
 
+// Creation from host arrays (pdlp_unroll_create and, after staging device
+// arrays on the host, pdlp_unroll_create_device).
+pdlp_unroll *unroll_new(int32_t count, const int32_t *m, const int32_t *n, const int64_t *nnz,
+                        const int32_t *row_ptr, const int32_t *col, const double *val,
+                        const double *c, const double *lc, const double *uc, const double *lv,
+                        const double *uv, const pdlp_params *params, void *hip_stream) {
+    auto *u = new pdlp_unroll();
+    try {
+        u->b = make_batch(count, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, nullptr,
+                          params, hip_stream, true);
+        u->arena = new Arena();
+        pdlp_problem *P = u->b->P;
+        u->N = P->n;
+        u->M = P->m;
+        u->NZ = P->nnz;
+        hipStream_t st = P->stream;
+        // A entry -> position in A^T (columns of A^T keep increasing row order)
+        std::vector<int32_t> rp((size_t)u->M + 1), cl((size_t)u->NZ), trp((size_t)u->N + 1),
+            a2t((size_t)u->NZ);
+        HIPCHECK(hipMemcpy(rp.data(), P->A.row_ptr, sizeof(int32_t) * rp.size(),
+                           hipMemcpyDeviceToHost));
+        if (u->NZ > 0)
+            HIPCHECK(hipMemcpy(cl.data(), P->A.col, sizeof(int32_t) * cl.size(),
+                               hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(trp.data(), P->AT.row_ptr, sizeof(int32_t) * trp.size(),
+                           hipMemcpyDeviceToHost));
+        std::vector<int32_t> next(trp.begin(), trp.end() - 1);
+        for (int64_t r = 0; r < u->M; ++r)
+            for (int32_t e = rp[r]; e < rp[r + 1]; ++e) a2t[e] = next[cl[e]]++;
+        Arena &a = *u->arena;
+        u->val_orig = a.dev<double>(u->NZ);
+        u->a2t = a.dev<int32_t>(u->NZ);
+        if (u->NZ > 0) {
+            HIPCHECK(hipMemcpyAsync(u->a2t, a2t.data(), sizeof(int32_t) * u->NZ,
+                                    hipMemcpyHostToDevice, st));
+            HIPCHECK(hipMemcpyAsync(u->val_orig, val, sizeof(double) * u->NZ,
+                                    hipMemcpyHostToDevice, st));
+            HIPCHECK(pdlp::launch_u_scale_values(st, P->A, u->val_orig, P->d1, P->d2, u->a2t,
+                                                 P->A.val, P->AT.val));
+            refresh_block_gathers(P, st);
+        }
+        // identity lists: every instance and block in order
+        const BatchMaps &bm = u->b->bm;
+        std::vector<int32_t> il(u->b->B), al(bm.nA), tl(bm.nT), cll(bm.nA + bm.nT);
+        for (size_t k = 0; k < il.size(); ++k) il[k] = (int32_t)k;
+        for (size_t k = 0; k < al.size(); ++k) al[k] = (int32_t)k;
+        for (size_t k = 0; k < tl.size(); ++k) tl[k] = (int32_t)k;
+        for (size_t k = 0; k < cll.size(); ++k) cll[k] = (int32_t)k;
+        int32_t *d_i = a.dev<int32_t>(il.size()), *d_a = a.dev<int32_t>(al.size());
+        int32_t *d_t = a.dev<int32_t>(tl.size()), *d_c = a.dev<int32_t>(cll.size());
+        HIPCHECK(hipMemcpyAsync(d_i, il.data(), sizeof(int32_t) * il.size(), hipMemcpyHostToDevice, st));
+        if (!al.empty())
+            HIPCHECK(hipMemcpyAsync(d_a, al.data(), sizeof(int32_t) * al.size(), hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(d_t, tl.data(), sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(d_c, cll.data(), sizeof(int32_t) * cll.size(), hipMemcpyHostToDevice, st));
+        u->all = bm;
+        u->all.ni = (int32_t)il.size();
+        u->all.na = (int32_t)al.size();
+        u->all.nt = (int32_t)tl.size();
+        u->all.nc = (int32_t)cll.size();
+        u->all.ilist = d_i;
+        u->all.alist = d_a;
+        u->all.tlist = d_t;
+        u->all.clist = d_c;
+        HIPCHECK(hipStreamSynchronize(st));
+    } catch (...) {
+        delete u;
+        throw;
+    }
+    return u;
+}
+
 }  // namespace
 
 extern "C" {
@@ -385,70 +457,24 @@ int pdlp_unroll_create(int32_t count, const int32_t *m, const int32_t *n, const 
     return guarded([&] {
         if (!out) invalid("out is NULL");
         *out = nullptr;
-        auto *u = new pdlp_unroll();
-        try {
-            u->b = make_batch(count, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, nullptr,
-                              params, hip_stream, true);
-            u->arena = new Arena();
-            pdlp_problem *P = u->b->P;
-            u->N = P->n;
-            u->M = P->m;
-            u->NZ = P->nnz;
-            hipStream_t st = P->stream;
-            // A entry -> position in A^T (columns of A^T keep increasing row order)
-            std::vector<int32_t> rp((size_t)u->M + 1), cl((size_t)u->NZ), trp((size_t)u->N + 1),
-                a2t((size_t)u->NZ);
-            HIPCHECK(hipMemcpy(rp.data(), P->A.row_ptr, sizeof(int32_t) * rp.size(),
-                               hipMemcpyDeviceToHost));
-            if (u->NZ > 0)
-                HIPCHECK(hipMemcpy(cl.data(), P->A.col, sizeof(int32_t) * cl.size(),
-                                   hipMemcpyDeviceToHost));
-            HIPCHECK(hipMemcpy(trp.data(), P->AT.row_ptr, sizeof(int32_t) * trp.size(),
-                               hipMemcpyDeviceToHost));
-            std::vector<int32_t> next(trp.begin(), trp.end() - 1);
-            for (int64_t r = 0; r < u->M; ++r)
-                for (int32_t e = rp[r]; e < rp[r + 1]; ++e) a2t[e] = next[cl[e]]++;
-            Arena &a = *u->arena;
-            u->val_orig = a.dev<double>(u->NZ);
-            u->a2t = a.dev<int32_t>(u->NZ);
-            if (u->NZ > 0) {
-                HIPCHECK(hipMemcpyAsync(u->a2t, a2t.data(), sizeof(int32_t) * u->NZ,
-                                        hipMemcpyHostToDevice, st));
-                HIPCHECK(hipMemcpyAsync(u->val_orig, val, sizeof(double) * u->NZ,
-                                        hipMemcpyHostToDevice, st));
-                HIPCHECK(pdlp::launch_u_scale_values(st, P->A, u->val_orig, P->d1, P->d2, u->a2t,
-                                                     P->A.val, P->AT.val));
-                refresh_block_gathers(P, st);
-            }
-            // identity lists: every instance and block in order
-            const BatchMaps &bm = u->b->bm;
-            std::vector<int32_t> il(u->b->B), al(bm.nA), tl(bm.nT), cll(bm.nA + bm.nT);
-            for (size_t k = 0; k < il.size(); ++k) il[k] = (int32_t)k;
-            for (size_t k = 0; k < al.size(); ++k) al[k] = (int32_t)k;
-            for (size_t k = 0; k < tl.size(); ++k) tl[k] = (int32_t)k;
-            for (size_t k = 0; k < cll.size(); ++k) cll[k] = (int32_t)k;
-            int32_t *d_i = a.dev<int32_t>(il.size()), *d_a = a.dev<int32_t>(al.size());
-            int32_t *d_t = a.dev<int32_t>(tl.size()), *d_c = a.dev<int32_t>(cll.size());
-            HIPCHECK(hipMemcpyAsync(d_i, il.data(), sizeof(int32_t) * il.size(), hipMemcpyHostToDevice, st));
-            if (!al.empty())
-                HIPCHECK(hipMemcpyAsync(d_a, al.data(), sizeof(int32_t) * al.size(), hipMemcpyHostToDevice, st));
-            HIPCHECK(hipMemcpyAsync(d_t, tl.data(), sizeof(int32_t) * tl.size(), hipMemcpyHostToDevice, st));
-            HIPCHECK(hipMemcpyAsync(d_c, cll.data(), sizeof(int32_t) * cll.size(), hipMemcpyHostToDevice, st));
-            u->all = bm;
-            u->all.ni = (int32_t)il.size();
-            u->all.na = (int32_t)al.size();
-            u->all.nt = (int32_t)tl.size();
-            u->all.nc = (int32_t)cll.size();
-            u->all.ilist = d_i;
-            u->all.alist = d_a;
-            u->all.tlist = d_t;
-            u->all.clist = d_c;
-            HIPCHECK(hipStreamSynchronize(st));
-        } catch (...) {
-            delete u;
-            throw;
-        }
-        *out = u;
+        *out = unroll_new(count, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, params,
+                          hip_stream);
+    });
+}
+
+int pdlp_unroll_create_device(int32_t count, const int32_t *m, const int32_t *n,
+                              const int64_t *nnz, const int32_t *row_ptr, const int32_t *col,
+                              const double *val, const double *c, const double *lc,
+                              const double *uc, const double *lv, const double *uv,
+                              const pdlp_params *params, void *hip_stream, pdlp_unroll **out) {
+    return guarded([&] {
+        if (!out) invalid("out is NULL");
+        *out = nullptr;
+        const StagedBatch h = stage_batch(count, m, n, nnz, row_ptr, col, val, c, lc, uc, lv,
+                                          uv, hip_stream);
+        *out = unroll_new(count, m, n, nnz, h.row_ptr.data(), h.col.data(), h.val.data(),
+                          h.c.data(), h.lc.data(), h.uc.data(), h.lv.data(), h.uv.data(),
+                          params, hip_stream);
     });
 }
 

@@ -73,5 +73,16 @@ class LPLayer(torch.nn.Module):
         self.unroll = Unroll(lps, params)
         self.K, self.ckpt, self.params = int(K), int(ckpt), params
 
+    @classmethod
+    def from_tensors(cls, m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, K: int = 500,
+                     ckpt: int = 25, params: Params | None = None) -> "LPLayer":
+        """The layer of a batch given as CUDA tensors (see Unroll.from_tensors);
+        the scalings are those of the data given here."""
+        self = cls.__new__(cls)
+        torch.nn.Module.__init__(self)
+        self.unroll = Unroll.from_tensors(m, n, nnz, row_ptr, col, val, c, lc, uc, lv, uv, params)
+        self.K, self.ckpt, self.params = int(K), int(ckpt), params
+        return self
+
     def forward(self, c, lc, uc, val):
         return UnrolledPDHG.apply(c, lc, uc, val, self.unroll, self.K, self.ckpt, self.params)

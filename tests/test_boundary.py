@@ -119,3 +119,43 @@ def test_empty_batch_is_rejected():
     rc = pd.lib().pdlp_batch_create(0, None, None, None, None, None, None, None, None, None,
                                     None, None, None, None, None, C.byref(h))
     assert rc == pd.PDLP_ERR_INVALID_ARGUMENT and not h.value
+
+
+@pytest.mark.parametrize("fn", ["pdlp_batch_create_device", "pdlp_unroll_create_device"])
+def test_device_batch_creation_checks_sizes_before_any_copy(fn):
+    """The device-input creation calls check the host size arrays (and NULL
+    data pointers) before they copy anything, so bad sizes never reach the
+    runtime; here no GPU is present at all."""
+    f = getattr(pd.lib(), fn)
+    extra = [None] if fn == "pdlp_batch_create_device" else []   # obj_offset
+    h = C.c_void_p()
+    rc = f(0, None, None, None, *[None] * 8, *extra, None, None, C.byref(h))
+    assert rc == pd.PDLP_ERR_INVALID_ARGUMENT and not h.value
+    m = np.array([3, 2], np.int32)
+    n = np.array([4, 0], np.int32)        # instance 1 has no columns
+    nnz = np.array([5, 1], np.int64)
+    rc = f(2, m.ctypes.data_as(pd.I32), n.ctypes.data_as(pd.I32),
+           nnz.ctypes.data_as(C.POINTER(C.c_int64)), *[None] * 8, *extra, None, None, C.byref(h))
+    assert rc == pd.PDLP_ERR_INVALID_ARGUMENT and not h.value
+    assert "instance 1" in pd.lib().pdlp_last_error().decode()
+    n[1] = 3
+    rc = f(2, m.ctypes.data_as(pd.I32), n.ctypes.data_as(pd.I32),
+           nnz.ctypes.data_as(C.POINTER(C.c_int64)), *[None] * 8, *extra, None, None, C.byref(h))
+    assert rc == pd.PDLP_ERR_INVALID_ARGUMENT and not h.value
+    assert "NULL" in pd.lib().pdlp_last_error().decode()
+
+
+def test_from_tensors_checks_before_the_library():
+    """Batch/Unroll.from_tensors refuse host tensors, wrong dtypes and wrong
+    lengths in Python, before any call into the library."""
+    torch = pytest.importorskip("torch")
+    lp = _tiny()
+    m, n, nnz = [len(lp["lc"])], [len(lp["c"])], [len(lp["col"])]
+    ts = [torch.as_tensor(lp[k]) for k in ("row_ptr", "col", "val", "c", "lc", "uc", "lv", "uv")]
+    for cls in (pd.Batch, pd.Unroll):
+        with pytest.raises(ValueError, match="CUDA tensors"):
+            cls.from_tensors(m, n, nnz, *ts)
+        with pytest.raises(ValueError, match="n >= 1"):
+            cls.from_tensors(m, [0], nnz, *ts)
+        with pytest.raises(ValueError, match="one entry per instance"):
+            cls.from_tensors(m + m, n, nnz, *ts)

@@ -178,3 +178,88 @@ def test_layer_on_device_tensors_matches_the_host_path():
     assert got["device"].startswith("cuda"), got
     assert all(got["same"]), got    # x_K and the four gradients, bitwise
     assert got["refused"], got
+
+
+_BATCH_CHILD = r"""
+import json, sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+import lpgen
+import paper_2501_07018_amd as pd
+from paper_2501_07018_amd.layer import LPLayer
+lps = [lpgen.planted_uniform(150, 225, 8, seed=101), lpgen.tiny_random_lp(104, 7, 12),
+       lpgen.planted_skewed(1000, 2000, seed=106, mean_degree=4.0, cap=500, n_dense=10,
+                            dense_frac=0.3)]
+d = torch.device("cuda:0")
+i32, f64 = torch.int32, torch.float64
+keys = ("row_ptr", "col", "val", "c", "lc", "uc", "lv", "uv")
+def cat(k, lst=lps):
+    return np.concatenate([np.asarray(getattr(lp, k)) for lp in lst])
+def tens(arrs):
+    return [torch.as_tensor(np.ascontiguousarray(arrs[k])).to(
+        dtype=i32 if k in ("row_ptr", "col") else f64, device=d) for k in keys]
+m = [lp.m for lp in lps]
+n = [lp.n for lp in lps]
+nnz = [lp.nnz for lp in lps]
+arrs = {k: cat(k) for k in keys}
+prm = pd.pdlp_params_default(eps_feas=1e-7, eps_gap=1e-7, max_iters=6000)
+rh = pd.Batch(lps).solve(prm)
+rd = pd.Batch.from_tensors(m, n, nnz, *tens(arrs)).solve(prm)
+batch_same = all(a["status_name"] == b["status_name"] and a["iterations"] == b["iterations"]
+                 and all(np.array_equal(a[k], b[k]) for k in ("x", "y", "r"))
+                 for a, b in zip(rh, rd))
+# wrong lengths are refused before anything is handed over
+short = []
+for k in keys:
+    a = dict(arrs)
+    a[k] = a[k][:-1]
+    try:
+        pd.Batch.from_tensors(m, n, nnz, *tens(a))
+        short.append((k, "accepted"))
+    except ValueError:
+        short.append((k, "refused"))
+# invalid data in one instance is refused by the library, naming the instance
+bad = dict(arrs)
+bad["lc"] = arrs["lc"].copy()
+bad["lc"][lps[0].m + 1] = bad["uc"][lps[0].m + 1] + 1.0
+try:
+    pd.Batch.from_tensors(m, n, nnz, *tens(bad))
+    invalid = "accepted"
+except pd.PdlpError as e:
+    invalid = "instance 1" if (e.code == pd.PDLP_ERR_INVALID_ARGUMENT and "instance 1" in str(e)) else str(e)
+# the unrolled map and the layer built from device tensors
+lay = [lpgen.planted_uniform(60, 100, 5, seed=3), lpgen.planted_uniform(150, 225, 8, seed=101)]
+la = {k: cat(k, lay) for k in keys}
+lm, ln, lz = [lp.m for lp in lay], [lp.n for lp in lay], [lp.nnz for lp in lay]
+uh = pd.Unroll(lay)
+ud = pd.Unroll.from_tensors(lm, ln, lz, *tens(la))
+xh, xd = uh.forward(60, 25), ud.forward(60, 25)
+gx = np.random.default_rng(3).standard_normal(len(xh))
+gh, gd = uh.backward(gx), ud.backward(gx)
+unroll_same = bool(np.array_equal(xh, xd)) and all(np.array_equal(gh[k], gd[k]) for k in gh)
+layers = []
+for layer in (LPLayer(lay, K=60, ckpt=25), LPLayer.from_tensors(lm, ln, lz, *tens(la), K=60,
+                                                                ckpt=25)):
+    ts = [torch.tensor(la[k], device=d, requires_grad=True) for k in ("c", "lc", "uc", "val")]
+    x = layer(*ts)
+    (x * torch.tensor(gx, device=d)).sum().backward()
+    layers.append([x.detach().cpu().numpy()] + [t.grad.detach().cpu().numpy() for t in ts])
+layer_same = all(np.array_equal(a, b) for a, b in zip(*layers))
+print(json.dumps({"batch_same": batch_same, "short": short, "invalid": invalid,
+                  "unroll_same": unroll_same, "layer_same": bool(layer_same)}))
+"""
+
+
+def test_batch_and_unroll_from_device_tensors_match_the_host_path():
+    say("Batch / Unroll / LPLayer from CUDA tensors vs host arrays (child process)")
+    pytest.importorskip("torch")
+    out = subprocess.run([sys.executable, "-c", _BATCH_CHILD, ROOT], capture_output=True,
+                         text=True, timeout=240)
+    assert out.returncode == 0, out.stderr[-2000:]
+    got = json.loads(out.stdout.strip().splitlines()[-1])
+    assert got["batch_same"], got          # solves bitwise equal to the host-array batch
+    assert got["short"] and all(v == "refused" for _, v in got["short"]), got["short"]
+    assert got["invalid"] == "instance 1", got
+    assert got["unroll_same"], got         # x_K and gradients bitwise equal
+    assert got["layer_same"], got
