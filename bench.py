@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel source they were taken on (hash of the hot-path
 # region of the kernels and constants); reported as null otherwise.
 TRAFFIC_RECORD = {
-    "hot_source": "f134d5146ee8e847",
-    "k_spmv_dual": 9175939680,
-    "k_seg_gather_primal+k_seg_primal": 8606410160,   # 5637942912 + 2968467248
+    "hot_source": "672f4d36f6d08e1c",
+    "k_spmv_dual": 9175810240,
+    "k_seg_gather_primal+k_seg_primal": 8243926464,   # 5636830336 + 2607096128
     "k_spmv_primal": None,                             # not run on this workload any more
 }
 

@@ -369,7 +369,10 @@ __device__ __forceinline__ void staged_spmv(const SegCsr &sg, Epi &epi, double (
                 else z = mid - 1;
             }
             const int64_t qi = (int64_t)run_lo[a] + (q - run_at[a]);
-            prod[stream_load(sg.slot + qi)] = stream_load(sg.Q + qi);
+            // plain loads: the runs are short and unaligned, so neighbouring
+            // runs (other lanes, the next block on this CU) share cache lines
+            // that the non-temporal hint would keep out of L1
+            prod[sg.slot[qi]] = sg.Q[qi];
         }
         __syncthreads();
         if (rr < r1) {
