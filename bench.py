@@ -43,6 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # region of the kernels and constants); reported as null otherwise.
 TRAFFIC_RECORD = {
     "hot_source": "672f4d36f6d08e1c",
+    "workload": ("skewed", 124695196),                 # the default 20M x 25M LP only
     "k_spmv_dual": 9175810240,
     "k_seg_gather_primal+k_seg_primal": 8243926464,   # 5636830336 + 2607096128
     "k_spmv_primal": None,                             # not run on this workload any more
@@ -352,6 +353,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=("skewed", "grid"), default="skewed",
+                    help="single-LP workload: the planted skewed LP (--m x --n, the default) or "
+                         "the L x L multicommodity grid (--grid-side; kernel profiles only)")
+    ap.add_argument("--grid-side", type=int, default=300)
     ap.add_argument("--m", type=int, default=20_000_000)
     ap.add_argument("--n", type=int, default=25_000_000)
     ap.add_argument("--cpu-steps", type=int, default=8)
@@ -367,7 +372,7 @@ def main():
     ap.add_argument("--unroll-k", type=int, default=500)
     ap.add_argument("--solve-budget", type=float, default=0.0,
                     help="after the timed steps, continue the same solve to its tolerances "
-                         "(1% gap, polishing to 1e-8) for at most this many seconds")
+                         "(1%% gap, polishing to 1e-8) for at most this many seconds")
     ap.add_argument("--stream-block", type=int, default=0,
                     help="stream-block schedule of the 20M x 25M problem: 0 default, -1 autotune "
                          "on the solver's steps, else nonzeros per block")
@@ -390,12 +395,18 @@ def main():
     import paper_2501_07018_amd as pd
 
     t0 = time.perf_counter()
-    lp = lpgen.skewed_lp(args.m, args.n, verbose=True)
-    st = lp.stats()
-    log(f"generated {st} in {time.perf_counter() - t0:.1f}s")
-
-    prm = pd.pdlp_params_default(eps_feas=1e-8, eps_gap=1e-2, polish=1, profile=1,
-                                 stream_block=args.stream_block)
+    if args.workload == "grid":
+        lp = lpgen.grid_flow_lp(L=args.grid_side)
+        log(f"generated the {args.grid_side} x {args.grid_side} grid ({lp.m} x {lp.n}, "
+            f"{lp.nnz} nonzeros) in {time.perf_counter() - t0:.1f}s")
+        prm = pd.pdlp_params_default(eps_feas=1e-6, eps_gap=1e-6, profile=1,
+                                     stream_block=args.stream_block)
+    else:
+        lp = lpgen.skewed_lp(args.m, args.n, verbose=True)
+        st = lp.stats()
+        log(f"generated {st} in {time.perf_counter() - t0:.1f}s")
+        prm = pd.pdlp_params_default(eps_feas=1e-8, eps_gap=1e-2, polish=1, profile=1,
+                                     stream_block=args.stream_block)
     t0 = time.perf_counter()
     prob = pd.Problem(lp, prm)
     state = prob.state(prm)
@@ -467,7 +478,11 @@ def main():
         "config": {
             "workload": (f"planted skewed LP {m}x{n}, {nnz} nonzeros (power-law column degrees "
                          f"capped at 10,000, 5,000 dense rows); eps_feas 1e-8, eps_gap 1e-2, "
-                         f"polishing on; step = 64 accepted PDHG iterations + periodic check"),
+                         f"polishing on; step = 64 accepted PDHG iterations + periodic check"
+                         if args.workload == "skewed" else
+                         f"multicommodity grid {args.grid_side}x{args.grid_side} (8 commodities, "
+                         f"20 pairs each), {m}x{n}, {nnz} nonzeros; relative KKT 1e-6; step = 64 "
+                         f"accepted PDHG iterations + periodic check"),
             "m": m, "n": n, "nnz": nnz, "iterations_per_step": step_k,
             "schedule": prob.schedule(),
             "status_at_end": status, "rel_gap_at_end": r["rel_gap"],
@@ -480,7 +495,8 @@ def main():
             "unit": "GB/s",
             "frac": dom[1] / HBM_PEAK_GBS,
             "traffic": (TRAFFIC_RECORD.get(dom[0])
-                        if hot_source_hash() == TRAFFIC_RECORD["hot_source"] else None),
+                        if (hot_source_hash() == TRAFFIC_RECORD["hot_source"]
+                            and (args.workload, nnz) == TRAFFIC_RECORD["workload"]) else None),
             "avg_launch_ms": dom[2],
             "algorithmic_bytes_per_launch": dom[3],
             "launches": dom[4],
