@@ -212,9 +212,9 @@ struct BatchPrimalEpi : NoPrefetch {
     __device__ __forceinline__ void apply(int j, double s, double (&acc)[1], const Pre &) const {
         row.apply(j, s, acc, row.pre(j));
     }
-    __device__ __forceinline__ void end(int b, double (&acc)[1], double *red) {
+    __device__ __forceinline__ void end(int b, double (&acc)[1], double *rbuf) {
         if (row.next) {
-            block_reduce<1>(acc, red);
+            block_reduce<1>(acc, rbuf);
             if (threadIdx.x == 0) part[b] = acc[0];
         }
         acc[0] = 0.0;
