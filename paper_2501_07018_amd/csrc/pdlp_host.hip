@@ -950,14 +950,39 @@ struct Engine {
         kkt_passes += 1;
     }
 
+    // Gap evaluations: the head of each (setup and the first active-set
+    // steps) is enqueued at once; gap_fetch reads the states and enqueues the
+    // tail (further steps, multisection, final segment) only for evaluations
+    // that have not finished, instead of launches that would do nothing.
+    struct GapArgs {
+        const double *x, *y, *ax, *aty;
+        bool live;
+    };
+    GapArgs gap_args[4] = {};
     void gap_enqueue(int slot, const double *x, const double *y, const double *ax,
                      const double *aty, const double *xr, const double *yr, double omega) {
-        HIPCHECK(pdlp::launch_gap(s(), m, n, v, x, y, ax, aty, xr, yr, omega, gap_part, ggrid,
-                                  gap_d + slot));
+        HIPCHECK(pdlp::launch_gap_head(s(), m, n, v, x, y, ax, aty, xr, yr, omega, gap_part,
+                                       ggrid, gap_d + slot));
+        gap_args[slot] = GapArgs{x, y, ax, aty, true};
     }
     void gap_fetch() {
         HIPCHECK(hipMemcpyAsync(gap_h, gap_d, 4 * sizeof(GapState), hipMemcpyDeviceToHost, s()));
         HIPCHECK(hipStreamSynchronize(s()));
+        bool more = false;
+        for (int k = 0; k < 4; ++k) {
+            const GapArgs &g = gap_args[k];
+            if (g.live && (gap_h[k].done == 0 || gap_h[k].done == 1)) {
+                HIPCHECK(pdlp::launch_gap_tail(s(), m, n, v, g.x, g.y, g.ax, g.aty, gap_part,
+                                               ggrid, gap_d + k));
+                more = true;
+            }
+            gap_args[k].live = false;
+        }
+        if (more) {
+            HIPCHECK(hipMemcpyAsync(gap_h, gap_d, 4 * sizeof(GapState), hipMemcpyDeviceToHost,
+                                    s()));
+            HIPCHECK(hipStreamSynchronize(s()));
+        }
     }
 
     // Infeasibility candidate c (0 difference of the two latest iterates,

@@ -29,6 +29,7 @@ constexpr int kWaveRows = kThreads / 64;
 constexpr int kGapPts = 32;          // abscissae per multisection pass of the gap search
 constexpr int kGapMaxPass = 24;
 constexpr int kGapNewton = 12;       // active-set steps before the multisection fallback
+constexpr int kGapHead = 8;          // active-set steps launched before the first look at the state
 
 // CSR matrix on the device with a row-block partition: block b covers rows
 // [blk[b], blk[b+1]) and is one of
@@ -293,10 +294,21 @@ hipError_t launch_cert_out(hipStream_t s, int m, int n, const double *px, const 
                            const double *lv, const double *uv, double *x_out, double *y_out,
                            double *r_out);
 
-// normalized duality gap
+// normalized duality gap: launch_gap = launch_gap_head then launch_gap_tail.
+// The head sets up the evaluation and runs kGapHead active-set steps; the
+// tail (the remaining steps, the multisection fallback and the final
+// segment) does nothing once gs->done is 2 or 3, so a caller that reads the
+// state after the head may leave it out then.
 hipError_t launch_gap(hipStream_t s, int m, int n, Vecs v, const double *x, const double *y,
                       const double *ax, const double *aty, const double *xr, const double *yr,
                       double omega, double *part, int grid, GapState *gs);
+hipError_t launch_gap_head(hipStream_t s, int m, int n, Vecs v, const double *x,
+                           const double *y, const double *ax, const double *aty,
+                           const double *xr, const double *yr, double omega, double *part,
+                           int grid, GapState *gs);
+hipError_t launch_gap_tail(hipStream_t s, int m, int n, Vecs v, const double *x,
+                           const double *y, const double *ax, const double *aty, double *part,
+                           int grid, GapState *gs);
 
 // device-rate probes (timed by the caller)
 hipError_t launch_rate_copy(hipStream_t s, int64_t len, const double *a, double *b);

@@ -1592,13 +1592,33 @@ hipError_t launch_rate_gather(hipStream_t s, int64_t n, const uint32_t *idx, con
     return hipGetLastError();
 }
 
-hipError_t launch_gap(hipStream_t s, int m, int n, Vecs v, const double *x, const double *y,
-                      const double *ax, const double *aty, const double *xr, const double *yr,
-                      double omega, double *part, int grid, GapState *gs) {
+hipError_t launch_gap_head(hipStream_t s, int m, int n, Vecs v, const double *x,
+                           const double *y, const double *ax, const double *aty,
+                           const double *xr, const double *yr, double omega, double *part,
+                           int grid, GapState *gs) {
     hipLaunchKernelGGL(k_gap_setup, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty, xr,
                        yr, omega, part);
     hipLaunchKernelGGL(k_gap_init, dim3(1), dim3(kThreads), 0, s, part, grid, omega, gs);
-    for (int p = 0; p < kGapNewton; ++p) {
+    for (int p = 0; p < kGapHead; ++p) {
+        hipLaunchKernelGGL(k_gap_step, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty,
+                           gs, part);
+        hipLaunchKernelGGL(k_gap_update, dim3(1), dim3(kThreads), 0, s, part, grid, gs);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gap(hipStream_t s, int m, int n, Vecs v, const double *x, const double *y,
+                      const double *ax, const double *aty, const double *xr, const double *yr,
+                      double omega, double *part, int grid, GapState *gs) {
+    const hipError_t e = launch_gap_head(s, m, n, v, x, y, ax, aty, xr, yr, omega, part, grid, gs);
+    if (e != hipSuccess) return e;
+    return launch_gap_tail(s, m, n, v, x, y, ax, aty, part, grid, gs);
+}
+
+hipError_t launch_gap_tail(hipStream_t s, int m, int n, Vecs v, const double *x,
+                           const double *y, const double *ax, const double *aty, double *part,
+                           int grid, GapState *gs) {
+    for (int p = kGapHead; p < kGapNewton; ++p) {
         hipLaunchKernelGGL(k_gap_step, dim3(grid), dim3(kThreads), 0, s, m, n, v, x, y, ax, aty,
                            gs, part);
         hipLaunchKernelGGL(k_gap_update, dim3(1), dim3(kThreads), 0, s, part, grid, gs);
